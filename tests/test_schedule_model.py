@@ -1,0 +1,85 @@
+"""The GPU library's schedule, modelled in slow Python, against the oracle and
+against the counts of App. B.  Runs on the CPU; a mistake in the family,
+canonical-parent or unique-reader bookkeeping fails here before any kernel."""
+import numpy as np
+import pytest
+
+import oracle as O
+from schedule_model import Model
+
+
+def rand_triple(rng, M, b_zero):
+    D = 2 * M
+    X = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+    X = 0.25 * (X + X.T)
+    b = np.zeros(D, complex) if b_zero else 0.4 * (rng.standard_normal(D) + 1j * rng.standard_normal(D))
+    return X, b, 0.8 + 0.1j
+
+
+CASES = [
+    (2, [4, 4], 0b11, True), (2, [4, 4], 0b11, False), (3, [4, 3, 3], 0b111, True),
+    (3, [4, 3, 3], 0b111, False), (2, [3, 4], 0b10, True), (2, [3, 4], 0b10, False),
+    (3, [3, 3, 2], 0b110, False), (3, [2, 3, 3], 0b101, False), (3, [3, 2, 2], 0b001, False),
+    (2, [2, 2], 0b11, False), (3, [1, 3, 3], 0b011, False), (3, [3, 3, 2], 0b000, False),
+    (4, [3, 2, 2, 3], 0b1011, False), (3, [2, 3, 2], 0b111, False), (1, [6], 0b1, False),
+]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", CASES)
+def test_model_forward_and_vjp(M, cut, mask, bz):
+    rng = np.random.default_rng(M * 100 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz)
+    ref = O.fock_diag(A, b, c, cut, mask)
+    mdl = Model(M, cut, mask, bz)
+    out = mdl.forward(A, b, c)
+    assert O.rel_err(out, ref) < 1e-14
+    g = rng.standard_normal(ref.shape) + 1j * rng.standard_normal(ref.shape)
+    dA, db, dc, _ = mdl.vjp(g)
+    rA, rb, rc = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    assert O.rel_err(dA, rA) < 1e-13
+    assert np.linalg.norm(db - rb) <= 1e-13 * max(1.0, np.linalg.norm(rb))
+    assert abs(dc - rc) <= 1e-13 * abs(rc)
+
+
+def pivot_count_formula(C):
+    # App. B.1: (C_1 - 1) prod_{i>=2} C_i + sum_K (C_K - 1) prod_{i>K} C_i
+    M = len(C)
+    tot = (C[0] - 1) * int(np.prod(C[1:]))
+    for K in range(M):
+        tot += (C[K] - 1) * int(np.prod(C[K + 1:]))
+    return tot
+
+
+def written_count_formula(M, C):
+    # App. B.3, equal cutoffs
+    t1 = (C - 1) * C ** (M - 1) + (C - 2) * C ** (M - 1) + (2 * M - 2) * (C - 1) ** 2 * C ** (M - 2)
+    t0 = C ** M
+    t2 = (C - 2) * sum(C ** (M - K - 1) for K in range(M))
+    t10 = (C - 1) ** 2 * sum((M - K - 1) * C ** (M - K - 2) for K in range(M - 1))
+    return dict(F1=t1, F0=t0, F2=t2, F1010=t10, F1001=t10)
+
+
+@pytest.mark.parametrize("M,C", [(2, 4), (3, 3), (3, 4), (2, 6)])
+def test_model_counts_match_appendix_b(M, C):
+    rng = np.random.default_rng(0)
+    A, b, c = rand_triple(rng, M, False)
+    mdl = Model(M, [C] * M, (1 << M) - 1, False)
+    mdl.forward(A, b, c)
+    cnt = mdl.stored_counts()
+    ref = written_count_formula(M, C)
+    assert cnt["F0"] == ref["F0"]
+    assert cnt["F1k"] + cnt["F1b"] == ref["F1"]
+    assert cnt.get("F2", 0) == ref["F2"]
+    assert cnt.get("F1010", 0) == ref["F1010"] and cnt.get("F1001", 0) == ref["F1001"]
+    # equal-cutoff pivot count 2 C^M - C^{M-1} - 1
+    assert pivot_count_formula([C] * M) == 2 * C ** M - C ** (M - 1) - 1
+
+
+def test_model_figure11_cutoffs():
+    # App. A / Fig. 11 cutoffs (4,3,3): 62 pivots, 255 stored amplitudes
+    rng = np.random.default_rng(1)
+    A, b, c = rand_triple(rng, 3, False)
+    mdl = Model(3, [4, 3, 3], 0b111, False)
+    mdl.forward(A, b, c)
+    assert sum(mdl.stored_counts().values()) == 255
+    assert pivot_count_formula([4, 3, 3]) == 62
