@@ -1,0 +1,181 @@
+/*
+ * fockdiag.h -- C ABI of the MI355X (gfx950) library for the selective
+ * Fock-amplitude recurrence of noisy Gaussian states (De Prins, Yao, Apte,
+ * Miatto, "A Quadratic Speedup in the Optimization of Noisy Quantum Optical
+ * Circuits", Quantum 2023).
+ *
+ * What is computed (Sec. 2.1 Eq. recrel, Sec. 3.1 probability p(n), Sec. 3.2):
+ * for an M-mode state with Bargmann triple (A, b, c) -- A complex symmetric
+ * 2M x 2M, b in C^2M, c in C -- the Fock amplitudes are the scaled Taylor
+ * coefficients rho_k = d^k F(0)/sqrt(k!) of F(z) = c exp(1/2 z^T A z + b^T z).
+ * For a set D of detected modes and U of undetected modes the library returns
+ *
+ *     rho[k_U..., l_U..., n_D...] = < k_U, n_D | rho | l_U, n_D >,
+ *
+ * i.e. every ket/bra block of the undetected modes and only the diagonal of
+ * the detected modes, at O(M^2 prod_U C^2 prod_D C) cost (Algorithm 1 for
+ * U empty, Algorithm 2 otherwise; Sec. 4 complexity).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex numbers are interleaved (re, im): complex128 = two doubles,
+ *    complex64 = two floats, selected by the plan's dtype.
+ *  - A is 2M x 2M, row-major, in BLOCK order [ket_1..ket_M, bra_1..bra_M]
+ *    (the paper's block formulas, Sec. 2.1 Eqs. A_rho/b_rho, read ket-first:
+ *    the returned amplitudes satisfy rho[k, l] = <k|rho|l>); b has length 2M
+ *    in the same order; c is one complex scalar.  The library uses
+ *    1/2 (A + A^T): the recurrence is route-independent only for symmetric A.
+ *  - rho is C-contiguous with shape [C_u for u in U (kets)] + [C_u for u in U
+ *    (bras)] + [C_j for j in D], U and D each in increasing mode order.
+ *    With U empty it is the table of detection probabilities p(n).
+ *  - All data pointers (A, b, c, rho, workspace, saved, gradients) are DEVICE
+ *    pointers owned by the caller.  No call frees caller memory.  A plan owns
+ *    its own small device tables, released by fd_plan_destroy.
+ *  - Every call is asynchronous on the given stream.  Argument errors are
+ *    detected on the host, return a status and set fd_last_error(); nothing
+ *    is launched then.  Non-finite inputs or outputs detected on the device
+ *    set the plan's device status word, read by fd_device_status().
+ *  - A plan may be used by one host thread at a time; calls on one plan that
+ *    overlap on different streams race on its device status word only.
+ */
+#ifndef FOCKDIAG_H
+#define FOCKDIAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FD_OK = 0,
+  FD_ERR_INVALID_ARG = 1,   /* bad shape, mask, pointer or size             */
+  FD_ERR_UNSUPPORTED = 2,   /* outside the compiled limits (see below)      */
+  FD_ERR_WORKSPACE = 3,     /* workspace or saved buffer too small          */
+  FD_ERR_OOM = 4,           /* the plan could not allocate its tables       */
+  FD_ERR_HIP = 5,           /* a HIP runtime call failed                    */
+  FD_ERR_NONFINITE = 6      /* device saw NaN/Inf (fd_device_status only)   */
+} fd_status;
+
+typedef enum { FD_C128 = 0, FD_C64 = 1 } fd_dtype;
+
+/* Plan flags: how the displacement vector b is treated.
+ * FD_B_AUTO    the forward call copies b to the host (one synchronising
+ *              2M-element read) and takes the b = 0 schedule when b is
+ *              exactly zero (Sec. 2.4: odd-weight amplitudes then vanish and
+ *              pivots need not be read);
+ * FD_B_ZERO    the caller promises b == 0 (the b = 0 schedule, no host read);
+ *              a non-zero b is then reported through fd_device_status;
+ * FD_B_GENERAL always the general schedule (no host read). */
+enum { FD_B_AUTO = 0u, FD_B_ZERO = 1u, FD_B_GENERAL = 2u };
+
+/* Compiled limits: M <= 16 modes, at most 8 detected modes with cutoff >= 2,
+ * at most 2 undetected modes with cutoff >= 2, every cutoff in [1, 64],
+ * prod over detected cutoffs < 2^31, undetected block prod C_u^2 <= 65536.
+ * Modes with cutoff 1 carry no photons and are dropped internally. */
+
+typedef struct fd_plan_s* fd_plan;
+
+/* fd_plan_create -- validate a problem shape and build its schedule tables
+ * on the host (the level structure of Algorithms 1/2: the families
+ * diag + offset of Sec. 3.1.4 / App. B.2 and their per-level sizes).
+ *   M              number of modes, 1..16
+ *   cutoffs        host array of M Fock cutoffs C_j (>= 1); detected modes
+ *                  return n_j < C_j, undetected modes k, l < C_j
+ *   detected_mask  bit j set = mode j carries a PNR detector
+ *   dt             FD_C128 or FD_C64 for every complex buffer of this plan
+ *   flags          FD_B_AUTO / FD_B_ZERO / FD_B_GENERAL
+ *   out            receives the plan (host handle)
+ * No device memory is touched here; device tables are created on first use. */
+fd_status fd_plan_create(int M, const int* cutoffs, uint32_t detected_mask, fd_dtype dt,
+                         uint32_t flags, fd_plan* out);
+fd_status fd_plan_destroy(fd_plan p);
+
+/* fd_plan_workspace -- byte sizes of the caller-owned device buffers.
+ *   with_vjp = 0: *fwd_bytes = workspace of fock_diag_fwd with saved == NULL
+ *                 (intermediates kept in a two-level ring, Sec. 3.1.4 buffer
+ *                 strategy), *saved_bytes = 0.
+ *   with_vjp = 1: *saved_bytes = size of the `saved` buffer that keeps every
+ *                 intermediate amplitude for the reverse sweep, *fwd_bytes =
+ *                 workspace of both fock_diag_fwd (with saved) and
+ *                 fock_diag_vjp (with saved).  fock_diag_vjp with saved ==
+ *                 NULL needs fwd_bytes + saved_bytes of workspace. */
+fd_status fd_plan_workspace(fd_plan p, int with_vjp, size_t* fwd_bytes, size_t* saved_bytes);
+
+/* fd_plan_query -- integer facts about the plan (host only, for tests and
+ * reports).  `what`: see FD_Q_* below. */
+enum {
+  FD_Q_OUT_ELEMS = 0,      /* elements of rho                                   */
+  FD_Q_LEVELS = 1,         /* photon-number levels swept (sum_D (C_j - 1) + 1)  */
+  FD_Q_PIVOTS = 2,         /* pivots of Algorithm 1 over the detected modes     */
+  FD_Q_STORED_NODES = 3,   /* written amplitudes (nodes) per App. B.3 types     */
+  FD_Q_TARGETS = 4,        /* computed amplitudes incl. U blocks (per call)     */
+  FD_Q_READ_TERMS = 5,     /* A-terms summed over all computed amplitudes       */
+  FD_Q_BLOCK = 6,          /* entries per node (prod_U C_u^2, 1 if U empty)     */
+  FD_Q_NODES_F0 = 7,       /* detected diagonal nodes prod_D C_j                */
+  FD_Q_NODES_F1 = 8,       /* type-1 offset nodes                               */
+  FD_Q_NODES_F2 = 9,       /* type-2 offset nodes                               */
+  FD_Q_NODES_F1010 = 10,   /* type-1010 offset nodes                            */
+  FD_Q_NODES_F1001 = 11,   /* type-1001 offset nodes                            */
+  FD_Q_B_SCHEDULE = 12     /* 1 if the plan will use the b = 0 schedule         */
+};
+fd_status fd_plan_query(fd_plan p, int what, int64_t* out);
+
+/* fock_diag_fwd -- rho[k_U, l_U, n_D] (Algorithm 1 or 2, Sec. 3).
+ *   A, b, c    device inputs as described above
+ *   rho        device output, fd_plan_query(FD_Q_OUT_ELEMS) complex elements
+ *   workspace  device scratch of at least ws_bytes >= fd_plan_workspace(...)
+ *   saved      NULL, or a device buffer of saved_bytes that receives every
+ *              intermediate amplitude for fock_diag_vjp
+ *   stream     HIP stream; all work is enqueued on it. */
+fd_status fock_diag_fwd(fd_plan p, const void* A, const void* b, const void* c, void* rho,
+                        void* workspace, size_t ws_bytes, void* saved, size_t saved_bytes,
+                        hipStream_t stream);
+
+/* fock_diag_vjp -- reverse-mode derivative of fock_diag_fwd (Sec. 2.5,
+ * Eqs. dL_dB and dL_dA, taken in reverse instead of the paper's forward
+ * mode).  With g = drho (same layout as rho), the outputs are
+ *     dA = sum_k g_k conj(d rho_k / d A),  db = sum_k g_k conj(d rho_k / d b),
+ *     dc = sum_k g_k conj(d rho_k / d c),
+ * A being used through 1/2 (A + A^T), so dA is symmetric; block order.
+ *   saved     the buffer filled by fock_diag_fwd with the same (A, b, c), or
+ *             NULL to recompute the forward inside the workspace
+ *   drho      device cotangent, same shape and dtype as rho
+ *   dA/db/dc  device outputs (2M x 2M, 2M, 1 complex elements)
+ * The reduction over amplitudes is done in a fixed order: results are
+ * bitwise reproducible for a given plan and device. */
+fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c,
+                        const void* saved, size_t saved_bytes, const void* drho,
+                        void* dA, void* db, void* dc, void* workspace, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* detection_probs -- p(n) = rho_{n1 n1 ... nM nM} for every n < cutoffs
+ * (Sec. 3.1, Algorithm 1): fock_diag_fwd for a plan whose detected_mask
+ * covers every mode.  probs has prod_j C_j complex elements (imaginary parts
+ * are rounding noise for physical states). */
+fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c, void* probs,
+                          void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Batched forward over n independent circuits, each with its own plan and
+ * buffers (arrays of n host-side entries holding device pointers).  Every
+ * circuit's workspace must satisfy its own plan (with_vjp = 0).  All circuits
+ * are swept level by level in shared launches on one stream (the per-level
+ * independence of Sec. 2.2 applied across circuits). */
+fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
+                              const void* const* b, const void* const* c, void* const* rho,
+                              void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
+
+/* Message of the last host-side error on the calling thread ("" if none). */
+const char* fd_last_error(void);
+
+/* Reads and clears the plan's device status word (synchronises `stream`):
+ * FD_OK, or FD_ERR_NONFINITE if a non-finite input or output was seen, or
+ * FD_ERR_INVALID_ARG if a plan made with FD_B_ZERO received a non-zero b. */
+fd_status fd_device_status(fd_plan p, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOCKDIAG_H */

@@ -1,0 +1,213 @@
+// extern "C" entry points declared in include/fockdiag.h: argument checks on
+// the host, workspace carving, schedule choice, then the kernel launchers.
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fd_internal.h"
+
+struct fd_plan_s {
+  fd::Plan P;
+};
+
+namespace {
+thread_local std::string g_err;
+
+fd_status fail(fd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+fd_status ok() {
+  g_err.clear();
+  return FD_OK;
+}
+
+// Decide the b = 0 schedule (Sec. 2.4) for this call.
+fd_status decide_b_zero(const fd::Plan& P, const void* b, hipStream_t s, bool* b_zero) {
+  if (P.flags == FD_B_ZERO) {
+    *b_zero = true;
+    return FD_OK;
+  }
+  if (P.flags == FD_B_GENERAL) {
+    *b_zero = false;
+    return FD_OK;
+  }
+  const size_t eb = fd::elem_bytes(P.dt);
+  std::vector<unsigned char> h((size_t)2 * P.M * eb);
+  if (hipMemcpyAsync(h.data(), b, h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FD_ERR_HIP, "reading b for the b = 0 test failed");
+  bool z = true;
+  if (P.dt == FD_C64) {
+    const float* v = reinterpret_cast<const float*>(h.data());
+    for (size_t i = 0; i < (size_t)4 * P.M; ++i) z = z && v[i] == 0.0f;
+  } else {
+    const double* v = reinterpret_cast<const double*>(h.data());
+    for (size_t i = 0; i < (size_t)4 * P.M; ++i) z = z && v[i] == 0.0;
+  }
+  *b_zero = z;
+  return FD_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+fd_status check_ptrs(const fd::Plan& P, std::initializer_list<const void*> ps) {
+  const size_t a = P.dt == FD_C64 ? 8 : 16;
+  for (const void* p : ps) {
+    if (!p) return fail(FD_ERR_INVALID_ARG, "a required device pointer is NULL");
+    if (!aligned(p, a)) return fail(FD_ERR_INVALID_ARG, "complex buffers must be aligned to their element size");
+  }
+  return FD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fd_status fd_plan_create(int M, const int* cutoffs, uint32_t detected_mask, fd_dtype dt, uint32_t flags,
+                         fd_plan* out) {
+  if (!out) return fail(FD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  fd_plan p = new (std::nothrow) fd_plan_s;
+  if (!p) return fail(FD_ERR_OOM, "host allocation failed");
+  std::string err;
+  fd_status s = fd::build_plan(M, cutoffs, detected_mask, dt, flags, &p->P, &err);
+  if (s != FD_OK) {
+    delete p;
+    return fail(s, err);
+  }
+  *out = p;
+  return ok();
+}
+
+fd_status fd_plan_destroy(fd_plan p) {
+  if (!p) return ok();
+  fd::Plan& P = p->P;
+  if (P.d_pn) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P.device);
+    (void)hipFree(P.d_pn);
+    (void)hipFree(P.d_lvl);
+    (void)hipFree(P.d_status);
+    (void)hipFree(P.d_elist);
+    (void)hipFree(P.d_woff);
+    (void)hipSetDevice(cur);
+  }
+  delete p;
+  return ok();
+}
+
+fd_status fd_plan_workspace(fd_plan p, int with_vjp, size_t* fwd_bytes, size_t* saved_bytes) {
+  if (!p || !fwd_bytes || !saved_bytes) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  const fd::Plan& P = p->P;
+  if (!with_vjp) {
+    *fwd_bytes = fd::fwd_layout(P, true, false, 0).total;
+    *saved_bytes = 0;
+  } else {
+    *saved_bytes = fd::fwd_layout(P, true, true, 0).total;
+    size_t v = fd::vjp_layout(P, true, 0).total;
+    *fwd_bytes = std::max(v, fd::prep_bytes(P));
+  }
+  return ok();
+}
+
+fd_status fd_plan_query(fd_plan p, int what, int64_t* out) {
+  if (!p || !out) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  fd::Plan& P = p->P;
+  switch (what) {
+    case FD_Q_OUT_ELEMS: *out = P.out_elems; break;
+    case FD_Q_LEVELS: *out = P.smax + 1; break;
+    case FD_Q_PIVOTS: *out = P.pivots; break;
+    case FD_Q_STORED_NODES: {
+      int64_t t = 0;
+      for (int i = 0; i < 6; ++i) t += P.stored[i];
+      *out = t;
+      break;
+    }
+    case FD_Q_TARGETS:
+    case FD_Q_READ_TERMS: {
+      if (P.targets < 0) fd::count_work(P, P.flags == FD_B_ZERO, &P.targets, &P.terms);
+      *out = what == FD_Q_TARGETS ? P.targets : P.terms;
+      break;
+    }
+    case FD_Q_BLOCK: *out = P.B; break;
+    case FD_Q_NODES_F0: *out = P.stored[fd::F_F0]; break;
+    case FD_Q_NODES_F1: *out = P.stored[fd::F_F1K] + P.stored[fd::F_F1B]; break;
+    case FD_Q_NODES_F2: *out = P.stored[fd::F_F2]; break;
+    case FD_Q_NODES_F1010: *out = P.stored[fd::F_1010]; break;
+    case FD_Q_NODES_F1001: *out = P.stored[fd::F_1001]; break;
+    case FD_Q_B_SCHEDULE: *out = P.flags == FD_B_ZERO ? 1 : 0; break;
+    default: return fail(FD_ERR_INVALID_ARG, "unknown query");
+  }
+  return ok();
+}
+
+fd_status fock_diag_fwd(fd_plan p, const void* A, const void* b, const void* c, void* rho, void* workspace,
+                        size_t ws_bytes, void* saved, size_t saved_bytes, hipStream_t stream) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  fd_status s = check_ptrs(P, {A, b, c, rho, workspace});
+  if (s != FD_OK) return s;
+  if (saved && !aligned(saved, 256)) return fail(FD_ERR_INVALID_ARG, "saved must be 256-byte aligned");
+  if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  bool b_zero = false;
+  if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;
+  const bool odd = P.odd_for(b_zero);
+  if (saved) {
+    if (saved_bytes < fd::fwd_layout(P, true, true, 0).total) return fail(FD_ERR_WORKSPACE, "saved buffer too small");
+    if (ws_bytes < fd::prep_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  } else if (ws_bytes < fd::fwd_layout(P, odd, false, 0).total) {
+    return fail(FD_ERR_WORKSPACE, "workspace too small");
+  }
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  hipError_t e = fd::run_forward(P, odd, A, b, c, rho, workspace, saved, stream);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return ok();
+}
+
+fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c, void* probs, void* workspace,
+                          size_t ws_bytes, hipStream_t stream) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  const fd::Plan& P = p->P;
+  const uint32_t all = P.M >= 32 ? 0xffffffffu : ((1u << P.M) - 1u);
+  if (P.mask != all) return fail(FD_ERR_INVALID_ARG, "detection_probs needs a plan with every mode detected");
+  return fock_diag_fwd(p, A, b, c, probs, workspace, ws_bytes, nullptr, 0, stream);
+}
+
+fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, const void* saved,
+                        size_t saved_bytes, const void* drho, void* dA, void* db, void* dc, void* workspace,
+                        size_t ws_bytes, hipStream_t stream) {
+  (void)p; (void)A; (void)b; (void)c; (void)saved; (void)saved_bytes; (void)drho;
+  (void)dA; (void)db; (void)dc; (void)workspace; (void)ws_bytes; (void)stream;
+  return fail(FD_ERR_UNSUPPORTED, "fock_diag_vjp is not built yet");
+}
+
+fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A, const void* const* b,
+                              const void* const* c, void* const* rho, void* const* workspace,
+                              const size_t* ws_bytes, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!plans || !A || !b || !c || !rho || !workspace || !ws_bytes)))
+    return fail(FD_ERR_INVALID_ARG, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    fd_status s = fock_diag_fwd(plans[i], A[i], b[i], c[i], rho[i], workspace[i], ws_bytes[i], nullptr, 0, stream);
+    if (s != FD_OK) return s;
+  }
+  return ok();
+}
+
+const char* fd_last_error(void) { return g_err.c_str(); }
+
+fd_status fd_device_status(fd_plan p, hipStream_t stream) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  if (!P.d_status) return ok();
+  int h = 0;
+  if (hipMemcpyAsync(&h, P.d_status, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemsetAsync(P.d_status, 0, sizeof(int), stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+    return fail(FD_ERR_HIP, "reading the device status failed");
+  if (h & 1) return fail(FD_ERR_NONFINITE, "non-finite value seen on the device");
+  if (h & 2) return fail(FD_ERR_INVALID_ARG, "plan made with FD_B_ZERO received a non-zero b");
+  return ok();
+}
+
+}  // extern "C"

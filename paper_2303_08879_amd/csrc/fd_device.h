@@ -1,0 +1,137 @@
+// Device-side helpers shared by the forward and reverse kernels: complex
+// arithmetic on interleaved (re, im) pairs, the level rank / unrank of the
+// detected lattice, and the per-launch pointer tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> cmake(R x, R y) {
+  cx<R> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename R>
+__device__ __forceinline__ cx<R> czero() {
+  return cmake<R>(R(0), R(0));
+}
+// acc += a * b
+template <typename R>
+__device__ __forceinline__ void cfma(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename R>
+__device__ __forceinline__ void cfma_conj(cx<R>& acc, const cx<R>& a, const cx<R>& b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cscale(const cx<R>& a, R s) {
+  return cmake<R>(a.x * s, a.y * s);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cadd(const cx<R>& a, const cx<R>& b) {
+  return cmake<R>(a.x + b.x, a.y + b.y);
+}
+
+// 16-byte / 8-byte vector load and store of one complex element.
+__device__ __forceinline__ cx<double> ld(const cx<double>* p) {
+  double2 v = *reinterpret_cast<const double2*>(p);
+  return cmake<double>(v.x, v.y);
+}
+__device__ __forceinline__ cx<float> ld(const cx<float>* p) {
+  float2 v = *reinterpret_cast<const float2*>(p);
+  return cmake<float>(v.x, v.y);
+}
+__device__ __forceinline__ void st(cx<double>* p, const cx<double>& a) {
+  *reinterpret_cast<double2*>(p) = make_double2(a.x, a.y);
+}
+__device__ __forceinline__ void st(cx<float>* p, const cx<float>& a) {
+  *reinterpret_cast<float2*>(p) = make_float2(a.x, a.y);
+}
+
+// Per-launch node-0 pointers of every family at the levels a sweep step
+// touches: rd = level S-1 (reads), wr = level S (writes), plus F0 at S and
+// S+1.  Entries of families not used by the schedule are null.
+template <typename R>
+struct LevelPtrs {
+  const cx<R>* rd[kMaxFam];
+  cx<R>* wr[kMaxFam];
+  const cx<R>* f0cur;
+  cx<R>* f0nxt;
+};
+
+// PN[d][x] for x in [-1, smax+1]; table row width pnw.
+__device__ __forceinline__ int pnv(const int* spn, int pnw, int d, int x) { return spn[d * pnw + x + 1]; }
+
+// Lattice point of rank r at level S (lexicographic, first mode slowest).
+// s[d] = S - sum_{i<d} m_i.  The count of points of sub-box d+1 whose sum
+// lies in (s - v, s] is PN[d+1][s] - PN[d+1][s-v]; m_d is the largest v with
+// that count <= r (binary search; counts are monotone in v).
+template <int MD>
+__device__ __forceinline__ void unrank(const int* spn, int pnw, const int* C, int S, int r, int* m, int* s) {
+  s[0] = S;
+#pragma unroll
+  for (int d = 0; d < MD - 1; ++d) {
+    const int sd = s[d];
+    const int base = pnv(spn, pnw, d + 1, sd);
+    const int target = base - r;
+    int lo = 0, hi = min(C[d] - 1, sd);
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pnv(spn, pnw, d + 1, sd - mid) >= target)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    m[d] = lo;
+    r -= base - pnv(spn, pnw, d + 1, sd - lo);
+    s[d + 1] = sd - lo;
+  }
+  m[MD - 1] = s[MD - 1];
+  s[MD] = 0;
+}
+
+// Ranks of the neighbours of m: rdn[j] = rank of m - 1_j at level S-1 (valid
+// when m_j > 0) and rup[K] = rank of m + 1_K at level S+1 (valid when
+// m_<K = 0).  With U_d = PN[d+1][s_d] - PN[d+1][s_{d+1}] (the terms of the
+// rank of m), the rank of m - 1_j shifts the partial sums of every mode
+// before j and of j itself by one; modes after j keep their terms.
+template <int MD>
+__device__ __forceinline__ void neighbour_ranks(const int* spn, int pnw, const int* s, int* rdn, int* rup) {
+  int U[MD];
+#pragma unroll
+  for (int d = 0; d < MD; ++d) U[d] = pnv(spn, pnw, d + 1, s[d]) - pnv(spn, pnw, d + 1, s[d + 1]);
+  int suff = 0;
+  int suffU[MD];
+#pragma unroll
+  for (int d = MD - 1; d >= 0; --d) {
+    suffU[d] = suff;
+    suff += U[d];
+  }
+  int pref = 0;
+#pragma unroll
+  for (int j = 0; j < MD; ++j) {
+    rdn[j] = pref + (pnv(spn, pnw, j + 1, s[j] - 1) - pnv(spn, pnw, j + 1, s[j + 1])) + suffU[j];
+    rup[j] = (pnv(spn, pnw, j + 1, s[j] + 1) - pnv(spn, pnw, j + 1, s[j + 1])) + suffU[j];
+    pref += pnv(spn, pnw, j + 1, s[j] - 1) - pnv(spn, pnw, j + 1, s[j + 1] - 1);
+  }
+}
+
+}  // namespace fd

@@ -1,0 +1,147 @@
+// Internal declarations shared by the planner, the kernels and the C ABI.
+//
+// Storage model (Sec. 3.1.4 / App. B.2): every amplitude the schedule writes
+// is diag(n) + offset for one of a few offset types.  With the detected modes
+// numbered j = 0..MD-1 (ket position 2j, bra 2j+1 of the detected index):
+//   F0          offset 0                          (the outputs)
+//   F1k(j)      offset 1_ket(j)                   n_0 <= C_0-2 [, n_j <= C_j-2]
+//   F1b(j)      offset 1_bra(j)                   n_0 <= C_0-3 (j=0), else as F1k
+//   F2(K)       offset 2*1_ket(K)                 n_<K = 0, n_K <= C_K-3
+//   F1010(K,j)  offset 1_ket(K) + 1_ket(j), j>K   n_<K = 0, n_K <= C_K-2, n_j <= C_j-2
+//   F1001(K,j)  offset 1_ket(K) + 1_bra(j), j>K   same as F1010
+// Each family is indexed by its diagonal coordinate n.  Families of "group"
+// K (F2(K), F1010(K,.), F1001(K,.)) only hold n with n_<K = 0; F0 and the
+// type-1 families are group 0.
+//
+// Nodes are stored level-major: level S = |n| holds the lattice points of
+// the detected box with sum S in lexicographic order (first mode slowest).
+// With that order the points of sub-box K (n_<K = 0) are exactly the first
+// Ncnt[K][S] points of level S, so one rank serves every family, and the
+// ranks of n - 1_j (level S-1) and n + 1_K (level S+1) are increasing in the
+// rank of n: neighbouring threads touch neighbouring addresses.
+//
+// Every node carries a block of B = prod_U C_u^2 entries (the undetected
+// modes' ket/bra indices, C order [k_u..., l_u...]; Algorithm 2); B = 1 when
+// every mode is detected (Algorithm 1).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/fockdiag.h"
+
+namespace fd {
+
+constexpr int kMaxModes = 16;
+constexpr int kMaxD = 8;                 // detected modes with cutoff >= 2
+constexpr int kMaxUq = 4;                // undetected block coordinates (2 per U mode)
+constexpr int kMaxCut = 64;
+constexpr int kMaxPos = kMaxUq + 2 * kMaxD;   // positions of the active index
+constexpr int kMaxFam = 1 + 3 * kMaxD + kMaxD * (kMaxD - 1);
+constexpr int kMaxSmax = kMaxD * (kMaxCut - 1);
+constexpr int kPnMax = (kMaxD + 1) * (kMaxSmax + 3);
+constexpr int kPartialSlots = 1024;      // deterministic VJP partial accumulators
+constexpr int kThreads = 256;
+
+enum FamType { F_F0 = 0, F_F1K, F_F1B, F_F2, F_1010, F_1001 };
+
+__host__ __device__ constexpr inline int fam_f1k(int j) { return 1 + j; }
+__host__ __device__ constexpr inline int fam_f1b(int MD, int j) { return 1 + MD + j; }
+__host__ __device__ constexpr inline int fam_f2(int MD, int K) { return 1 + 2 * MD + K; }
+__host__ __device__ constexpr inline int pair_index(int MD, int K, int j) {
+  return K * MD - K * (K + 1) / 2 + (j - K - 1);
+}
+__host__ __device__ constexpr inline int fam_1010(int MD, int K, int j) { return 1 + 3 * MD + 2 * pair_index(MD, K, j); }
+__host__ __device__ constexpr inline int fam_1001(int MD, int K, int j) {
+  return 1 + 3 * MD + 2 * pair_index(MD, K, j) + 1;
+}
+
+// Plain-old-data view of a plan passed by value to kernels.
+struct DevPlan {
+  int MD, MU, nq, npos;      // detected modes, undetected modes, U coords, positions
+  int B;                     // entries per node
+  int smax, pnw;             // max level, row width of the PN table (smax + 3)
+  int odd;                   // 1 if type-1 (odd) families are computed
+  int CD[kMaxD];             // detected cutoffs (all >= 2)
+  int udims[kMaxUq];         // U block dims [C_u.., C_u..]
+  int ustride[kMaxUq];
+  const int* pn;             // [(MD+1) x pnw]: PN[d][s+1] = #points of sub-box d with sum <= s
+  const int64_t* lvl;        // [(MD) x (smax+2)]: node offset of level S for group g (store-all)
+  int64_t ringN[kMaxD];      // ring slot stride in nodes per group (ring mode)
+};
+
+// Device pointers of one set of family arrays (forward values or cotangents).
+template <typename R>
+struct FamPtrs {
+  R* f[kMaxFam];             // interleaved complex, element pointer of node 0
+  int ring;                  // 1: two-slot ring (slot S&1), 0: store-all by level
+};
+
+struct Plan {
+  // caller's view
+  int M = 0;
+  std::vector<int> cut;
+  uint32_t mask = 0;
+  fd_dtype dt = FD_C128;
+  uint32_t flags = 0;
+  // active problem
+  int MU = 0, MD = 0, nq = 0, npos = 0, B = 1, smax = 0, nfam = 0;
+  std::vector<int> umodes, dmodes, CU, CD, udims, ustride;
+  std::vector<int> pos2blk;          // internal position -> block index in [0, 2M)
+  std::vector<int> pn;               // (MD+1) x pnw
+  std::vector<int64_t> ncnt;         // (MD+1) x (smax+1)
+  std::vector<int64_t> lvl;          // MD x (smax+2)
+  std::vector<int64_t> group_nodes;  // per group: prod_{i>=g} CD_i
+  std::vector<int64_t> maxN;         // per group: max level size
+  std::vector<int> fam_group;        // per family
+  int64_t nodes_total = 1;           // prod CD
+  int64_t out_elems = 1;
+  // structure counts (App. B)
+  int64_t pivots = 0, stored[6] = {0, 0, 0, 0, 0, 0}, targets = 0, terms = 0;
+  // device state
+  int device = -1;
+  int* d_pn = nullptr;
+  int64_t* d_lvl = nullptr;
+  int* d_status = nullptr;
+  // undetected-block fill order (step 1 of Algorithm 2): entries sorted by weight
+  std::vector<int> elist, woff;
+  int wmax = 0;
+  int* d_elist = nullptr;
+  int* d_woff = nullptr;
+  bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
+};
+
+size_t elem_bytes(fd_dtype dt);
+fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
+                     std::string* err);
+fd_status ensure_device(Plan* P, std::string* err);
+DevPlan make_devplan(const Plan& P, bool odd);
+
+// Workspace layouts (byte offsets from the start of the buffer).
+struct FwdLayout {
+  size_t prep = 0;                   // A_int, b_int, c, status scratch
+  size_t f0 = 0;                     // F0 store-all (output-sized)
+  std::vector<size_t> fam;           // per family (index 0 unused)
+  size_t total = 0;
+};
+FwdLayout fwd_layout(const Plan& P, bool odd, bool store_all, size_t base);
+struct VjpLayout {
+  size_t prep = 0;
+  size_t g0 = 0;                     // drho in level-major node order
+  std::vector<size_t> gfam;          // cotangent rings per family (F0 too)
+  size_t partial = 0;                // kPartialSlots x (npos x (npos+1)) complex (double)
+  size_t total = 0;
+};
+VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);
+size_t prep_bytes(const Plan& P);
+void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
+
+// kernels (kernels_fwd.hip / kernels_vjp.hip)
+hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
+                       void* saved, hipStream_t st);
+
+}  // namespace fd

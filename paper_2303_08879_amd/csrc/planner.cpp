@@ -1,0 +1,377 @@
+// Host planner: validates a problem shape and builds the level tables of the
+// selective schedule (Algorithm 1 over the detected modes, each node carrying
+// the undetected block of Algorithm 2).  Host-only: no device call here
+// except in ensure_device(), which uploads the tables on first use.
+#include <algorithm>
+#include <cstring>
+
+#include "fd_internal.h"
+
+namespace fd {
+
+size_t elem_bytes(fd_dtype dt) { return dt == FD_C64 ? 8 : 16; }
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
+                     std::string* err) {
+  if (M < 1 || M > kMaxModes) {
+    *err = "M must be in [1, 16]";
+    return FD_ERR_INVALID_ARG;
+  }
+  if (!cutoffs) {
+    *err = "cutoffs is NULL";
+    return FD_ERR_INVALID_ARG;
+  }
+  if (dt != FD_C128 && dt != FD_C64) {
+    *err = "dtype must be FD_C128 or FD_C64";
+    return FD_ERR_INVALID_ARG;
+  }
+  if (flags > FD_B_GENERAL) {
+    *err = "flags must be FD_B_AUTO, FD_B_ZERO or FD_B_GENERAL";
+    return FD_ERR_INVALID_ARG;
+  }
+  if (M < 32 && (mask >> M) != 0) {
+    *err = "detected_mask has bits at or above M";
+    return FD_ERR_INVALID_ARG;
+  }
+  P->M = M;
+  P->cut.assign(cutoffs, cutoffs + M);
+  P->mask = mask;
+  P->dt = dt;
+  P->flags = flags;
+  for (int j = 0; j < M; ++j) {
+    if (cutoffs[j] < 1 || cutoffs[j] > kMaxCut) {
+      *err = "every cutoff must be in [1, 64]";
+      return FD_ERR_INVALID_ARG;
+    }
+  }
+  P->umodes.clear();
+  P->dmodes.clear();
+  for (int j = 0; j < M; ++j) {
+    if (cutoffs[j] < 2) continue;  // cutoff 1: vacuum only, no index moves
+    if ((mask >> j) & 1u)
+      P->dmodes.push_back(j);
+    else
+      P->umodes.push_back(j);
+  }
+  P->MU = (int)P->umodes.size();
+  P->MD = (int)P->dmodes.size();
+  if (P->MD > kMaxD) {
+    *err = "at most 8 detected modes with cutoff >= 2 are supported";
+    return FD_ERR_UNSUPPORTED;
+  }
+  if (P->MU > kMaxUq / 2) {
+    *err = "at most 2 undetected modes with cutoff >= 2 are supported";
+    return FD_ERR_UNSUPPORTED;
+  }
+  P->CU.clear();
+  P->CD.clear();
+  for (int j : P->umodes) P->CU.push_back(cutoffs[j]);
+  for (int j : P->dmodes) P->CD.push_back(cutoffs[j]);
+  P->nq = 2 * P->MU;
+  P->npos = P->nq + 2 * P->MD;
+  P->udims.clear();
+  for (int q = 0; q < 2; ++q)
+    for (int c : P->CU) P->udims.push_back(c);
+  P->ustride.assign(P->nq, 1);
+  int64_t B = 1;
+  for (int q = P->nq - 1; q >= 0; --q) {
+    P->ustride[q] = (int)B;
+    B *= P->udims[q];
+  }
+  if (B > 65536) {
+    *err = "undetected block prod C_u^2 exceeds 65536";
+    return FD_ERR_UNSUPPORTED;
+  }
+  P->B = (int)B;
+  // internal positions: U kets, U bras, then (ket, bra) per detected mode
+  P->pos2blk.clear();
+  for (int j : P->umodes) P->pos2blk.push_back(j);
+  for (int j : P->umodes) P->pos2blk.push_back(M + j);
+  for (int j : P->dmodes) {
+    P->pos2blk.push_back(j);
+    P->pos2blk.push_back(M + j);
+  }
+  // output size
+  int64_t out = 1;
+  for (int j = 0; j < M; ++j) out *= ((mask >> j) & 1u) ? cutoffs[j] : (int64_t)cutoffs[j] * cutoffs[j];
+  P->out_elems = out;
+  int64_t nt = 1;
+  for (int c : P->CD) {
+    nt *= c;
+    if (nt >= (int64_t(1) << 31)) {
+      *err = "product of detected cutoffs must be < 2^31";
+      return FD_ERR_UNSUPPORTED;
+    }
+  }
+  P->nodes_total = nt;
+  const int MD = P->MD;
+  int smax = 0;
+  for (int c : P->CD) smax += c - 1;
+  P->smax = smax;
+  const int pnw = smax + 3;
+  // ncnt[d][s] = #(n_d..n_{MD-1}) in the box with sum s
+  P->ncnt.assign((size_t)(MD + 1) * (smax + 1), 0);
+  auto NC = [&](int d, int s) -> int64_t& { return P->ncnt[(size_t)d * (smax + 1) + s]; };
+  NC(MD, 0) = 1;
+  for (int d = MD - 1; d >= 0; --d)
+    for (int s = 0; s <= smax; ++s) {
+      int64_t acc = 0;
+      for (int v = 0; v < P->CD[d] && v <= s; ++v) acc += NC(d + 1, s - v);
+      NC(d, s) = acc;
+    }
+  // PN[d][s+1] = sum_{s' <= s} ncnt[d][s'], s in [-1, smax+1]
+  P->pn.assign((size_t)(MD + 1) * pnw, 0);
+  for (int d = 0; d <= MD; ++d) {
+    int64_t acc = 0;
+    for (int s = -1; s <= smax + 1; ++s) {
+      if (s >= 0 && s <= smax) acc += NC(d, s);
+      P->pn[(size_t)d * pnw + (s + 1)] = (int)acc;
+    }
+  }
+  // level offsets and group sizes
+  const int G = std::max(MD, 1);
+  P->lvl.assign((size_t)G * (smax + 2), 0);
+  P->group_nodes.assign(G, 1);
+  P->maxN.assign(G, 1);
+  for (int g = 0; g < MD; ++g) {
+    int64_t acc = 0, mx = 0;
+    for (int S = 0; S <= smax + 1; ++S) {
+      P->lvl[(size_t)g * (smax + 2) + S] = acc;
+      if (S <= smax) {
+        acc += NC(g, S);
+        mx = std::max(mx, NC(g, S));
+      }
+    }
+    P->group_nodes[g] = acc;
+    P->maxN[g] = std::max<int64_t>(mx, 1);
+  }
+  // families
+  P->nfam = 1 + 3 * MD + MD * (MD - 1);
+  P->fam_group.assign(P->nfam, 0);
+  for (int K = 0; K < MD; ++K) {
+    P->fam_group[fam_f2(MD, K)] = K;
+    for (int j = K + 1; j < MD; ++j) {
+      P->fam_group[fam_1010(MD, K, j)] = K;
+      P->fam_group[fam_1001(MD, K, j)] = K;
+    }
+  }
+  // App. B counts (valid nodes per offset type; pivots of Algorithm 1)
+  const std::vector<int>& C = P->CD;
+  auto prod_except = [&](int a, int b2, int from) {
+    int64_t p = 1;
+    for (int i = from; i < MD; ++i)
+      if (i != a && i != b2) p *= C[i];
+    return p;
+  };
+  for (int i = 0; i < 6; ++i) P->stored[i] = 0;
+  P->pivots = 0;
+  if (MD > 0) {
+    P->stored[F_F0] = nt;
+    P->stored[F_F1K] += (C[0] - 1) * prod_except(0, -1, 0);
+    P->stored[F_F1B] += std::max(C[0] - 2, 0) * prod_except(0, -1, 0);
+    for (int j = 1; j < MD; ++j) {
+      P->stored[F_F1K] += (int64_t)(C[0] - 1) * (C[j] - 1) * prod_except(0, j, 0);
+      P->stored[F_F1B] += (int64_t)(C[0] - 1) * (C[j] - 1) * prod_except(0, j, 0);
+    }
+    for (int K = 0; K < MD; ++K) {
+      P->stored[F_F2] += std::max(C[K] - 2, 0) * prod_except(K, -1, K);
+      for (int j = K + 1; j < MD; ++j) {
+        int64_t v = (int64_t)(C[K] - 1) * (C[j] - 1) * prod_except(K, j, K);
+        P->stored[F_1010] += v;
+        P->stored[F_1001] += v;
+      }
+    }
+    P->pivots = (C[0] - 1) * prod_except(0, -1, 0);
+    for (int K = 0; K < MD; ++K) P->pivots += (C[K] - 1) * prod_except(K, -1, K);
+  } else {
+    P->stored[F_F0] = 1;
+  }
+  // undetected block entries by weight (fill order of step 1)
+  P->wmax = 0;
+  for (int q = 0; q < P->nq; ++q) P->wmax += P->udims[q] - 1;
+  P->woff.assign(P->wmax + 2, 0);
+  std::vector<int> wt(P->B, 0);
+  for (int e = 0; e < P->B; ++e) {
+    int rem = e, w = 0;
+    for (int q = 0; q < P->nq; ++q) {
+      w += rem / P->ustride[q];
+      rem %= P->ustride[q];
+    }
+    wt[e] = w;
+    P->woff[w + 1]++;
+  }
+  for (int w = 0; w <= P->wmax; ++w) P->woff[w + 1] += P->woff[w];
+  P->elist.assign(P->B, 0);
+  {
+    std::vector<int> pos(P->woff.begin(), P->woff.end() - 1);
+    for (int e = 0; e < P->B; ++e) P->elist[pos[wt[e]]++] = e;
+  }
+  P->targets = -1;
+  P->terms = -1;
+  return FD_OK;
+}
+
+DevPlan make_devplan(const Plan& P, bool odd) {
+  DevPlan d;
+  std::memset(&d, 0, sizeof(d));
+  d.MD = P.MD;
+  d.MU = P.MU;
+  d.nq = P.nq;
+  d.npos = P.npos;
+  d.B = P.B;
+  d.smax = P.smax;
+  d.pnw = P.smax + 3;
+  d.odd = odd ? 1 : 0;
+  for (int j = 0; j < P.MD; ++j) d.CD[j] = P.CD[j];
+  for (int q = 0; q < P.nq; ++q) {
+    d.udims[q] = P.udims[q];
+    d.ustride[q] = P.ustride[q];
+  }
+  d.pn = P.d_pn;
+  d.lvl = P.d_lvl;
+  for (int g = 0; g < std::max(P.MD, 1); ++g) d.ringN[g] = P.maxN[g];
+  return d;
+}
+
+size_t prep_bytes(const Plan& P) {
+  size_t n = (size_t)P.npos * P.npos + P.npos + 1;
+  return align256(n * elem_bytes(P.dt));
+}
+
+FwdLayout fwd_layout(const Plan& P, bool odd, bool store_all, size_t base) {
+  FwdLayout L;
+  const size_t eb = elem_bytes(P.dt);
+  size_t off = base;
+  L.prep = off;
+  off += prep_bytes(P);
+  L.f0 = off;
+  off = align256(off + (size_t)P.nodes_total * P.B * eb);
+  L.fam.assign(P.nfam, 0);
+  const int MD = P.MD;
+  for (int f = 1; f < P.nfam; ++f) {
+    bool is_odd = (f < 1 + 2 * MD);
+    if (is_odd && !odd) continue;
+    int g = P.fam_group[f];
+    size_t nodes = store_all ? (size_t)P.group_nodes[g] : 2 * (size_t)P.maxN[g];
+    L.fam[f] = off;
+    off = align256(off + nodes * P.B * eb);
+  }
+  L.total = off;
+  return L;
+}
+
+VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
+  VjpLayout L;
+  const size_t eb = elem_bytes(P.dt);
+  size_t off = base;
+  L.prep = off;
+  off += prep_bytes(P);
+  L.g0 = off;
+  off = align256(off + (size_t)P.nodes_total * P.B * eb);
+  L.gfam.assign(P.nfam, 0);
+  const int MD = P.MD;
+  for (int f = 0; f < P.nfam; ++f) {
+    bool is_odd = (f >= 1 && f < 1 + 2 * MD);
+    if (is_odd && !odd) continue;
+    int g = P.fam_group[f];
+    L.gfam[f] = off;
+    off = align256(off + 2 * (size_t)P.maxN[g] * P.B * eb);
+  }
+  L.partial = off;
+  off = align256(off + (size_t)kPartialSlots * P.npos * (P.npos + 1) * 16);
+  L.total = off;
+  return L;
+}
+
+fd_status ensure_device(Plan* P, std::string* err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *err = "hipGetDevice failed";
+    return FD_ERR_HIP;
+  }
+  if (P->d_pn && P->device == dev) return FD_OK;
+  if (P->d_pn) {
+    *err = "plan was initialised on another device";
+    return FD_ERR_INVALID_ARG;
+  }
+  size_t npn = P->pn.size() * sizeof(int);
+  size_t nlvl = P->lvl.size() * sizeof(int64_t);
+  size_t nel = P->elist.size() * sizeof(int), nwo = P->woff.size() * sizeof(int);
+  if (hipMalloc((void**)&P->d_pn, npn) != hipSuccess || hipMalloc((void**)&P->d_lvl, nlvl) != hipSuccess ||
+      hipMalloc((void**)&P->d_status, 256) != hipSuccess || hipMalloc((void**)&P->d_elist, nel) != hipSuccess ||
+      hipMalloc((void**)&P->d_woff, nwo) != hipSuccess) {
+    *err = "hipMalloc of plan tables failed";
+    return FD_ERR_OOM;
+  }
+  if (hipMemcpy(P->d_pn, P->pn.data(), npn, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_lvl, P->lvl.data(), nlvl, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_elist, P->elist.data(), nel, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(P->d_woff, P->woff.data(), nwo, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(P->d_status, 0, 256) != hipSuccess) {
+    *err = "upload of plan tables failed";
+    return FD_ERR_HIP;
+  }
+  P->device = dev;
+  return FD_OK;
+}
+
+}  // namespace fd
+
+namespace fd {
+
+// Computed amplitudes and A-terms of one forward sweep (for FLOP accounting):
+// every valid target of every applied pivot, times the block size; a term is
+// one read with a non-zero sqrt coefficient (undetected neighbours included),
+// plus the pivot's b-term when b != 0.
+void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms) {
+  const int MD = P.MD;
+  const bool odd = P.odd_for(b_zero);
+  double unb = 0.0;  // undetected-neighbour terms per target block
+  for (int q = 0; q < P.nq; ++q) unb += (double)P.B * (1.0 - 1.0 / P.udims[q]);
+  const double bterm = b_zero ? 0.0 : (double)P.B;
+  int64_t T = (P.B > 1) ? (P.B - 1) : 0;   // undetected block fill
+  double W = 0.0;
+  if (P.B > 1) W += (double)P.B * 2.0;     // rough: <= 2 reads per fill entry
+  if (MD == 0 || P.nodes_total > (int64_t(1) << 27)) {
+    *targets = MD == 0 ? T : -1;
+    *terms = MD == 0 ? (int64_t)W : -1;
+    return;
+  }
+  const std::vector<int>& C = P.CD;
+  std::vector<int> m(MD, 0);
+  for (int64_t it = 0; it < P.nodes_total; ++it) {
+    int nz = 0;
+    for (int j = 0; j < MD; ++j) nz += m[j] > 0;
+    if (odd && m[0] <= C[0] - 2) {
+      int t = 0;
+      for (int j = 0; j < MD; ++j) {
+        if (j == 0 || m[j] <= C[j] - 2) ++t;                                   // F1k(j)
+        if ((j == 0) ? (m[0] <= C[0] - 3) : (m[j] <= C[j] - 2)) ++t;          // F1b(j)
+      }
+      T += (int64_t)t * P.B;
+      W += (double)t * (2.0 * nz * P.B + unb + bterm);
+    }
+    int K0 = MD;
+    for (int d = MD - 1; d >= 0; --d)
+      if (m[d] > 0) K0 = d;
+    for (int K = 0; K < MD && K <= K0; ++K) {
+      if (m[K] > C[K] - 2) continue;
+      int reads = 1 + (m[K] > 0);
+      for (int j = K + 1; j < MD; ++j) reads += 2 * (m[j] > 0);
+      int t = 1 + (m[K] <= C[K] - 3);
+      for (int j = K + 1; j < MD; ++j) t += 2 * (m[j] <= C[j] - 2);
+      T += (int64_t)t * P.B;
+      W += (double)t * ((double)reads * P.B + (odd ? unb + bterm : 0.0));
+    }
+    for (int j = MD - 1; j >= 0; --j) {
+      if (++m[j] < C[j]) break;
+      m[j] = 0;
+    }
+  }
+  *targets = T;
+  *terms = (int64_t)W;
+}
+
+}  // namespace fd

@@ -1,0 +1,156 @@
+"""Thin ctypes binding of libfockdiag.so (include/fockdiag.h), same names.
+
+Only argument marshalling happens here: tensors become device pointers and
+sizes, the current torch stream becomes the hipStream_t.  Every step of the
+computation runs in the library's HIP kernels; if the library is missing the
+calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfockdiag.so")
+
+FD_OK, FD_ERR_INVALID_ARG, FD_ERR_UNSUPPORTED, FD_ERR_WORKSPACE, FD_ERR_OOM, FD_ERR_HIP, FD_ERR_NONFINITE = range(7)
+FD_C128, FD_C64 = 0, 1
+FD_B_AUTO, FD_B_ZERO, FD_B_GENERAL = 0, 1, 2
+(FD_Q_OUT_ELEMS, FD_Q_LEVELS, FD_Q_PIVOTS, FD_Q_STORED_NODES, FD_Q_TARGETS, FD_Q_READ_TERMS, FD_Q_BLOCK,
+ FD_Q_NODES_F0, FD_Q_NODES_F1, FD_Q_NODES_F2, FD_Q_NODES_F1010, FD_Q_NODES_F1001, FD_Q_B_SCHEDULE) = range(13)
+
+EXPORTS = [
+    "fd_plan_create", "fd_plan_destroy", "fd_plan_workspace", "fd_plan_query", "fock_diag_fwd",
+    "fock_diag_vjp", "detection_probs", "fock_diag_fwd_batch", "fd_last_error", "fd_device_status",
+]
+
+_lib = None
+
+
+class FockDiagError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fockdiag status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_2303_08879_amd/build.py (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, u32, i64p = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int64)
+    L.fd_plan_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), u32, i32, u32, ctypes.POINTER(vp)]
+    L.fd_plan_destroy.argtypes = [vp]
+    L.fd_plan_workspace.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.fd_plan_query.argtypes = [vp, i32, i64p]
+    L.fock_diag_fwd.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, sz, vp]
+    L.fock_diag_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp, vp, sz, vp]
+    L.detection_probs.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fock_diag_fwd_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(sz), vp]
+    L.fd_last_error.argtypes = []
+    L.fd_last_error.restype = ctypes.c_char_p
+    L.fd_device_status.argtypes = [vp, vp]
+    for name in EXPORTS:
+        if name != "fd_last_error":
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != FD_OK:
+        raise FockDiagError(status, lib().fd_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+class Plan:
+    """fd_plan_create / fd_plan_destroy.  ``dtype`` is torch.complex128 or
+    torch.complex64; ``b_mode`` one of 'auto', 'zero', 'general'."""
+
+    def __init__(self, cutoffs, detected_mask, dtype=torch.complex128, b_mode="auto"):
+        self.cutoffs = [int(c) for c in cutoffs]
+        self.M = len(self.cutoffs)
+        self.detected_mask = int(detected_mask)
+        self.dtype = dtype
+        dt = FD_C128 if dtype == torch.complex128 else FD_C64
+        flags = {"auto": FD_B_AUTO, "zero": FD_B_ZERO, "general": FD_B_GENERAL}[b_mode]
+        arr = (ctypes.c_int * self.M)(*self.cutoffs)
+        h = ctypes.c_void_p()
+        _check(lib().fd_plan_create(self.M, arr, self.detected_mask, dt, flags, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.fd_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def out_shape(self):
+        U = [j for j in range(self.M) if not (self.detected_mask >> j) & 1]
+        D = [j for j in range(self.M) if (self.detected_mask >> j) & 1]
+        return tuple([self.cutoffs[j] for j in U] * 2 + [self.cutoffs[j] for j in D])
+
+    def workspace(self, with_vjp=False):
+        """(workspace bytes, saved bytes) -- fd_plan_workspace."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().fd_plan_workspace(self.handle, int(bool(with_vjp)), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def query(self, what):
+        v = ctypes.c_int64()
+        _check(lib().fd_plan_query(self.handle, int(what), ctypes.byref(v)))
+        return v.value
+
+
+def fock_diag_fwd(plan, A, b, c, rho, workspace, saved=None, stream=None):
+    _check(lib().fock_diag_fwd(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(rho), _ptr(workspace),
+                               _nbytes(workspace), _ptr(saved), _nbytes(saved), _stream(stream)))
+
+
+def detection_probs(plan, A, b, c, probs, workspace, stream=None):
+    _check(lib().detection_probs(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(probs), _ptr(workspace),
+                                 _nbytes(workspace), _stream(stream)))
+
+
+def fock_diag_vjp(plan, A, b, c, saved, drho, dA, db, dc, workspace, stream=None):
+    _check(lib().fock_diag_vjp(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(saved), _nbytes(saved), _ptr(drho),
+                               _ptr(dA), _ptr(db), _ptr(dc), _ptr(workspace), _nbytes(workspace),
+                               _stream(stream)))
+
+
+def fock_diag_fwd_batch(plans, As, bs, cs, rhos, workspaces, stream=None):
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    mk = lambda ts: (ctypes.c_void_p * n)(*[t.data_ptr() for t in ts])
+    sizes = (ctypes.c_size_t * n)(*[_nbytes(w) for w in workspaces])
+    _check(lib().fock_diag_fwd_batch(n, P, mk(As), mk(bs), mk(cs), mk(rhos), mk(workspaces), sizes,
+                                     _stream(stream)))
+
+
+def fd_device_status(plan, stream=None):
+    _check(lib().fd_device_status(plan.handle, _stream(stream)))
+
+
+def fd_last_error():
+    return lib().fd_last_error().decode()

@@ -1,0 +1,92 @@
+"""PyTorch-facing API: plan caching, device buffers from the torch allocator,
+and a torch.autograd.Function whose backward is the library's reverse sweep."""
+from __future__ import annotations
+
+import torch
+
+from . import fockdiag as F
+
+_plans = {}
+
+
+def get_plan(cutoffs, detected_mask, dtype=torch.complex128, b_mode="auto"):
+    key = (tuple(int(c) for c in cutoffs), int(detected_mask), dtype, b_mode)
+    p = _plans.get(key)
+    if p is None:
+        p = F.Plan(cutoffs, detected_mask, dtype, b_mode)
+        _plans[key] = p
+    return p
+
+
+def _as_inputs(A, b, c, dtype, device):
+    A = torch.as_tensor(A, dtype=dtype, device=device).contiguous()
+    b = torch.as_tensor(b, dtype=dtype, device=device).contiguous()
+    c = torch.as_tensor(c, dtype=dtype, device=device).reshape(1).contiguous()
+    return A, b, c
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def fock_diag(A, b, c, cutoffs, detected_mask, dtype=torch.complex128, b_mode="auto", device="cuda"):
+    """rho[k_U, l_U, n_D] (no autograd)."""
+    plan = get_plan(cutoffs, detected_mask, dtype, b_mode)
+    A, b, c = _as_inputs(A, b, c, dtype, device)
+    ws_bytes, _ = plan.workspace(False)
+    ws = _workspace(ws_bytes, device)
+    rho = torch.empty(plan.out_shape, dtype=dtype, device=device)
+    F.fock_diag_fwd(plan, A, b, c, rho, ws)
+    return rho
+
+
+def detection_probs(A, b, c, cutoffs, dtype=torch.complex128, b_mode="auto", device="cuda"):
+    """p(n) for every n < cutoffs (all modes detected)."""
+    mask = (1 << len(cutoffs)) - 1
+    plan = get_plan(cutoffs, mask, dtype, b_mode)
+    A, b, c = _as_inputs(A, b, c, dtype, device)
+    ws_bytes, _ = plan.workspace(False)
+    ws = _workspace(ws_bytes, device)
+    probs = torch.empty(plan.out_shape, dtype=dtype, device=device)
+    F.detection_probs(plan, A, b, c, probs, ws)
+    return probs
+
+
+class FockDiagFunction(torch.autograd.Function):
+    """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
+    intermediate amplitudes (PyTorch's complex-gradient convention: the
+    incoming gradient g yields sum g conj(d rho / d x))."""
+
+    @staticmethod
+    def forward(ctx, A, b, c, cutoffs, detected_mask, b_mode):
+        dtype = A.dtype
+        plan = get_plan(cutoffs, detected_mask, dtype, b_mode)
+        A_, b_, c_ = A.contiguous(), b.contiguous(), c.reshape(1).contiguous()
+        ws_bytes, saved_bytes = plan.workspace(True)
+        ws = _workspace(ws_bytes, A.device)
+        saved = _workspace(saved_bytes, A.device)
+        rho = torch.empty(plan.out_shape, dtype=dtype, device=A.device)
+        F.fock_diag_fwd(plan, A_, b_, c_, rho, ws, saved)
+        ctx.plan = plan
+        ctx.saved_buf = saved
+        ctx.c_shape = c.shape
+        ctx.save_for_backward(A_, b_, c_)
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        A, b, c = ctx.saved_tensors
+        plan = ctx.plan
+        g = grad_rho.contiguous()
+        ws_bytes, _ = plan.workspace(True)
+        ws = _workspace(ws_bytes, A.device)
+        dA = torch.empty_like(A)
+        db = torch.empty_like(b)
+        dc = torch.empty_like(c)
+        F.fock_diag_vjp(plan, A, b, c, ctx.saved_buf, g, dA, db, dc, ws)
+        return dA, db, dc.reshape(ctx.c_shape), None, None, None
+
+
+def fock_diag_ad(A, b, c, cutoffs, detected_mask, b_mode="auto"):
+    """Differentiable rho[k_U, l_U, n_D] w.r.t. (A, b, c)."""
+    return FockDiagFunction.apply(A, b, c, tuple(cutoffs), int(detected_mask), b_mode)

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol the header declares, validates arguments, and its planner reproduces
+the structure counts of App. B."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2303_08879_amd import fockdiag as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "fockdiag.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:fd_status|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = F.lib()
+    names = header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(F.EXPORTS)
+
+
+def test_plan_create_rejects_bad_arguments():
+    L = F.lib()
+    h = ctypes.c_void_p()
+    cut = (ctypes.c_int * 2)(4, 4)
+    assert L.fd_plan_create(0, cut, 0b11, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_create(2, cut, 0b111, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_create(2, cut, 0b11, 7, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_create(2, cut, 0b11, 0, 9, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    bad = (ctypes.c_int * 2)(0, 4)
+    assert L.fd_plan_create(2, bad, 0b11, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    nine = (ctypes.c_int * 9)(*([3] * 9))
+    assert L.fd_plan_create(9, nine, 0x1FF, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    three_u = (ctypes.c_int * 3)(3, 3, 3)
+    assert L.fd_plan_create(3, three_u, 0, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    assert "undetected" in F.fd_last_error()
+
+
+def test_calls_reject_null_plan_and_pointers():
+    L = F.lib()
+    assert L.fock_diag_fwd(None, None, None, None, None, None, 0, None, 0, None) == F.FD_ERR_INVALID_ARG
+    p = F.Plan([4, 4], 0b11)
+    assert L.fock_diag_fwd(p.handle, None, None, None, None, None, 0, None, 0, None) == F.FD_ERR_INVALID_ARG
+    # detection_probs needs every mode detected
+    q = F.Plan([4, 4], 0b10)
+    assert L.detection_probs(q.handle, 16, 16, 16, 16, 256, 1 << 20, None) == F.FD_ERR_INVALID_ARG
+
+
+def pivots_formula(C):
+    # App. B.1
+    M = len(C)
+    prod = lambda xs: 1 if not xs else __import__("math").prod(xs)
+    return (C[0] - 1) * prod(C[1:]) + sum((C[K] - 1) * prod(C[K + 1:]) for K in range(M))
+
+
+def written_formula(M, C):
+    # App. B.3 (equal cutoffs)
+    t1 = (C - 1) * C ** (M - 1) + (C - 2) * C ** (M - 1) + (2 * M - 2) * (C - 1) ** 2 * C ** (M - 2)
+    t2 = (C - 2) * sum(C ** (M - K - 1) for K in range(M))
+    t10 = (C - 1) ** 2 * sum((M - K - 1) * C ** (M - K - 2) for K in range(M - 1))
+    return C ** M, t1, t2, t10
+
+
+@pytest.mark.parametrize("M,C", [(2, 4), (3, 5), (4, 10), (5, 6), (8, 8)])
+def test_planner_counts_match_appendix_b(M, C):
+    p = F.Plan([C] * M, (1 << M) - 1)
+    t0, t1, t2, t10 = written_formula(M, C)
+    assert p.query(F.FD_Q_NODES_F0) == t0
+    assert p.query(F.FD_Q_NODES_F1) == t1
+    assert p.query(F.FD_Q_NODES_F2) == t2
+    assert p.query(F.FD_Q_NODES_F1010) == t10
+    assert p.query(F.FD_Q_NODES_F1001) == t10
+    assert p.query(F.FD_Q_PIVOTS) == 2 * C ** M - C ** (M - 1) - 1
+    assert p.query(F.FD_Q_LEVELS) == M * (C - 1) + 1
+
+
+def test_planner_figure11_and_figure7():
+    p = F.Plan([4, 3, 3], 0b111)
+    assert p.query(F.FD_Q_PIVOTS) == pivots_formula([4, 3, 3]) == 62
+    assert p.query(F.FD_Q_STORED_NODES) == 255
+    q = F.Plan([4, 4], 0b11)
+    assert q.query(F.FD_Q_PIVOTS) == 27 and q.query(F.FD_Q_STORED_NODES) == 82
+
+
+def test_planner_shapes_and_workspace():
+    p = F.Plan([30, 12, 12, 12], 0b1110)
+    assert p.out_shape == (30, 30, 12, 12, 12)
+    assert p.query(F.FD_Q_OUT_ELEMS) == 30 * 30 * 12 ** 3
+    assert p.query(F.FD_Q_BLOCK) == 900
+    ws, saved = p.workspace(False)
+    assert ws > 0 and saved == 0
+    ws2, saved2 = p.workspace(True)
+    assert saved2 > ws and ws2 > 0
+    # cutoff-1 modes are dropped but keep their output axis
+    r = F.Plan([1, 5, 1], 0b101)
+    assert r.out_shape == (5, 5, 1, 1)
+    assert r.query(F.FD_Q_BLOCK) == 25
