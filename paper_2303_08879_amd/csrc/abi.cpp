@@ -178,9 +178,37 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
 fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, const void* saved,
                         size_t saved_bytes, const void* drho, void* dA, void* db, void* dc, void* workspace,
                         size_t ws_bytes, hipStream_t stream) {
-  (void)p; (void)A; (void)b; (void)c; (void)saved; (void)saved_bytes; (void)drho;
-  (void)dA; (void)db; (void)dc; (void)workspace; (void)ws_bytes; (void)stream;
-  return fail(FD_ERR_UNSUPPORTED, "fock_diag_vjp is not built yet");
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  fd_status s = check_ptrs(P, {A, b, c, drho, dA, db, dc, workspace});
+  if (s != FD_OK) return s;
+  if (!aligned(workspace, 256) || (saved && !aligned(saved, 256)))
+    return fail(FD_ERR_INVALID_ARG, "workspace and saved must be 256-byte aligned");
+  if (P.B > 1 && fd::vjp_lds_bytes(P) > fd::kMaxLds)
+    return fail(FD_ERR_UNSUPPORTED, "undetected block too large for the reverse sweep's LDS staging");
+  bool b_zero = false;
+  if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;
+  const bool odd = P.odd_for(b_zero);
+  const size_t vneed = fd::vjp_layout(P, odd, 0).total;
+  const size_t sneed = fd::fwd_layout(P, true, true, 0).total;
+  const void* sv = saved;
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  if (saved) {
+    if (saved_bytes < sneed) return fail(FD_ERR_WORKSPACE, "saved buffer too small");
+    if (ws_bytes < vneed) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  } else {
+    // recompute the forward intermediates behind the reverse sweep's workspace
+    const size_t off = (vneed + 255) & ~size_t(255);
+    if (ws_bytes < off + sneed) return fail(FD_ERR_WORKSPACE, "workspace too small (saved == NULL)");
+    void* region = static_cast<char*>(workspace) + off;
+    hipError_t e = fd::run_forward(P, odd, A, b, c, nullptr, workspace, region, stream);
+    if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("forward recompute failed: ") + hipGetErrorString(e));
+    sv = region;
+  }
+  hipError_t e = fd::run_vjp(P, odd, A, b, c, sv, drho, dA, db, dc, workspace, stream);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return ok();
 }
 
 fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A, const void* const* b,

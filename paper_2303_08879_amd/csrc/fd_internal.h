@@ -39,6 +39,7 @@ namespace fd {
 constexpr int kMaxModes = 16;
 constexpr int kMaxD = 8;                 // detected modes with cutoff >= 2
 constexpr int kMaxUq = 4;                // undetected block coordinates (2 per U mode)
+constexpr int kMaxBlock = 4096;          // entries per node (prod_U C_u^2)
 constexpr int kMaxCut = 64;
 constexpr int kMaxPos = kMaxUq + 2 * kMaxD;   // positions of the active index
 constexpr int kMaxFam = 1 + 3 * kMaxD + kMaxD * (kMaxD - 1);
@@ -134,8 +135,11 @@ struct VjpLayout {
   size_t g0 = 0;                     // drho in level-major node order
   std::vector<size_t> gfam;          // cotangent rings per family (F0 too)
   size_t partial = 0;                // kPartialSlots x (npos x (npos+1)) complex (double)
+  size_t ufin = 0;                   // B entries: reverse of the undetected block fill
   size_t total = 0;
 };
+size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel
+constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);
 size_t prep_bytes(const Plan& P);
 void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
@@ -143,5 +147,9 @@ void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
 // kernels (kernels_fwd.hip / kernels_vjp.hip)
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
                        void* saved, hipStream_t st);
+hipError_t launch_prep(const Plan& P, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
+                       hipStream_t st);
+hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,
+                   const void* drho, void* dA, void* db, void* dc, void* ws, hipStream_t st);
 
 }  // namespace fd

@@ -54,7 +54,7 @@ __global__ void k_prep(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
     const cx<R> cv = ld(c);
     if (!isfinite(cv.x) || !isfinite(cv.y)) bad |= 1;
     st(ci, cv);
-    st(f0node0, cv);  // G_0 = c (Sec. 2.2 vacuum amplitude)
+    if (f0node0) st(f0node0, cv);  // G_0 = c (Sec. 2.2 vacuum amplitude)
   }
   if (bad) atomicOr(status, bad);
 }
@@ -484,6 +484,29 @@ static cx<R>* fam_level_ptr(const Plan& Pl, char* base, size_t off, int g, int S
   return reinterpret_cast<cx<R>*>(base + off + node * Pl.B * eb);
 }
 
+hipError_t launch_prep(const Plan& Pl, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
+                       hipStream_t st) {
+  PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  for (int p = 0; p < Pl.npos; ++p) pa.pos2blk[p] = Pl.pos2blk[p];
+  pa.npos = Pl.npos;
+  pa.M2 = 2 * Pl.M;
+  pa.check_b_zero = (Pl.flags == FD_B_ZERO) ? 1 : 0;
+  const size_t n2 = (size_t)Pl.npos * Pl.npos;
+  if (Pl.dt == FD_C64) {
+    cx<float>* a = reinterpret_cast<cx<float>*>(Ai);
+    hipLaunchKernelGGL((k_prep<float>), dim3(1), dim3(kThreads), 0, st, reinterpret_cast<const cx<float>*>(A),
+                       reinterpret_cast<const cx<float>*>(b), reinterpret_cast<const cx<float>*>(c), a, a + n2,
+                       a + n2 + Pl.npos, reinterpret_cast<cx<float>*>(f0node0), pa, Pl.d_status);
+  } else {
+    cx<double>* a = reinterpret_cast<cx<double>*>(Ai);
+    hipLaunchKernelGGL((k_prep<double>), dim3(1), dim3(kThreads), 0, st, reinterpret_cast<const cx<double>*>(A),
+                       reinterpret_cast<const cx<double>*>(b), reinterpret_cast<const cx<double>*>(c), a, a + n2,
+                       a + n2 + Pl.npos, reinterpret_cast<cx<double>*>(f0node0), pa, Pl.d_status);
+  }
+  return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho,
                                 char* ws, char* saved, hipStream_t st) {
@@ -498,16 +521,8 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   cx<R>* ci = bi + Pl.npos;
   cx<R>* f0 = reinterpret_cast<cx<R>*>(fb + LF.f0);
   DevPlan P = make_devplan(Pl, odd);
-  PrepArgs pa;
-  std::memset(&pa, 0, sizeof(pa));
-  for (int p = 0; p < Pl.npos; ++p) pa.pos2blk[p] = Pl.pos2blk[p];
-  pa.npos = Pl.npos;
-  pa.M2 = 2 * Pl.M;
-  pa.check_b_zero = (Pl.flags == FD_B_ZERO) ? 1 : 0;
-  hipLaunchKernelGGL((k_prep<R>), dim3(1), dim3(kThreads), 0, st, reinterpret_cast<const cx<R>*>(A),
-                     reinterpret_cast<const cx<R>*>(b), reinterpret_cast<const cx<R>*>(c), Ai, bi, ci, f0, pa,
-                     Pl.d_status);
-  hipError_t e = hipGetLastError();
+  (void)ci;
+  hipError_t e = launch_prep(Pl, A, b, c, Ai, f0, st);
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
     hipLaunchKernelGGL((k_ufill<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff,
@@ -528,6 +543,7 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
     e = launch_fwd_level_t<R>(Pl, P, odd, S, L, Ai, bi, st);
     if (e != hipSuccess) return e;
   }
+  if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
   const int64_t total = Pl.out_elems;
   const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
   const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;

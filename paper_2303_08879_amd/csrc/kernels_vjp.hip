@@ -1,0 +1,867 @@
+// Reverse sweep (vector-Jacobian product) of the selective recurrence.
+//
+// Forward, every computed amplitude t has one canonical parent pivot p and
+// direction i:  G_t = (b_i G_p + sum_l sqrt(p_l) A_il G_{p-1_l}) / sqrt(p_i+1)
+// (Eq. recrel).  With h_t = gbar_t / sqrt(p_i + 1), the adjoint (Sec. 2.5,
+// Eqs. dL_dB / dL_dA, in reverse instead of forward mode) is
+//   gbar_{p-1_l} += sqrt(p_l) conj(A_il) h_t,   gbar_p += conj(b_i) h_t,
+//   Abar_il      += conj(sqrt(p_l) G_{p-1_l}) h_t,   bbar_i += conj(G_p) h_t.
+// The sweep visits the levels of the forward in reverse.  Each off-diagonal
+// amplitude is read by exactly one pivot (Sec. 3.1.4 / App. B.2), so the
+// cotangent slot of every read is *written* (not accumulated) by the thread
+// of its only reader: no atomics, and two-level rings suffice for the
+// cotangents.  Diagonal amplitudes F0(m) are read only by pivots that sit at
+// the same lattice point m, so their cotangents are summed locally.
+// Abar / bbar are sums over every target: each workgroup stages its
+// per-pivot vectors (h, G-reads) in LDS and a fixed set of threads forms the
+// outer products in a fixed order, then adds them to its own partial slot;
+// one final kernel sums the slots in order.  The result is bitwise
+// reproducible for a given plan.
+#include <algorithm>
+#include <cstring>
+
+#include "fd_device.h"
+
+namespace fd {
+
+constexpr int kRS = 64;     // records staged per sub-round
+
+template <typename R>
+struct VjpPtrs {
+  const cx<R>* fprev[kMaxFam];  // forward values, level S-1 (store-all)
+  const cx<R>* fcur[kMaxFam];   // forward values, level S (fcur[0] = F0)
+  cx<R>* gprev[kMaxFam];        // cotangent ring slot of level S-1
+  cx<R>* gcur[kMaxFam];         // cotangent ring slot of level S (gcur[0] = F0)
+  const cx<R>* gf0nxt;          // F0 cotangents, level S+1
+  const cx<R>* d0cur;           // drho in node order, level S
+};
+
+__global__ void k_zero_d2(double2* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+// rho-shaped cotangent (C order [kappa][n_D]) -> node order (level-major)
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __restrict__ drho, cx<R>* __restrict__ g0,
+                                                      int64_t N, int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int* spn = reinterpret_cast<int*>(smem_raw);
+  int64_t* slv = reinterpret_cast<int64_t*>(smem_raw + 16 * ((((P.MD + 1) * P.pnw) * 4 + 15) / 16));
+  const int npn = (P.MD + 1) * P.pnw;
+  for (int i = threadIdx.x; i < npn; i += blockDim.x) spn[i] = P.pn[i];
+  for (int i = threadIdx.x; i <= P.smax; i += blockDim.x) slv[i] = P.MD > 0 ? P.lvl[i] : 0;
+  __syncthreads();
+  const int MD = P.MD, B = P.B, pnw = P.pnw;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t kap = idx / N;
+    int64_t rem = idx - kap * N;
+    int n[kMaxD];
+    int S = 0;
+    for (int d = MD - 1; d >= 0; --d) {
+      n[d] = (int)(rem % P.CD[d]);
+      rem /= P.CD[d];
+      S += n[d];
+    }
+    int rank = 0, sd = S;
+    for (int d = 0; d < MD; ++d) {
+      rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - n[d]);
+      sd -= n[d];
+    }
+    st(g0 + (size_t)(slv[S] + rank) * B + kap, ld(drho + idx));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer-product accumulation Abar[i][l] += sum_records conj(X[l]) H[i].
+// Pairs p = i * NR + l (NR = npos + 1, column npos = b term).  With P pairs,
+// G = 256 / P record groups share a pair (P <= 256), else each thread owns
+// pairs t and t + 256.  Accumulators live in registers (double).
+// ---------------------------------------------------------------------------
+struct PairMap {
+  int P, NR, G;
+};
+
+__device__ __forceinline__ PairMap pair_map(int npos) {
+  PairMap m;
+  m.NR = npos + 1;
+  m.P = npos * m.NR;
+  m.G = m.P >= kThreads ? 1 : kThreads / m.P;
+  return m;
+}
+
+template <typename R>
+__device__ __forceinline__ void accumulate_records(const PairMap& pm, const cx<R>* Hs, const cx<R>* Xs, int E,
+                                                   cx<double>& a0, cx<double>& a1) {
+  const int t = threadIdx.x;
+  if (t < pm.P * pm.G) {
+    const int p = t % pm.P, g = t / pm.P;
+    const int i = p / pm.NR, l = p % pm.NR;
+    const cx<R>* h = Hs + i * kRS;
+    const cx<R>* x = Xs + l * kRS;
+    for (int e = g; e < E; e += pm.G) {
+      const cx<R> hv = h[e], xv = x[e];
+      a0.x += (double)xv.x * hv.x + (double)xv.y * hv.y;
+      a0.y += (double)xv.x * hv.y - (double)xv.y * hv.x;
+    }
+  }
+  if (pm.P > kThreads && t + kThreads < pm.P) {
+    const int p = t + kThreads;
+    const int i = p / pm.NR, l = p % pm.NR;
+    const cx<R>* h = Hs + i * kRS;
+    const cx<R>* x = Xs + l * kRS;
+    for (int e = 0; e < E; ++e) {
+      const cx<R> hv = h[e], xv = x[e];
+      a1.x += (double)xv.x * hv.x + (double)xv.y * hv.y;
+      a1.y += (double)xv.x * hv.y - (double)xv.y * hv.x;
+    }
+  }
+}
+
+// Every thread holds one record (h over npos write positions, x over npos
+// read positions + the pivot value); the workgroup folds them in sub-rounds
+// of kRS records.  Must be reached by every thread of the workgroup.
+template <typename R, int NW>
+__device__ __forceinline__ void stage_accumulate(const PairMap& pm, int npos, const cx<R>* h, const cx<R>* x,
+                                                 cx<R>* Hs, cx<R>* Xs, cx<double>& a0, cx<double>& a1) {
+#pragma unroll 1
+  for (int s = 0; s < kThreads / kRS; ++s) {
+    const int t = (int)threadIdx.x - s * kRS;
+    if (t >= 0 && t < kRS) {
+#pragma unroll
+      for (int i = 0; i < NW; ++i)
+        if (i < npos) Hs[i * kRS + t] = h[i];
+#pragma unroll
+      for (int l = 0; l < NW + 1; ++l)
+        if (l <= npos) Xs[l * kRS + t] = x[l];
+    }
+    __syncthreads();
+    accumulate_records(pm, Hs, Xs, kRS, a0, a1);
+    __syncthreads();
+  }
+}
+
+// Adds the workgroup's pair sums to its partial slot (combining record groups
+// in a fixed order).
+__device__ __forceinline__ void flush_pairs(const PairMap& pm, double2* slot, cx<double> a0, cx<double> a1,
+                                            cx<double>* red) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if (pm.G > 1) {
+    if (t < pm.P * pm.G) red[t] = a0;
+    __syncthreads();
+    if (t < pm.P) {
+      cx<double> s = cmake<double>(0.0, 0.0);
+      for (int g = 0; g < pm.G; ++g) {
+        s.x += red[g * pm.P + t].x;
+        s.y += red[g * pm.P + t].y;
+      }
+      double2 v = slot[t];
+      slot[t] = make_double2(v.x + s.x, v.y + s.y);
+    }
+  } else {
+    if (t < pm.P) {
+      double2 v = slot[t];
+      slot[t] = make_double2(v.x + a0.x, v.y + a0.y);
+    }
+    if (t + kThreads < pm.P) {
+      double2 v = slot[t + kThreads];
+      slot[t + kThreads] = make_double2(v.x + a1.x, v.y + a1.y);
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_tables_v(const DevPlan& P, int* spn, R* sq, R* isq) {
+  const int n = (P.MD + 1) * P.pnw;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) spn[i] = P.pn[i];
+  for (int v = threadIdx.x; v < kMaxCut + 4; v += blockDim.x) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 reverse step: one thread per lattice point.
+// ---------------------------------------------------------------------------
+template <int MD, bool ODD, typename R>
+__global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
+                                                        const cx<R>* __restrict__ bi, int S, int nwork,
+                                                        double2* __restrict__ partial) {
+  constexpr int NP = 2 * MD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* Hs = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* Xs = Hs + NP * kRS;
+  cx<double>* red = reinterpret_cast<cx<double>*>(Xs + (NP + 1) * kRS);
+  R* sq = reinterpret_cast<R*>(red + kThreads);
+  R* isq = sq + (kMaxCut + 4);
+  int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+  load_tables_v(P, spn, sq, isq);
+  __syncthreads();
+  const PairMap pm = pair_map(NP);
+  cx<double> a0 = cmake<double>(0.0, 0.0), a1 = a0;
+  const int pnw = P.pnw;
+
+  for (int base = blockIdx.x * kThreads; base < nwork; base += gridDim.x * kThreads) {
+    const int r = base + threadIdx.x;
+    const bool live = r < nwork;
+    int m[MD], s[MD + 1], rdn[MD], rup[MD];
+#pragma unroll
+    for (int d = 0; d < MD; ++d) m[d] = 0;
+    int K0 = MD;
+    cx<R> g0acc = czero<R>(), G0 = czero<R>();
+    if (live) {
+      unrank<MD>(spn, pnw, P.CD, S, r, m, s);
+      neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+#pragma unroll
+      for (int d = MD - 1; d >= 0; --d)
+        if (m[d] > 0) K0 = d;
+      g0acc = ld(V.d0cur + r);
+      G0 = ld(V.fcur[0] + r);
+    }
+    cx<R> ykg[MD];
+#pragma unroll
+    for (int K = 0; K < MD; ++K) ykg[K] = czero<R>();
+
+#pragma unroll
+    for (int K = 0; K < MD; ++K) {
+      const bool valid = live && K <= K0 && m[K] <= P.CD[K] - 2;
+      if (!__syncthreads_or(valid)) continue;
+      cx<R> h[NP], x[NP + 1];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) h[i] = czero<R>();
+#pragma unroll
+      for (int l = 0; l <= NP; ++l) x[l] = czero<R>();
+      if (valid) {
+        h[2 * K + 1] = cscale(ld(V.gf0nxt + rup[K]), isq[m[K] + 1]);
+        if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + r), isq[m[K] + 2]);
+#pragma unroll
+        for (int j = K + 1; j < MD; ++j) {
+          if (m[j] <= P.CD[j] - 2) {
+            h[2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + r), isq[m[j] + 1]);
+            h[2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + r), isq[m[j] + 1]);
+          }
+        }
+        x[2 * K] = cscale(G0, sq[m[K] + 1]);
+        if (m[K] > 0) x[2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + rdn[K]), sq[m[K]]);
+#pragma unroll
+        for (int j = K + 1; j < MD; ++j) {
+          if (m[j] > 0) {
+            x[2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]);
+            x[2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]);
+          }
+        }
+        if (ODD) x[NP] = ld(V.fcur[fam_f1k(K)] + r);
+        // adjoint of the reads
+#pragma unroll
+        for (int l = 2 * K; l < NP; ++l) {
+          cx<R> u = czero<R>();
+#pragma unroll
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
+          const int j = l >> 1;
+          if (l == 2 * K) {
+            g0acc = cadd(g0acc, cscale(u, sq[m[K] + 1]));
+          } else if (l == 2 * K + 1) {
+            if (m[K] > 0) st(V.gprev[fam_f2(MD, K)] + rdn[K], cscale(u, sq[m[K]]));
+          } else if (m[j] > 0) {
+            st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + rdn[j], cscale(u, sq[m[j]]));
+          }
+        }
+        if (ODD) {
+          cx<R> gp = czero<R>();
+#pragma unroll
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
+          const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
+          ykg[K] = has_diag_reader ? cadd(ld(V.gcur[fam_f1k(K)] + r), gp) : gp;
+        }
+      }
+      stage_accumulate<R, NP>(pm, NP, h, x, Hs, Xs, a0, a1);
+    }
+
+    if (ODD) {
+      const bool valid = live && m[0] <= P.CD[0] - 2;
+      if (__syncthreads_or(valid)) {
+        cx<R> h[NP], x[NP + 1];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) h[i] = czero<R>();
+#pragma unroll
+        for (int l = 0; l <= NP; ++l) x[l] = czero<R>();
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < MD; ++j) {
+            if (j == 0 || m[j] <= P.CD[j] - 2) {
+              const bool kpiv = (j <= K0) && (m[j] <= P.CD[j] - 2);
+              const cx<R> gt = kpiv ? ykg[j] : ld(V.gcur[fam_f1k(j)] + r);
+              h[2 * j] = cscale(gt, isq[m[j] + 1]);
+            }
+            const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
+            if (okb) h[2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + r), isq[m[j] + 1]);
+            if (m[j] > 0) {
+              x[2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]);
+              x[2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + rdn[j]), sq[m[j]]);
+            }
+          }
+          x[NP] = G0;
+#pragma unroll
+          for (int l = 0; l < NP; ++l) {
+            const int j = l >> 1;
+            if (m[j] == 0) continue;
+            cx<R> u = czero<R>();
+#pragma unroll
+            for (int i = 0; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
+            st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + rdn[j], cscale(u, sq[m[j]]));
+          }
+          cx<R> gp = czero<R>();
+#pragma unroll
+          for (int i = 0; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
+          g0acc = cadd(g0acc, gp);
+        }
+        stage_accumulate<R, NP>(pm, NP, h, x, Hs, Xs, a0, a1);
+      }
+    }
+    if (live) st(V.gcur[0] + r, g0acc);
+  }
+  flush_pairs(pm, partial + (size_t)blockIdx.x * pm.P, a0, a1, red);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 reverse step: one workgroup per lattice point, threads over
+// block entries.  LDS: the pivot's forward block (undetected neighbours) and
+// the per-entry pulls sum_i conj(A_iq) h_i for each undetected coordinate q.
+// ---------------------------------------------------------------------------
+template <int MD, int NQ, typename R>
+__global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
+                                                        const cx<R>* __restrict__ bi, int S, int nwork,
+                                                        double2* __restrict__ partial) {
+  constexpr int NPD = 2 * MD;
+  constexpr int NW = NPD + NQ;          // positions: NQ undetected coordinates, then detected
+  constexpr int nq = NQ, npos = NW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int B = P.B;
+  cx<R>* lpiv = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* qpull = lpiv + B;                          // nq x B
+  cx<R>* Hs = qpull + (size_t)nq * B;
+  cx<R>* Xs = Hs + (size_t)npos * kRS;
+  cx<double>* red = reinterpret_cast<cx<double>*>(Xs + (size_t)(npos + 1) * kRS);
+  R* sq = reinterpret_cast<R*>(red + kThreads);
+  R* isq = sq + (kMaxCut + 4);
+  int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+  load_tables_v(P, spn, sq, isq);
+  __syncthreads();
+  const PairMap pm = pair_map(npos);
+  cx<double> a0 = cmake<double>(0.0, 0.0), a1 = a0;
+  const int pnw = P.pnw;
+  const int nk = (B + kThreads - 1) / kThreads;
+
+  for (int r = blockIdx.x; r < nwork; r += gridDim.x) {
+    int m[MD], s[MD + 1], rdn[MD], rup[MD];
+    unrank<MD>(spn, pnw, P.CD, S, r, m, s);
+    neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+    int K0 = MD;
+#pragma unroll
+    for (int d = MD - 1; d >= 0; --d)
+      if (m[d] > 0) K0 = d;
+    const size_t rB = (size_t)r * B;
+    cx<R>* gf0 = V.gcur[0] + rB;
+    for (int e = threadIdx.x; e < B; e += blockDim.x) st(gf0 + e, ld(V.d0cur + rB + e));
+
+#pragma unroll
+    for (int K = 0; K < MD; ++K) {
+      if (K > K0 || m[K] > P.CD[K] - 2) continue;      // uniform over the workgroup
+      const cx<R>* fpiv = V.fcur[fam_f1k(K)] + rB;
+      for (int e = threadIdx.x; e < B; e += blockDim.x) lpiv[e] = ld(fpiv + e);
+      __syncthreads();
+      cx<R>* gpk = V.gcur[fam_f1k(K)] + rB;
+      const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
+      for (int k = 0; k < nk; ++k) {
+        const int e = threadIdx.x + k * kThreads;
+        const bool live = e < B;
+        cx<R> h[NW], x[NW + 1];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) h[i] = czero<R>();
+#pragma unroll
+        for (int l = 0; l <= NW; ++l) x[l] = czero<R>();
+        if (live) {
+          int kap[kMaxUq];
+          int rem = e;
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q) {
+            kap[q] = q < nq ? rem / P.ustride[q] : 0;
+            rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+          }
+          // target cotangents (internal positions nq + detected index)
+          h[nq + 2 * K + 1] = cscale(ld(V.gf0nxt + (size_t)rup[K] * B + e), isq[m[K] + 1]);
+          if (m[K] <= P.CD[K] - 3) h[nq + 2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + rB + e), isq[m[K] + 2]);
+#pragma unroll
+          for (int j = K + 1; j < MD; ++j) {
+            if (m[j] <= P.CD[j] - 2) {
+              h[nq + 2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + rB + e), isq[m[j] + 1]);
+              h[nq + 2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + rB + e), isq[m[j] + 1]);
+            }
+          }
+          // forward reads
+          x[nq + 2 * K] = cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]);
+          if (m[K] > 0) x[nq + 2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]);
+#pragma unroll
+          for (int j = K + 1; j < MD; ++j) {
+            if (m[j] > 0) {
+              x[nq + 2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+              x[nq + 2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q)
+            if (q < nq && kap[q] > 0) x[q] = cscale(lpiv[e - P.ustride[q]], sq[kap[q]]);
+          x[npos] = lpiv[e];
+          // adjoint of the detected reads
+#pragma unroll
+          for (int l = 2 * K; l < NPD; ++l) {
+            cx<R> u = czero<R>();
+#pragma unroll
+            for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + nq + l), h[nq + i]);
+            const int j = l >> 1;
+            if (l == 2 * K) {
+              st(gf0 + e, cadd(ld(gf0 + e), cscale(u, sq[m[K] + 1])));
+            } else if (l == 2 * K + 1) {
+              if (m[K] > 0) st(V.gprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e, cscale(u, sq[m[K]]));
+            } else if (m[j] > 0) {
+              st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e,
+                 cscale(u, sq[m[j]]));
+            }
+          }
+          // adjoint of the pivot: b term now, undetected neighbours after the barrier
+          cx<R> gp = czero<R>();
+#pragma unroll
+          for (int i = 2 * K; i < NPD; ++i) cfma_conj(gp, ld(bi + nq + i), h[nq + i]);
+          st(gpk + e, has_diag_reader ? cadd(ld(gpk + e), gp) : gp);
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q) {
+            if (q < nq) {
+              cx<R> u = czero<R>();
+#pragma unroll
+              for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + q), h[nq + i]);
+              qpull[(size_t)q * B + e] = u;
+            }
+          }
+        }
+        stage_accumulate<R, NW>(pm, npos, h, x, Hs, Xs, a0, a1);
+      }
+      // pull: gbar_p[e] += sqrt(kappa_q + 1) * qpull_q[e + s_q]
+      for (int e = threadIdx.x; e < B; e += blockDim.x) {
+        int rem = e;
+        cx<R> acc = ld(gpk + e);
+#pragma unroll
+        for (int q = 0; q < kMaxUq; ++q) {
+          if (q < nq) {
+            const int kq = rem / P.ustride[q];
+            rem -= kq * P.ustride[q];
+            if (kq + 1 < P.udims[q]) acc = cadd(acc, cscale(qpull[(size_t)q * B + e + P.ustride[q]], sq[kq + 1]));
+          }
+        }
+        st(gpk + e, acc);
+      }
+      __syncthreads();
+    }
+
+    if (m[0] <= P.CD[0] - 2) {
+      const cx<R>* fpiv = V.fcur[0] + rB;
+      for (int e = threadIdx.x; e < B; e += blockDim.x) lpiv[e] = ld(fpiv + e);
+      __syncthreads();
+      for (int k = 0; k < nk; ++k) {
+        const int e = threadIdx.x + k * kThreads;
+        const bool live = e < B;
+        cx<R> h[NW], x[NW + 1];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) h[i] = czero<R>();
+#pragma unroll
+        for (int l = 0; l <= NW; ++l) x[l] = czero<R>();
+        if (live) {
+          int kap[kMaxUq];
+          int rem = e;
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q) {
+            kap[q] = q < nq ? rem / P.ustride[q] : 0;
+            rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+          }
+#pragma unroll
+          for (int j = 0; j < MD; ++j) {
+            if (j == 0 || m[j] <= P.CD[j] - 2)
+              h[nq + 2 * j] = cscale(ld(V.gcur[fam_f1k(j)] + rB + e), isq[m[j] + 1]);
+            const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
+            if (okb) h[nq + 2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + rB + e), isq[m[j] + 1]);
+            if (m[j] > 0) {
+              x[nq + 2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+              x[nq + 2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q)
+            if (q < nq && kap[q] > 0) x[q] = cscale(lpiv[e - P.ustride[q]], sq[kap[q]]);
+          x[npos] = lpiv[e];
+#pragma unroll
+          for (int l = 0; l < NPD; ++l) {
+            const int j = l >> 1;
+            if (m[j] == 0) continue;
+            cx<R> u = czero<R>();
+#pragma unroll
+            for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + nq + l), h[nq + i]);
+            st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + (size_t)rdn[j] * B + e, cscale(u, sq[m[j]]));
+          }
+          cx<R> gp = czero<R>();
+#pragma unroll
+          for (int i = 0; i < NPD; ++i) cfma_conj(gp, ld(bi + nq + i), h[nq + i]);
+          st(gf0 + e, cadd(ld(gf0 + e), gp));
+#pragma unroll
+          for (int q = 0; q < kMaxUq; ++q) {
+            if (q < nq) {
+              cx<R> u = czero<R>();
+#pragma unroll
+              for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + q), h[nq + i]);
+              qpull[(size_t)q * B + e] = u;
+            }
+          }
+        }
+        stage_accumulate<R, NW>(pm, npos, h, x, Hs, Xs, a0, a1);
+      }
+      for (int e = threadIdx.x; e < B; e += blockDim.x) {
+        int rem = e;
+        cx<R> acc = ld(gf0 + e);
+#pragma unroll
+        for (int q = 0; q < kMaxUq; ++q) {
+          if (q < nq) {
+            const int kq = rem / P.ustride[q];
+            rem -= kq * P.ustride[q];
+            if (kq + 1 < P.udims[q]) acc = cadd(acc, cscale(qpull[(size_t)q * B + e + P.ustride[q]], sq[kq + 1]));
+          }
+        }
+        st(gf0 + e, acc);
+      }
+      __syncthreads();
+    }
+  }
+  flush_pairs(pm, partial + (size_t)blockIdx.x * pm.P, a0, a1, red);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of step 1 of Algorithm 2 (undetected block at zero detections), by
+// weight from the top: an entry's cotangent gathers from the targets that
+// used it as pivot (x + 1_q with first non-zero coordinate q) or as a read
+// (x + 1_q2 + 1_q with parent x + 1_q2, first non-zero coordinate q).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_ufill_vjp(DevPlan P, const cx<R>* __restrict__ Ai,
+                                                        const cx<R>* __restrict__ bi, const cx<R>* __restrict__ G,
+                                                        const cx<R>* __restrict__ gin, cx<R>* gfin,
+                                                        const int* __restrict__ elist, const int* __restrict__ woff,
+                                                        int wmax, double2* slot, cx<R>* cbar) {
+  const int nq = P.nq, npos = P.npos;
+  const int NR = npos + 1;
+  cx<double> ab[kMaxUq][kMaxUq + 1];
+#pragma unroll
+  for (int a = 0; a < kMaxUq; ++a)
+#pragma unroll
+    for (int c = 0; c <= kMaxUq; ++c) ab[a][c] = cmake<double>(0.0, 0.0);
+  for (int w = wmax; w >= 0; --w) {
+    for (int t = woff[w] + threadIdx.x; t < woff[w + 1]; t += blockDim.x) {
+      const int e = elist[t];
+      int x[kMaxUq];
+      int rem = e;
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        x[q] = q < nq ? rem / P.ustride[q] : 0;
+        rem -= x[q] * (q < nq ? P.ustride[q] : 0);
+      }
+      int first0 = nq;
+#pragma unroll
+      for (int q = kMaxUq - 1; q >= 0; --q)
+        if (q < nq && x[q] > 0) first0 = q;
+      cx<R> acc = ld(gin + e);
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        if (q >= nq || q > first0) continue;
+        if (x[q] + 1 < P.udims[q]) {
+          const cx<R> ht = cscale(ld(gfin + e + P.ustride[q]), R(1) / sqrt(R(x[q] + 1)));
+          cfma_conj(acc, ld(bi + q), ht);
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < kMaxUq; ++q2) {
+          if (q2 < q || q2 >= nq) continue;
+          const int p2 = x[q2] + 1;                  // parent coordinate along q2
+          const int pq = x[q] + (q2 == q ? 1 : 0);   // parent coordinate along q
+          if (p2 >= P.udims[q2] || pq + 1 >= P.udims[q]) continue;
+          const cx<R> ht = cscale(ld(gfin + e + P.ustride[q2] + P.ustride[q]), R(1) / sqrt(R(pq + 1)));
+          cx<R> u = czero<R>();
+          cfma_conj(u, ld(Ai + q * npos + q2), ht);
+          acc = cadd(acc, cscale(u, sqrt(R(p2))));
+        }
+      }
+      st(gfin + e, acc);
+      if (e > 0) {
+        // this entry as a target: parent x - 1_first0, direction first0
+        const int qf = first0;
+        const int pe = e - P.ustride[qf];
+        const R s = R(1) / sqrt(R(x[qf]));
+        const cx<R> h = cscale(acc, s);
+        const cx<R> gp = ld(G + pe);
+#pragma unroll
+        for (int a = 0; a < kMaxUq; ++a) {
+          if (a != qf) continue;
+          ab[a][kMaxUq].x += (double)gp.x * h.x + (double)gp.y * h.y;
+          ab[a][kMaxUq].y += (double)gp.x * h.y - (double)gp.y * h.x;
+#pragma unroll
+          for (int q2 = 0; q2 < kMaxUq; ++q2) {
+            if (q2 >= nq) continue;
+            const int pq2 = x[q2] - (q2 == qf ? 1 : 0);
+            if (pq2 <= 0) continue;
+            const cx<R> g2 = cscale(ld(G + pe - P.ustride[q2]), sqrt(R(pq2)));
+            ab[a][q2].x += (double)g2.x * h.x + (double)g2.y * h.y;
+            ab[a][q2].y += (double)g2.x * h.y - (double)g2.y * h.x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // workgroup reduction of ab (fixed order) into the slot
+  __shared__ cx<double> red[kThreads];
+#pragma unroll
+  for (int a = 0; a < kMaxUq; ++a) {
+#pragma unroll
+    for (int c = 0; c <= kMaxUq; ++c) {
+      if (a >= nq || (c >= nq && c != kMaxUq)) continue;   // uniform
+      red[threadIdx.x] = ab[a][c];
+      __syncthreads();
+      for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+          red[threadIdx.x].x += red[threadIdx.x + w].x;
+          red[threadIdx.x].y += red[threadIdx.x + w].y;
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        const int p = a * NR + (c == kMaxUq ? npos : c);
+        double2 v = slot[p];
+        slot[p] = make_double2(v.x + red[0].x, v.y + red[0].y);
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) st(cbar, ld(gfin));
+}
+
+// Final: sum the partial slots in order, symmetrise Abar, scatter to the
+// caller's block order (zero for dropped modes), write dc.
+struct FinalArgs {
+  int blk2pos[2 * kMaxModes];
+  int M2, npos, nslots;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_vjp_final(const double2* __restrict__ partial, FinalArgs a,
+                                                        const cx<R>* __restrict__ cbar, cx<R>* dA, cx<R>* db,
+                                                        cx<R>* dc) {
+  __shared__ double2 red[kThreads];
+  const int NR = a.npos + 1, P = a.npos * NR;
+  const int idx = blockIdx.x;
+  int c1 = -1, c2 = -1;   // pair columns summed (c2: transpose for the symmetric part)
+  if (idx < a.M2 * a.M2) {
+    const int p = a.blk2pos[idx / a.M2], q = a.blk2pos[idx % a.M2];
+    if (p >= 0 && q >= 0) {
+      c1 = p * NR + q;
+      c2 = q * NR + p;
+    }
+  } else if (idx < a.M2 * a.M2 + a.M2) {
+    const int p = a.blk2pos[idx - a.M2 * a.M2];
+    if (p >= 0) c1 = p * NR + a.npos;
+  }
+  double sx = 0.0, sy = 0.0;
+  if (c1 >= 0)
+    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) {
+      const double2 v = partial[(size_t)s * P + c1];
+      sx += v.x;
+      sy += v.y;
+      if (c2 >= 0) {
+        const double2 w = partial[(size_t)s * P + c2];
+        sx += w.x;
+        sy += w.y;
+      }
+    }
+  red[threadIdx.x] = make_double2(sx, sy);
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double2 t = red[0];
+  if (idx < a.M2 * a.M2)
+    st(dA + idx, cmake<R>((R)(0.5 * t.x), (R)(0.5 * t.y)));
+  else if (idx < a.M2 * a.M2 + a.M2)
+    st(db + (idx - a.M2 * a.M2), cmake<R>((R)t.x, (R)t.y));
+  else
+    st(dc, ld(cbar));
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+template <typename R>
+static const cx<R>* fptr(const Plan& Pl, const char* base, size_t off, int g, int S) {
+  if (S < 0 || off == 0) return nullptr;
+  return reinterpret_cast<const cx<R>*>(base + off +
+                                         (size_t)Pl.lvl[(size_t)g * (Pl.smax + 2) + S] * Pl.B * sizeof(cx<R>));
+}
+template <typename R>
+static cx<R>* gptr(const Plan& Pl, char* base, size_t off, int g, int S) {
+  if (S < 0 || off == 0) return nullptr;
+  return reinterpret_cast<cx<R>*>(base + off + (size_t)(S & 1) * Pl.maxN[g] * Pl.B * sizeof(cx<R>));
+}
+
+template <typename R>
+static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c,
+                            const void* saved, const void* drho, void* dA, void* db, void* dc, char* ws,
+                            hipStream_t st) {
+  const VjpLayout V = vjp_layout(Pl, odd, 0);
+  const FwdLayout Ls = fwd_layout(Pl, true, true, 0);
+  const char* sv = reinterpret_cast<const char*>(saved);
+  cx<R>* Ai = reinterpret_cast<cx<R>*>(ws + V.prep);
+  cx<R>* bi = Ai + (size_t)Pl.npos * Pl.npos;
+  cx<R>* cb = bi + Pl.npos;   // reused: holds cbar at the end
+  double2* partial = reinterpret_cast<double2*>(ws + V.partial);
+  hipError_t e = launch_prep(Pl, A, b, c, Ai, nullptr, st);
+  if (e != hipSuccess) return e;
+  const int PP = Pl.npos * (Pl.npos + 1);
+  const int64_t npart = (int64_t)kPartialSlots * PP;
+  hipLaunchKernelGGL(k_zero_d2, dim3((unsigned)std::min<int64_t>((npart + 255) / 256, 4096)), dim3(256), 0, st,
+                     partial, npart);
+  DevPlan P = make_devplan(Pl, odd);
+  cx<R>* g0 = reinterpret_cast<cx<R>*>(ws + V.g0);
+  {
+    const int64_t total = Pl.out_elems;
+    const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
+    const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;
+    hipLaunchKernelGGL((k_perm_in<R>), dim3(grid), dim3(kThreads), shm, st, P,
+                       reinterpret_cast<const cx<R>*>(drho), g0, (int64_t)Pl.nodes_total, total);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int MD = Pl.MD;
+  const size_t tab = 2 * (kMaxCut + 4) * sizeof(R) + (size_t)(MD + 1) * (Pl.smax + 3) * sizeof(int);
+  for (int S = Pl.smax; S >= 0 && MD > 0; --S) {
+    VjpPtrs<R> Vp;
+    std::memset(&Vp, 0, sizeof(Vp));
+    for (int f = 0; f < Pl.nfam; ++f) {
+      const size_t foff = f == 0 ? Ls.f0 : Ls.fam[f];
+      const int g = Pl.fam_group[f];
+      Vp.fprev[f] = fptr<R>(Pl, sv, foff, g, S - 1);
+      Vp.fcur[f] = fptr<R>(Pl, sv, foff, g, S);
+      Vp.gprev[f] = gptr<R>(Pl, ws, V.gfam[f], g, S - 1);
+      Vp.gcur[f] = gptr<R>(Pl, ws, V.gfam[f], g, S);
+    }
+    Vp.gf0nxt = gptr<R>(Pl, ws, V.gfam[0], 0, S + 1);
+    Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
+                                              (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
+    const int nwork = (int)Pl.ncnt[S];
+    if (Pl.B == 1) {
+      const int NP = 2 * MD;
+      const size_t shm = (size_t)(2 * NP + 1) * kRS * sizeof(cx<R>) + kThreads * sizeof(cx<double>) + tab;
+      const int grid = (int)std::min<int64_t>((nwork + kThreads - 1) / kThreads, kPartialSlots - 1);
+#define FD_VJP_POINT(MDV)                                                                                        \
+  case MDV:                                                                                                      \
+    if (odd) {                                                                                                   \
+      if (shm > 65536)                                                                                           \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, true, R>),                    \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                         \
+      hipLaunchKernelGGL((k_vjp_point<MDV, true, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,   \
+                         nwork, partial);                                                                        \
+    } else {                                                                                                     \
+      if (shm > 65536)                                                                                           \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, false, R>),                   \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                         \
+      hipLaunchKernelGGL((k_vjp_point<MDV, false, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,  \
+                         nwork, partial);                                                                        \
+    }                                                                                                            \
+    break;
+      switch (MD) {
+        FD_VJP_POINT(1)
+        FD_VJP_POINT(2)
+        FD_VJP_POINT(3)
+        FD_VJP_POINT(4)
+        FD_VJP_POINT(5)
+        FD_VJP_POINT(6)
+        FD_VJP_POINT(7)
+        FD_VJP_POINT(8)
+        default:
+          return hipErrorInvalidValue;
+      }
+#undef FD_VJP_POINT
+    } else {
+      const size_t shm = (size_t)(1 + Pl.nq) * Pl.B * sizeof(cx<R>) + (size_t)(2 * Pl.npos + 1) * kRS * sizeof(cx<R>) +
+                         kThreads * sizeof(cx<double>) + tab;
+      const int grid = std::min(nwork, kPartialSlots - 1);
+#define FD_VJP_BLOCK(MDV)                                                                                       \
+  case MDV:                                                                                                     \
+    if (Pl.nq == 2) {                                                                                           \
+      if (shm > 65536)                                                                                          \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R>),                      \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
+                         nwork, partial);                                                                       \
+    } else {                                                                                                    \
+      if (shm > 65536)                                                                                          \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R>),                      \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
+                         nwork, partial);                                                                       \
+    }                                                                                                           \
+    break;
+      switch (MD) {
+        FD_VJP_BLOCK(1)
+        FD_VJP_BLOCK(2)
+        FD_VJP_BLOCK(3)
+        FD_VJP_BLOCK(4)
+        FD_VJP_BLOCK(5)
+        FD_VJP_BLOCK(6)
+        FD_VJP_BLOCK(7)
+        FD_VJP_BLOCK(8)
+        default:
+          return hipErrorInvalidValue;
+      }
+#undef FD_VJP_BLOCK
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // cotangent of the seed block: F0 ring slot of level 0 (MD > 0) or drho itself
+  const cx<R>* gseed = MD > 0 ? gptr<R>(Pl, ws, V.gfam[0], 0, 0) : g0;
+  const cx<R>* cbar_src = gseed;
+  if (Pl.B > 1) {
+    cx<R>* gfin = reinterpret_cast<cx<R>*>(ws + V.ufin);
+    const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + Ls.f0);
+    hipLaunchKernelGGL((k_ufill_vjp<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, G0blk, gseed, gfin, Pl.d_elist,
+                       Pl.d_woff, Pl.wmax, partial + (size_t)(kPartialSlots - 1) * PP, cb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    cbar_src = cb;
+  }
+  FinalArgs fa;
+  std::memset(&fa, 0, sizeof(fa));
+  for (int u = 0; u < 2 * Pl.M; ++u) fa.blk2pos[u] = -1;
+  for (int p = 0; p < Pl.npos; ++p) fa.blk2pos[Pl.pos2blk[p]] = p;
+  fa.M2 = 2 * Pl.M;
+  fa.npos = Pl.npos;
+  fa.nslots = kPartialSlots;
+  const int nout = fa.M2 * fa.M2 + fa.M2 + 1;
+  hipLaunchKernelGGL((k_vjp_final<R>), dim3(nout), dim3(kThreads), 0, st, partial, fa, cbar_src,
+                     reinterpret_cast<cx<R>*>(dA), reinterpret_cast<cx<R>*>(db), reinterpret_cast<cx<R>*>(dc));
+  return hipGetLastError();
+}
+
+hipError_t run_vjp(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, const void* saved,
+                   const void* drho, void* dA, void* db, void* dc, void* ws, hipStream_t st) {
+  if (Pl.dt == FD_C64) return run_vjp_t<float>(Pl, odd, A, b, c, saved, drho, dA, db, dc, (char*)ws, st);
+  return run_vjp_t<double>(Pl, odd, A, b, c, saved, drho, dA, db, dc, (char*)ws, st);
+}
+
+}  // namespace fd

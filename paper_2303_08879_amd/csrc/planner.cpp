@@ -80,8 +80,8 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     P->ustride[q] = (int)B;
     B *= P->udims[q];
   }
-  if (B > 65536) {
-    *err = "undetected block prod C_u^2 exceeds 65536";
+  if (B > kMaxBlock) {
+    *err = "undetected block prod C_u^2 exceeds 4096";
     return FD_ERR_UNSUPPORTED;
   }
   P->B = (int)B;
@@ -281,8 +281,17 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   }
   L.partial = off;
   off = align256(off + (size_t)kPartialSlots * P.npos * (P.npos + 1) * 16);
+  L.ufin = off;
+  off = align256(off + (size_t)P.B * eb);
   L.total = off;
   return L;
+}
+
+size_t vjp_lds_bytes(const Plan& P) {
+  const size_t eb = elem_bytes(P.dt);
+  const size_t rdt = P.dt == FD_C64 ? 4 : 8;
+  return (size_t)(1 + P.nq) * P.B * eb + (size_t)(2 * P.npos + 1) * 64 * eb + 256 * 16 +
+         2 * (kMaxCut + 4) * rdt + (size_t)(P.MD + 1) * (P.smax + 3) * 4;
 }
 
 fd_status ensure_device(Plan* P, std::string* err) {
