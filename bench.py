@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the selective Fock-amplitude path on one MI355X.
+
+Workload (default): the conditional-state circuit with M=4 modes, mode 0
+undetected (cutoff 30) and modes 1..3 detected (cutoff 12), displaced
+(b != 0), seeded synthetic triple; one step = forward (every intermediate
+kept for the reverse sweep) + reverse sweep with a dense seeded cotangent,
+complex128.  `value` = output Fock amplitudes (entries of rho) per second of
+whole-step wall time, inputs already resident in HBM.
+
+Prints one JSON line.  See the design doc for the roofline accounting.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "Fock amplitudes/s (c128, fwd+VJP) and batched circuits/s at ≤1e-10 rel err"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def workload(name):
+    from paper_2303_08879_amd import workloads as W
+    if name == "config2":
+        return W.config2(), "M=4 conditional state: mode 0 undetected C_U=30, modes 1-3 detected C_D=12, b!=0"
+    if name == "config4":
+        return W.config4(), "M=5 conditional state: mode 0 undetected C_U=40, modes 1-4 detected C_D=10, b=0"
+    if name == "config5":
+        return W.config5(), "M=8 all detected C=8 (16.8M detection probabilities), b=0"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(circ, rho_gpu, g_full, corner):
+    """The oracle, unchanged, on a bounded sample of the same workload: all
+    conditional blocks rho[:, :, n] with every detected n_j < corner, forward
+    plus the closed-form adjoint for the cotangent restricted to that sample."""
+    import numpy as np
+    import oracle as O
+    M = circ.M
+    cut = [circ.cutoffs[j] if not (circ.detected_mask >> j) & 1 else corner for j in range(M)]
+    nU = sum(1 for j in range(M) if not (circ.detected_mask >> j) & 1)
+    sl = (slice(None),) * (2 * nU) + (slice(0, corner),) * (len(rho_gpu.shape) - 2 * nU)
+    t0 = time.perf_counter()
+    out = O.fock_diag(circ.A, circ.b, circ.c, cut, circ.detected_mask)
+    gs = g_full[sl]
+    O.fock_diag_vjp(circ.A, circ.b, circ.c, cut, circ.detected_mask, gs)
+    dt = time.perf_counter() - t0
+    err = O.rel_err(rho_gpu[sl], out)
+    return dict(value=out.size / dt, unit="Fock amplitudes/s", cores=1, kind="oracle",
+                sample=(f"every output block with detected n_j < {corner} ({out.size} of {rho_gpu.size} "
+                        f"amplitudes), forward + closed-form adjoint, numpy float64, single thread; "
+                        f"per-amplitude cost grows with n, so this sample overstates the oracle's full rate"),
+                seconds=dt, sample_rel_err_gpu_vs_oracle=err)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-corner", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this library runs each circuit on a single device and "
+              f"the build targets one-GPU boxes (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+
+    circ, desc = workload(args.workload)
+    dev = "cuda"
+    dt = torch.complex128
+    b_zero = not np.any(circ.b)
+    plan = F.Plan(circ.cutoffs, circ.detected_mask, dt, "zero" if b_zero else "general")
+    A = torch.tensor(circ.A, dtype=dt, device=dev)
+    b = torch.tensor(circ.b, dtype=dt, device=dev)
+    c = torch.tensor([circ.c], dtype=dt, device=dev)
+    shape = plan.out_shape
+    g_np = W.random_cotangent(shape, seed=7)
+    g = torch.tensor(g_np, dtype=dt, device=dev)
+    ws_bytes, saved_bytes = plan.workspace(True)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    saved = torch.empty(saved_bytes, dtype=torch.uint8, device=dev)
+    rho = torch.empty(shape, dtype=dt, device=dev)
+    dA, db, dc = torch.empty_like(A), torch.empty_like(b), torch.empty_like(c)
+
+    def step():
+        F.fock_diag_fwd(plan, A, b, c, rho, ws, saved)
+        F.fock_diag_vjp(plan, A, b, c, saved, g, dA, db, dc, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    F.fd_device_status(plan)
+
+    # timed region: whole steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = t1 - t0
+    out_elems = plan.query(F.FD_Q_OUT_ELEMS)
+    value = out_elems * args.steps / sec
+
+    # same steps again with HIP events around every level-sweep launch
+    F.fd_plan_timing(plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_VJP_LEVEL))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n_f, ms_f = F.fd_plan_kernel_times(plan, F.FD_K_FWD_LEVEL)
+    n_v, ms_v = F.fd_plan_kernel_times(plan, F.FD_K_VJP_LEVEL)
+    F.fd_plan_timing(plan, 0)
+    F.fd_device_status(plan)
+
+    targets = plan.query(F.FD_Q_TARGETS)
+    terms = plan.query(F.FD_Q_READ_TERMS)
+    # algorithmic bytes per computed amplitude (c128): forward writes it once and
+    # its reader reads it once (32 B); reverse reads its cotangent, reads the
+    # forward value it was computed from and writes the cotangent of that read (48 B)
+    fwd_bytes = 32.0 * targets * args.steps
+    vjp_bytes = 48.0 * targets * args.steps
+    fwd_gbs = fwd_bytes / (ms_f * 1e-3) / 1e9
+    vjp_gbs = vjp_bytes / (ms_v * 1e-3) / 1e9
+    kind = "block" if plan.query(F.FD_Q_BLOCK) > 1 else "point"
+    if ms_v >= ms_f:
+        dom = dict(kernel=f"k_vjp_{kind} (reverse level sweep)", achieved=vjp_gbs, launches=n_v,
+                   avg_launch_us=1e3 * ms_v / max(n_v, 1), bytes_per_unit=48)
+    else:
+        dom = dict(kernel=f"k_fwd_{kind} (forward level sweep)", achieved=fwd_gbs, launches=n_f,
+                   avg_launch_us=1e3 * ms_f / max(n_f, 1), bytes_per_unit=32)
+    roof = {"bound": "hbm", "achieved": round(dom["achieved"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom["kernel"],
+            "avg_launch_us": round(dom["avg_launch_us"], 3), "launches": dom["launches"],
+            "algorithmic_bytes_per_amplitude": dom["bytes_per_unit"]}
+    flops_fwd = 8.0 * terms
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Fock amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}; one step = forward + VJP, complex128",
+                   "out_amplitudes": out_elems, "computed_amplitudes": targets},
+        "roofline": roof,
+        "detail": {
+            "computed_amplitudes_per_s": targets * args.steps / sec,
+            "fwd_level_ms_per_step": ms_f / args.steps, "vjp_level_ms_per_step": ms_v / args.steps,
+            "fwd_level_GBs": round(fwd_gbs, 2), "vjp_level_GBs": round(vjp_gbs, 2),
+            "fwd_level_GFLOPs": flops_fwd * args.steps / (ms_f * 1e-3) / 1e9,
+            "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS,
+            "events_pass_ms_per_step": 1e3 * (t3 - t2) / args.steps,
+        },
+    }
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize()
+        step()
+        torch.cuda.synchronize()
+        line["cpu_baseline"] = cpu_baseline(circ, rho.cpu().numpy(), g_np, args.cpu_corner)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,19 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
                               const void* const* b, const void* const* c, void* const* rho,
                               void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
 
+/* Per-kernel timing for reports: with bit k of kind_mask set, every launch of
+ * kernel kind k made through this plan is bracketed by two HIP events on its
+ * stream (fd_plan_timing also drops earlier records).  fd_plan_kernel_times
+ * waits for the recorded events and returns the number of launches and their
+ * summed duration in milliseconds, then drops the records.  Kinds:
+ * 0 input prep, 1 undetected-block fill, 2 forward level sweep, 3 output
+ * permutation, 4 cotangent permutation, 5 reverse level sweep, 6 reverse of
+ * the undetected-block fill, 7 gradient reduction, 8 accumulator clear. */
+enum { FD_K_PREP = 0, FD_K_UFILL = 1, FD_K_FWD_LEVEL = 2, FD_K_OUT_PERM = 3, FD_K_PERM_IN = 4,
+       FD_K_VJP_LEVEL = 5, FD_K_UFILL_VJP = 6, FD_K_VJP_FINAL = 7, FD_K_ZERO = 8 };
+fd_status fd_plan_timing(fd_plan p, uint32_t kind_mask);
+fd_status fd_plan_kernel_times(fd_plan p, int kind, int64_t* launches, double* total_ms);
+
 /* Message of the last host-side error on the calling thread ("" if none). */
 const char* fd_last_error(void);
 

@@ -93,6 +93,12 @@ fd_status fd_plan_destroy(fd_plan p) {
     (void)hipFree(P.d_woff);
     (void)hipSetDevice(cur);
   }
+  for (auto& v : P.timing.rec)
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : P.timing.pool) (void)hipEventDestroy(e);
   delete p;
   return ok();
 }
@@ -220,6 +226,42 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
     fd_status s = fock_diag_fwd(plans[i], A[i], b[i], c[i], rho[i], workspace[i], ws_bytes[i], nullptr, 0, stream);
     if (s != FD_OK) return s;
   }
+  return ok();
+}
+
+fd_status fd_plan_timing(fd_plan p, uint32_t kind_mask) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Timing& T = p->P.timing;
+  for (auto& v : T.rec) {
+    for (auto& pr : v) {
+      T.pool.push_back(pr.first);
+      T.pool.push_back(pr.second);
+    }
+    v.clear();
+  }
+  T.mask = kind_mask;
+  return ok();
+}
+
+fd_status fd_plan_kernel_times(fd_plan p, int kind, int64_t* launches, double* total_ms) {
+  if (!p || !launches || !total_ms || kind < 0 || kind >= fd::KK_COUNT)
+    return fail(FD_ERR_INVALID_ARG, "bad timing query");
+  fd::Timing& T = p->P.timing;
+  double tot = 0.0;
+  for (auto& pr : T.rec[kind]) {
+    if (hipEventSynchronize(pr.second) != hipSuccess) return fail(FD_ERR_HIP, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+      return fail(FD_ERR_HIP, "hipEventElapsedTime failed");
+    tot += ms;
+  }
+  *launches = (int64_t)T.rec[kind].size();
+  *total_ms = tot;
+  for (auto& pr : T.rec[kind]) {
+    T.pool.push_back(pr.first);
+    T.pool.push_back(pr.second);
+  }
+  T.rec[kind].clear();
   return ok();
 }
 

@@ -82,6 +82,17 @@ struct FamPtrs {
   int ring;                  // 1: two-slot ring (slot S&1), 0: store-all by level
 };
 
+// Optional per-launch HIP-event timing, by kernel kind.
+enum KernelKind {
+  KK_PREP = 0, KK_UFILL, KK_FWD_LEVEL, KK_OUT_PERM, KK_PERM_IN, KK_VJP_LEVEL, KK_UFILL_VJP, KK_VJP_FINAL,
+  KK_ZERO, KK_COUNT
+};
+struct Timing {
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[KK_COUNT];
+};
+
 struct Plan {
   // caller's view
   int M = 0;
@@ -113,6 +124,7 @@ struct Plan {
   int wmax = 0;
   int* d_elist = nullptr;
   int* d_woff = nullptr;
+  mutable Timing timing;
   bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
 };
 
@@ -143,6 +155,36 @@ constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);
 size_t prep_bytes(const Plan& P);
 void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
+
+// Brackets one launch with events when its kind is enabled on the plan.
+struct KTimer {
+  Timing* T = nullptr;
+  int kind = 0;
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(const Plan& P, int k, hipStream_t st) : T(&P.timing), kind(k), s(st) {
+    if (!(T->mask & (1u << k))) return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~KTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      T->rec[kind].push_back({a, b});
+    }
+  }
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!T->pool.empty()) {
+      e = T->pool.back();
+      T->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+};
 
 // kernels (kernels_fwd.hip / kernels_vjp.hip)
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,

@@ -522,9 +522,14 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   cx<R>* f0 = reinterpret_cast<cx<R>*>(fb + LF.f0);
   DevPlan P = make_devplan(Pl, odd);
   (void)ci;
-  hipError_t e = launch_prep(Pl, A, b, c, Ai, f0, st);
+  hipError_t e;
+  {
+    KTimer kt(Pl, KK_PREP, st);
+    e = launch_prep(Pl, A, b, c, Ai, f0, st);
+  }
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
+    KTimer kt(Pl, KK_UFILL, st);
     hipLaunchKernelGGL((k_ufill<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff,
                        Pl.wmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -540,13 +545,17 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
     }
     L.f0cur = fam_level_ptr<R>(Pl, fb, LF.f0, 0, S, false);
     L.f0nxt = S < Pl.smax ? fam_level_ptr<R>(Pl, fb, LF.f0, 0, S + 1, false) : nullptr;
-    e = launch_fwd_level_t<R>(Pl, P, odd, S, L, Ai, bi, st);
+    {
+      KTimer kt(Pl, KK_FWD_LEVEL, st);
+      e = launch_fwd_level_t<R>(Pl, P, odd, S, L, Ai, bi, st);
+    }
     if (e != hipSuccess) return e;
   }
   if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
   const int64_t total = Pl.out_elems;
   const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
   const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;
+  KTimer kt(Pl, KK_OUT_PERM, st);
   hipLaunchKernelGGL((k_out_perm<R>), dim3(grid), dim3(kThreads), shm, st, P, f0, reinterpret_cast<cx<R>*>(rho),
                      (int64_t)Pl.nodes_total, total, Pl.d_status);
   return hipGetLastError();

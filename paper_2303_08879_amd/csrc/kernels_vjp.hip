@@ -732,18 +732,26 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   cx<R>* bi = Ai + (size_t)Pl.npos * Pl.npos;
   cx<R>* cb = bi + Pl.npos;   // reused: holds cbar at the end
   double2* partial = reinterpret_cast<double2*>(ws + V.partial);
-  hipError_t e = launch_prep(Pl, A, b, c, Ai, nullptr, st);
+  hipError_t e;
+  {
+    KTimer kt(Pl, KK_PREP, st);
+    e = launch_prep(Pl, A, b, c, Ai, nullptr, st);
+  }
   if (e != hipSuccess) return e;
   const int PP = Pl.npos * (Pl.npos + 1);
   const int64_t npart = (int64_t)kPartialSlots * PP;
-  hipLaunchKernelGGL(k_zero_d2, dim3((unsigned)std::min<int64_t>((npart + 255) / 256, 4096)), dim3(256), 0, st,
-                     partial, npart);
+  {
+    KTimer kt(Pl, KK_ZERO, st);
+    hipLaunchKernelGGL(k_zero_d2, dim3((unsigned)std::min<int64_t>((npart + 255) / 256, 4096)), dim3(256), 0, st,
+                       partial, npart);
+  }
   DevPlan P = make_devplan(Pl, odd);
   cx<R>* g0 = reinterpret_cast<cx<R>*>(ws + V.g0);
   {
     const int64_t total = Pl.out_elems;
     const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
     const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;
+    KTimer kt(Pl, KK_PERM_IN, st);
     hipLaunchKernelGGL((k_perm_in<R>), dim3(grid), dim3(kThreads), shm, st, P,
                        reinterpret_cast<const cx<R>*>(drho), g0, (int64_t)Pl.nodes_total, total);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -765,6 +773,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
                                               (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
     const int nwork = (int)Pl.ncnt[S];
+    KTimer kt(Pl, KK_VJP_LEVEL, st);
     if (Pl.B == 1) {
       const int NP = 2 * MD;
       const size_t shm = (size_t)(2 * NP + 1) * kRS * sizeof(cx<R>) + kThreads * sizeof(cx<double>) + tab;
@@ -840,6 +849,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   if (Pl.B > 1) {
     cx<R>* gfin = reinterpret_cast<cx<R>*>(ws + V.ufin);
     const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + Ls.f0);
+    KTimer kt(Pl, KK_UFILL_VJP, st);
     hipLaunchKernelGGL((k_ufill_vjp<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, G0blk, gseed, gfin, Pl.d_elist,
                        Pl.d_woff, Pl.wmax, partial + (size_t)(kPartialSlots - 1) * PP, cb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -853,6 +863,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   fa.npos = Pl.npos;
   fa.nslots = kPartialSlots;
   const int nout = fa.M2 * fa.M2 + fa.M2 + 1;
+  KTimer kt(Pl, KK_VJP_FINAL, st);
   hipLaunchKernelGGL((k_vjp_final<R>), dim3(nout), dim3(kThreads), 0, st, partial, fa, cbar_src,
                      reinterpret_cast<cx<R>*>(dA), reinterpret_cast<cx<R>*>(db), reinterpret_cast<cx<R>*>(dc));
   return hipGetLastError();
