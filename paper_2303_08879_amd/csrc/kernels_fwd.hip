@@ -220,51 +220,68 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 2 (undetected modes present): one workgroup per lattice point,
-// threads over the B entries of the node blocks.  The pivot block (its own
-// undetected neighbours enter every target) is staged in LDS.
+// Algorithm 2 (undetected modes present).  A node's block of B entries is
+// split into chunks of whole rows of the first undetected coordinate (rows of
+// R0 = B / C0 entries); one workgroup handles one (lattice point, chunk).
+// The pivot's undetected neighbours reach one row back, so a chunk computes
+// the pivot rows it needs one row above its own (recomputed, not stored).
+// LDS: F0(m) rows [k0-2, k1) and the bridge pivot blocks F1k(K)(m), rows
+// [k0-1, k1), for every bridge K applied at m.
 // ---------------------------------------------------------------------------
-template <int MD, typename R>
+template <int MD, int NQ, typename R>
 __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
-                                                        const cx<R>* __restrict__ bi, int S, int nwork) {
+                                                        const cx<R>* __restrict__ bi, int S, int nwork,
+                                                        ChunkGeo G) {
   constexpr int NPD = 2 * MD;
+  constexpr int NPOS = NQ + NPD;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int B = P.B, nq = P.nq, npos = P.npos;
-  cx<R>* lds0 = reinterpret_cast<cx<R>*>(smem_raw);   // F0(m) block
-  cx<R>* lds1 = lds0 + B;                              // current pivot block
-  R* sq = reinterpret_cast<R*>(lds1 + B);
+  const int B = P.B, R0 = G.R0;
+  cx<R>* lf0 = reinterpret_cast<cx<R>*>(smem_raw);             // (RC + 2) rows
+  cx<R>* lpk = lf0 + (size_t)(G.RC + 2) * R0;                  // MD x (RC + 1) rows
+  R* sq = reinterpret_cast<R*>(lpk + (size_t)MD * (G.RC + 1) * R0);
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables(P, spn, sq, isq);
   __syncthreads();
   const int pnw = P.pnw;
-  for (int r = blockIdx.x; r < nwork; r += gridDim.x) {
+  const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
+  for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
+    const int r = w / G.nchunks, c = w - r * G.nchunks;
+    const int k0 = c * G.RC, k1 = min(G.C0, k0 + G.RC);
     int m[MD], s[MD + 1], rdn[MD], rup[MD];
     unrank<MD>(spn, pnw, P.CD, S, r, m, s);
     neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
-    const size_t rB = (size_t)r * B;
-    for (int e = threadIdx.x; e < B; e += blockDim.x) lds0[e] = ld(L.f0cur + rB + e);
-    __syncthreads();
     int K0 = MD;
 #pragma unroll
     for (int d = MD - 1; d >= 0; --d)
       if (m[d] > 0) K0 = d;
-
-    if (m[0] <= P.CD[0] - 2) {
-      // diagonal pivot block [., ., d(m)]
-      for (int e = threadIdx.x; e < B; e += blockDim.x) {
-        int kap[kMaxUq];
+    if (m[0] > P.CD[0] - 2) continue;   // no pivot at this point (uniform)
+    const size_t rB = (size_t)r * B;
+    // F0(m), rows [k0-2, k1)
+    {
+      const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
+      const int base = (k0 - 2) * R0;
+      for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) lf0[e - base] = ld(L.f0cur + rB + e);
+    }
+    __syncthreads();
+    // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
+    // the halo row only keeps the bridge pivot blocks
+    {
+      const int e0 = max(0, k0 - 1) * R0, e1 = k1 * R0;
+      for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const bool own = e >= k0 * R0;
+        int kap[NQ];
         int rem = e;
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q) {
-          kap[q] = q < nq ? rem / P.ustride[q] : 0;
-          rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+        for (int q = 0; q < NQ; ++q) {
+          kap[q] = rem / P.ustride[q];
+          rem -= kap[q] * P.ustride[q];
         }
-        const cx<R> piv = lds0[e];
-        cx<R> un[kMaxUq];
+        const int le = e - (k0 - 2) * R0;
+        const cx<R> piv = lf0[le];
+        cx<R> un[NQ];
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q)
-          un[q] = (q < nq && kap[q] > 0) ? cscale(lds0[e - P.ustride[q]], sq[kap[q]]) : czero<R>();
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(lf0[le - P.ustride[q]], sq[kap[q]]) : czero<R>();
         cx<R> x[NPD];
 #pragma unroll
         for (int j = 0; j < MD; ++j) {
@@ -283,48 +300,43 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> 
             const int i = 2 * j + side;
             const bool ok = side == 0 ? (j == 0 || m[j] <= P.CD[j] - 2)
                                       : ((j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2));
-            if (!ok) continue;
-            const int row = (nq + i) * npos;
+            const bool bridge = side == 0 && j <= K0 && m[j] <= P.CD[j] - 2;
+            if (!(ok && own) && !bridge) continue;
+            const int row = (NQ + i) * NPOS;
             cx<R> acc = czero<R>();
-            cfma(acc, ld(bi + nq + i), piv);
-            #pragma unroll
-            for (int q = 0; q < kMaxUq; ++q)
-              if (q < nq) cfma(acc, ld(Ai + row + q), un[q]);
+            cfma(acc, ld(bi + NQ + i), piv);
 #pragma unroll
-            for (int l = 0; l < NPD; ++l) cfma(acc, ld(Ai + row + nq + l), x[l]);
+            for (int q = 0; q < NQ; ++q) cfma(acc, ld(Ai + row + q), un[q]);
+#pragma unroll
+            for (int l = 0; l < NPD; ++l) cfma(acc, ld(Ai + row + NQ + l), x[l]);
             acc = cscale(acc, isq[m[j] + 1]);
-            st(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)] + rB + e, acc);
-            if (side == 0 && j == 0) lds1[e] = acc;   // pivot block of the K = 0 bridge
+            if (ok && own) st(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)] + rB + e, acc);
+            if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
           }
         }
       }
     }
     __syncthreads();
-
+    // bridges d(m) + 1_ket(K), own rows
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
-      if (K > K0) break;
-      if (m[K] > P.CD[K] - 2) continue;
-      if (K > 0) {
-        // pivot block F1k(K)(m), written above by this workgroup
-        for (int e = threadIdx.x; e < B; e += blockDim.x) lds1[e] = ld(L.wr[fam_f1k(K)] + rB + e);
-        __syncthreads();
-      }
-      for (int e = threadIdx.x; e < B; e += blockDim.x) {
-        int kap[kMaxUq];
+      if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
+      const cx<R>* pv = lpk + (size_t)K * pk1;
+      for (int e = k0 * R0 + threadIdx.x; e < k1 * R0; e += blockDim.x) {
+        int kap[NQ];
         int rem = e;
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q) {
-          kap[q] = q < nq ? rem / P.ustride[q] : 0;
-          rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+        for (int q = 0; q < NQ; ++q) {
+          kap[q] = rem / P.ustride[q];
+          rem -= kap[q] * P.ustride[q];
         }
-        const cx<R> piv = lds1[e];
-        cx<R> un[kMaxUq];
+        const int lp = e - (k0 - 1) * R0;
+        const cx<R> piv = pv[lp];
+        cx<R> un[NQ];
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q)
-          un[q] = (q < nq && kap[q] > 0) ? cscale(lds1[e - P.ustride[q]], sq[kap[q]]) : czero<R>();
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : czero<R>();
         cx<R> x[NPD];
-        x[2 * K] = cscale(lds0[e], sq[m[K] + 1]);
+        x[2 * K] = cscale(lf0[e - (k0 - 2) * R0], sq[m[K] + 1]);
         x[2 * K + 1] = (m[K] > 0) ? cscale(ld(L.rd[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]) : czero<R>();
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
@@ -356,19 +368,18 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> 
             dst = L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)] + rB + e;
           }
           if (!ok) continue;
-          const int row = (nq + i) * npos;
+          const int row = (NQ + i) * NPOS;
           cx<R> acc = czero<R>();
-          cfma(acc, ld(bi + nq + i), piv);
-          #pragma unroll
-            for (int q = 0; q < kMaxUq; ++q)
-              if (q < nq) cfma(acc, ld(Ai + row + q), un[q]);
+          cfma(acc, ld(bi + NQ + i), piv);
 #pragma unroll
-          for (int l = 2 * K; l < NPD; ++l) cfma(acc, ld(Ai + row + nq + l), x[l]);
+          for (int q = 0; q < NQ; ++q) cfma(acc, ld(Ai + row + q), un[q]);
+#pragma unroll
+          for (int l = 2 * K; l < NPD; ++l) cfma(acc, ld(Ai + row + NQ + l), x[l]);
           st(dst, cscale(acc, scale));
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -414,6 +425,19 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// Rows of the first undetected coordinate per chunk: as many as fit one
+// 256-thread pass together with the recomputed halo row, spread evenly.
+static ChunkGeo chunk_geo(const Plan& Pl) {
+  ChunkGeo G;
+  G.C0 = Pl.udims[0];
+  G.R0 = Pl.B / G.C0;
+  int rc = std::max(1, kThreads / G.R0 - 1);
+  rc = std::min(rc, G.C0);
+  G.nchunks = (G.C0 + rc - 1) / rc;
+  G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
+  return G;
+}
+
 template <typename R>
 static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd, int S, const LevelPtrs<R>& L,
                                      const void* Ai, const void* bi, hipStream_t st) {
@@ -449,14 +473,24 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
     }
 #undef FD_LAUNCH_POINT
   } else {
-    const size_t shm = 2 * (size_t)Pl.B * sizeof(cx<R>) + tab;
-    const int grid = nwork;
-#define FD_LAUNCH_BLOCK(MDV)                                                                                \
-  case MDV:                                                                                                 \
-    if (shm > 65536)                                                                                        \
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, R>),                       \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                      \
-    hipLaunchKernelGGL((k_fwd_block<MDV, R>), dim3(grid), dim3(kThreads), shm, st, P, L, A, b, S, nwork); \
+    const ChunkGeo G = chunk_geo(Pl);
+    const size_t shm = ((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 * sizeof(cx<R>) + tab;
+    const int grid = nwork * G.nchunks;
+#define FD_LAUNCH_BLOCK(MDV)                                                                               \
+  case MDV:                                                                                                \
+    if (Pl.nq == 2) {                                                                                      \
+      if (shm > 65536)                                                                                     \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 2, R>),                 \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
+      hipLaunchKernelGGL((k_fwd_block<MDV, 2, R>), dim3(grid), dim3(kThreads), shm, st, P, L, A, b, S,    \
+                         nwork, G);                                                                        \
+    } else {                                                                                               \
+      if (shm > 65536)                                                                                     \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 4, R>),                 \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
+      hipLaunchKernelGGL((k_fwd_block<MDV, 4, R>), dim3(grid), dim3(kThreads), shm, st, P, L, A, b, S,    \
+                         nwork, G);                                                                        \
+    }                                                                                                      \
     break;
     switch (MD) {
       FD_LAUNCH_BLOCK(1)

@@ -326,35 +326,100 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 2 reverse step: one workgroup per lattice point, threads over
-// block entries.  LDS: the pivot's forward block (undetected neighbours) and
-// the per-entry pulls sum_i conj(A_iq) h_i for each undetected coordinate q.
+// Algorithm 2 reverse step.  One workgroup per (lattice point, chunk of rows
+// of the first undetected coordinate), as in the forward.  The undetected
+// neighbour terms make the cotangent of a pivot entry pull from the entry one
+// row below, so a chunk recomputes the target cotangents of two rows past its
+// own (bridge pivots: the rows its diagonal pivot needs; diagonal pivot: one
+// row), without storing them.
+// Abar records are folded per wavefront: each wave stages WREC records at a
+// time in its own LDS region and each lane accumulates fixed (i, l) pairs in
+// registers for the whole kernel; no workgroup barrier is involved.
 // ---------------------------------------------------------------------------
+constexpr int kWRec = 32;
+
+__device__ __forceinline__ void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// records: H rows NPD (detected write positions), X rows NR (NQ undetected
+// reads, NPD detected reads, pivot value).  Pair p = i * NR + l.
+template <typename R, int NPD, int NR, int PPL>
+__device__ __forceinline__ void wave_accum(cx<R>* recw, const cx<R>* h, const cx<R>* x, bool have,
+                                           cx<double>* acc) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long bal = __ballot(have);
+#pragma unroll 1
+  for (int half = 0; half < 64 / kWRec; ++half) {
+    const unsigned long long hm = (bal >> (half * kWRec)) & ((1ull << kWRec) - 1);
+    if (hm == 0ull) continue;   // uniform over the wave
+    if (lane / kWRec == half) {
+      const int e = lane % kWRec;
+#pragma unroll
+      for (int i = 0; i < NPD; ++i) recw[i * kWRec + e] = have ? h[i] : czero<R>();
+#pragma unroll
+      for (int l = 0; l < NR; ++l) recw[(NPD + l) * kWRec + e] = have ? x[l] : czero<R>();
+    }
+    wave_sync();
+#pragma unroll
+    for (int pp = 0; pp < PPL; ++pp) {
+      const int p = lane + 64 * pp;
+      if (p < NPD * NR) {
+        const int i = p / NR, l = p - (p / NR) * NR;
+        const cx<R>* H = recw + i * kWRec;
+        const cx<R>* X = recw + (NPD + l) * kWRec;
+        double ax = acc[pp].x, ay = acc[pp].y;
+#pragma unroll 8
+        for (int e = 0; e < kWRec; ++e) {
+          const cx<R> hv = H[e], xv = X[e];
+          ax += (double)xv.x * hv.x + (double)xv.y * hv.y;
+          ay += (double)xv.x * hv.y - (double)xv.y * hv.x;
+        }
+        acc[pp].x = ax;
+        acc[pp].y = ay;
+      }
+    }
+    wave_sync();
+  }
+}
+
 template <int MD, int NQ, typename R>
 __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
-                                                        double2* __restrict__ partial) {
+                                                        ChunkGeo G, double2* __restrict__ partial) {
   constexpr int NPD = 2 * MD;
-  constexpr int NW = NPD + NQ;          // positions: NQ undetected coordinates, then detected
-  constexpr int nq = NQ, npos = NW;
+  constexpr int NPOS = NQ + NPD;
+  constexpr int NR = NPOS + 1;
+  constexpr int NPAIR = NPD * NR;
+  constexpr int PPL = (NPAIR + 63) / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int B = P.B;
-  cx<R>* lpiv = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* qpull = lpiv + B;                          // nq x B
-  cx<R>* Hs = qpull + (size_t)nq * B;
-  cx<R>* Xs = Hs + (size_t)npos * kRS;
-  cx<double>* red = reinterpret_cast<cx<double>*>(Xs + (size_t)(npos + 1) * kRS);
-  R* sq = reinterpret_cast<R*>(red + kThreads);
+  const int B = P.B, R0 = G.R0, RC = G.RC;
+  const int nrow1 = (RC + 1) * R0, nrow2 = (RC + 2) * R0;
+  cx<R>* lfw = reinterpret_cast<cx<R>*>(smem_raw);   // forward pivot rows [k0-1, k1)
+  cx<R>* qv = lfw + nrow1;                           // NQ x rows [k0, k1+2)
+  cx<R>* gbv = qv + (size_t)NQ * nrow2;              // rows [k0, k1+1)
+  cx<R>* gpk = gbv + nrow1;                          // MD x rows [k0, k1+1)
+  cx<R>* g0a = gpk + (size_t)MD * nrow1;             // own rows
+  cx<R>* rec = g0a + (size_t)RC * R0;                // 4 waves x kWRec x (NPD + NR)
+  R* sq = reinterpret_cast<R*>(rec + (size_t)(kThreads / 64) * kWRec * (NPD + NR));
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables_v(P, spn, sq, isq);
   __syncthreads();
-  const PairMap pm = pair_map(npos);
-  cx<double> a0 = cmake<double>(0.0, 0.0), a1 = a0;
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWRec * (NPD + NR);
+  cx<double> acc[PPL];
+#pragma unroll
+  for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
   const int pnw = P.pnw;
-  const int nk = (B + kThreads - 1) / kThreads;
 
-  for (int r = blockIdx.x; r < nwork; r += gridDim.x) {
+  for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
+    const int r = w / G.nchunks, c = w - r * G.nchunks;
+    const int k0 = c * RC, k1 = min(G.C0, k0 + RC);
+    const int e_own0 = k0 * R0, e_own1 = k1 * R0;
     int m[MD], s[MD + 1], rdn[MD], rup[MD];
     unrank<MD>(spn, pnw, P.CD, S, r, m, s);
     neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
@@ -363,184 +428,219 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
     for (int d = MD - 1; d >= 0; --d)
       if (m[d] > 0) K0 = d;
     const size_t rB = (size_t)r * B;
-    cx<R>* gf0 = V.gcur[0] + rB;
-    for (int e = threadIdx.x; e < B; e += blockDim.x) st(gf0 + e, ld(V.d0cur + rB + e));
+    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) g0a[e - e_own0] = ld(V.d0cur + rB + e);
 
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
-      if (K > K0 || m[K] > P.CD[K] - 2) continue;      // uniform over the workgroup
-      const cx<R>* fpiv = V.fcur[fam_f1k(K)] + rB;
-      for (int e = threadIdx.x; e < B; e += blockDim.x) lpiv[e] = ld(fpiv + e);
+      if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
+      {
+        const cx<R>* f = V.fcur[fam_f1k(K)] + rB;
+        const int e0 = max(0, k0 - 1) * R0;
+        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(f + e);
+      }
       __syncthreads();
-      cx<R>* gpk = V.gcur[fam_f1k(K)] + rB;
+      const int eq1 = min(G.C0, k1 + 2) * R0, eb1 = min(G.C0, k1 + 1) * R0;
       const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
-      for (int k = 0; k < nk; ++k) {
-        const int e = threadIdx.x + k * kThreads;
-        const bool live = e < B;
-        cx<R> h[NW], x[NW + 1];
+      for (int base = e_own0; base < eq1; base += blockDim.x) {
+        const int e = base + threadIdx.x;
+        const bool live = e < eq1, own = e < e_own1;
+        cx<R> h[NPD], x[NR];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) h[i] = czero<R>();
+        for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
 #pragma unroll
-        for (int l = 0; l <= NW; ++l) x[l] = czero<R>();
+        for (int l = 0; l < NR; ++l) x[l] = czero<R>();
         if (live) {
-          int kap[kMaxUq];
+          int kap[NQ];
           int rem = e;
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q) {
-            kap[q] = q < nq ? rem / P.ustride[q] : 0;
-            rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+          for (int q = 0; q < NQ; ++q) {
+            kap[q] = rem / P.ustride[q];
+            rem -= kap[q] * P.ustride[q];
           }
-          // target cotangents (internal positions nq + detected index)
-          h[nq + 2 * K + 1] = cscale(ld(V.gf0nxt + (size_t)rup[K] * B + e), isq[m[K] + 1]);
-          if (m[K] <= P.CD[K] - 3) h[nq + 2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + rB + e), isq[m[K] + 2]);
+          h[2 * K + 1] = cscale(ld(V.gf0nxt + (size_t)rup[K] * B + e), isq[m[K] + 1]);
+          if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + rB + e), isq[m[K] + 2]);
 #pragma unroll
           for (int j = K + 1; j < MD; ++j) {
             if (m[j] <= P.CD[j] - 2) {
-              h[nq + 2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + rB + e), isq[m[j] + 1]);
-              h[nq + 2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + rB + e), isq[m[j] + 1]);
-            }
-          }
-          // forward reads
-          x[nq + 2 * K] = cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]);
-          if (m[K] > 0) x[nq + 2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]);
-#pragma unroll
-          for (int j = K + 1; j < MD; ++j) {
-            if (m[j] > 0) {
-              x[nq + 2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-              x[nq + 2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+              h[2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + rB + e), isq[m[j] + 1]);
+              h[2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + rB + e), isq[m[j] + 1]);
             }
           }
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q)
-            if (q < nq && kap[q] > 0) x[q] = cscale(lpiv[e - P.ustride[q]], sq[kap[q]]);
-          x[npos] = lpiv[e];
-          // adjoint of the detected reads
-#pragma unroll
-          for (int l = 2 * K; l < NPD; ++l) {
+          for (int q = 0; q < NQ; ++q) {
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + nq + l), h[nq + i]);
-            const int j = l >> 1;
-            if (l == 2 * K) {
-              st(gf0 + e, cadd(ld(gf0 + e), cscale(u, sq[m[K] + 1])));
-            } else if (l == 2 * K + 1) {
-              if (m[K] > 0) st(V.gprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e, cscale(u, sq[m[K]]));
-            } else if (m[j] > 0) {
-              st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e,
-                 cscale(u, sq[m[j]]));
-            }
+            for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + q), h[i]);
+            qv[(size_t)q * nrow2 + (e - e_own0)] = u;
           }
-          // adjoint of the pivot: b term now, undetected neighbours after the barrier
-          cx<R> gp = czero<R>();
+          if (e < eb1) {
+            cx<R> gb = czero<R>();
 #pragma unroll
-          for (int i = 2 * K; i < NPD; ++i) cfma_conj(gp, ld(bi + nq + i), h[nq + i]);
-          st(gpk + e, has_diag_reader ? cadd(ld(gpk + e), gp) : gp);
+            for (int i = 2 * K; i < NPD; ++i) cfma_conj(gb, ld(bi + NQ + i), h[i]);
+            gbv[e - e_own0] = gb;
+          }
+          if (own) {
+            const int lf = e - (k0 - 1) * R0;
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q) {
-            if (q < nq) {
+            for (int q = 0; q < NQ; ++q)
+              if (kap[q] > 0) x[q] = cscale(lfw[lf - P.ustride[q]], sq[kap[q]]);
+            x[NPOS] = lfw[lf];
+            x[NQ + 2 * K] = cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]);
+            if (m[K] > 0)
+              x[NQ + 2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]);
+#pragma unroll
+            for (int j = K + 1; j < MD; ++j) {
+              if (m[j] > 0) {
+                x[NQ + 2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+                x[NQ + 2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+              }
+            }
+#pragma unroll
+            for (int l = 2 * K; l < NPD; ++l) {
+              const int j = l >> 1;
+              if (l != 2 * K && m[j] == 0) continue;
               cx<R> u = czero<R>();
 #pragma unroll
-              for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + q), h[nq + i]);
-              qpull[(size_t)q * B + e] = u;
+              for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + NQ + l), h[i]);
+              if (l == 2 * K) {
+                g0a[e - e_own0] = cadd(g0a[e - e_own0], cscale(u, sq[m[K] + 1]));
+              } else if (l == 2 * K + 1) {
+                st(V.gprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e, cscale(u, sq[m[K]]));
+              } else {
+                st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e,
+                   cscale(u, sq[m[j]]));
+              }
             }
           }
         }
-        stage_accumulate<R, NW>(pm, npos, h, x, Hs, Xs, a0, a1);
+        wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
       }
-      // pull: gbar_p[e] += sqrt(kappa_q + 1) * qpull_q[e + s_q]
-      for (int e = threadIdx.x; e < B; e += blockDim.x) {
+      __syncthreads();
+      // total cotangent of the bridge pivot block F1k(K)(m), rows [k0, k1+1)
+      for (int e = e_own0 + threadIdx.x; e < eb1; e += blockDim.x) {
         int rem = e;
-        cx<R> acc = ld(gpk + e);
+        const int le = e - e_own0;
+        cx<R> v = gbv[le];
+        if (has_diag_reader) v = cadd(v, ld(V.gcur[fam_f1k(K)] + rB + e));
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q) {
-          if (q < nq) {
-            const int kq = rem / P.ustride[q];
-            rem -= kq * P.ustride[q];
-            if (kq + 1 < P.udims[q]) acc = cadd(acc, cscale(qpull[(size_t)q * B + e + P.ustride[q]], sq[kq + 1]));
-          }
+        for (int q = 0; q < NQ; ++q) {
+          const int kq = rem / P.ustride[q];
+          rem -= kq * P.ustride[q];
+          if (kq + 1 < P.udims[q]) v = cadd(v, cscale(qv[(size_t)q * nrow2 + le + P.ustride[q]], sq[kq + 1]));
         }
-        st(gpk + e, acc);
+        gpk[(size_t)K * nrow1 + le] = v;
       }
       __syncthreads();
     }
 
     if (m[0] <= P.CD[0] - 2) {
-      const cx<R>* fpiv = V.fcur[0] + rB;
-      for (int e = threadIdx.x; e < B; e += blockDim.x) lpiv[e] = ld(fpiv + e);
+      {
+        const cx<R>* f = V.fcur[0] + rB;
+        const int e0 = max(0, k0 - 1) * R0;
+        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(f + e);
+      }
       __syncthreads();
-      for (int k = 0; k < nk; ++k) {
-        const int e = threadIdx.x + k * kThreads;
-        const bool live = e < B;
-        cx<R> h[NW], x[NW + 1];
+      const int eq1 = min(G.C0, k1 + 1) * R0;
+      for (int base = e_own0; base < eq1; base += blockDim.x) {
+        const int e = base + threadIdx.x;
+        const bool live = e < eq1, own = e < e_own1;
+        cx<R> h[NPD], x[NR];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) h[i] = czero<R>();
+        for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
 #pragma unroll
-        for (int l = 0; l <= NW; ++l) x[l] = czero<R>();
+        for (int l = 0; l < NR; ++l) x[l] = czero<R>();
         if (live) {
-          int kap[kMaxUq];
+          int kap[NQ];
           int rem = e;
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q) {
-            kap[q] = q < nq ? rem / P.ustride[q] : 0;
-            rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+          for (int q = 0; q < NQ; ++q) {
+            kap[q] = rem / P.ustride[q];
+            rem -= kap[q] * P.ustride[q];
           }
+          const int le = e - e_own0;
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
-            if (j == 0 || m[j] <= P.CD[j] - 2)
-              h[nq + 2 * j] = cscale(ld(V.gcur[fam_f1k(j)] + rB + e), isq[m[j] + 1]);
-            const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-            if (okb) h[nq + 2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + rB + e), isq[m[j] + 1]);
-            if (m[j] > 0) {
-              x[nq + 2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-              x[nq + 2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            if (j == 0 || m[j] <= P.CD[j] - 2) {
+              const bool bridge = j <= K0 && m[j] <= P.CD[j] - 2;
+              const cx<R> gt = bridge ? gpk[(size_t)j * nrow1 + le] : ld(V.gcur[fam_f1k(j)] + rB + e);
+              h[2 * j] = cscale(gt, isq[m[j] + 1]);
             }
+            const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
+            if (okb) h[2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + rB + e), isq[m[j] + 1]);
           }
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q)
-            if (q < nq && kap[q] > 0) x[q] = cscale(lpiv[e - P.ustride[q]], sq[kap[q]]);
-          x[npos] = lpiv[e];
-#pragma unroll
-          for (int l = 0; l < NPD; ++l) {
-            const int j = l >> 1;
-            if (m[j] == 0) continue;
+          for (int q = 0; q < NQ; ++q) {
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + nq + l), h[nq + i]);
-            st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + (size_t)rdn[j] * B + e, cscale(u, sq[m[j]]));
+            for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + q), h[i]);
+            qv[(size_t)q * nrow2 + le] = u;
           }
-          cx<R> gp = czero<R>();
+          if (own) {
+            const int lf = e - (k0 - 1) * R0;
 #pragma unroll
-          for (int i = 0; i < NPD; ++i) cfma_conj(gp, ld(bi + nq + i), h[nq + i]);
-          st(gf0 + e, cadd(ld(gf0 + e), gp));
+            for (int q = 0; q < NQ; ++q)
+              if (kap[q] > 0) x[q] = cscale(lfw[lf - P.ustride[q]], sq[kap[q]]);
+            x[NPOS] = lfw[lf];
 #pragma unroll
-          for (int q = 0; q < kMaxUq; ++q) {
-            if (q < nq) {
+            for (int j = 0; j < MD; ++j) {
+              if (m[j] > 0) {
+                x[NQ + 2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+                x[NQ + 2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+              }
+            }
+#pragma unroll
+            for (int l = 0; l < NPD; ++l) {
+              const int j = l >> 1;
+              if (m[j] == 0) continue;
               cx<R> u = czero<R>();
 #pragma unroll
-              for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (nq + i) * npos + q), h[nq + i]);
-              qpull[(size_t)q * B + e] = u;
+              for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + NQ + l), h[i]);
+              st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + (size_t)rdn[j] * B + e, cscale(u, sq[m[j]]));
             }
-          }
-        }
-        stage_accumulate<R, NW>(pm, npos, h, x, Hs, Xs, a0, a1);
-      }
-      for (int e = threadIdx.x; e < B; e += blockDim.x) {
-        int rem = e;
-        cx<R> acc = ld(gf0 + e);
+            cx<R> gb = czero<R>();
 #pragma unroll
-        for (int q = 0; q < kMaxUq; ++q) {
-          if (q < nq) {
-            const int kq = rem / P.ustride[q];
-            rem -= kq * P.ustride[q];
-            if (kq + 1 < P.udims[q]) acc = cadd(acc, cscale(qpull[(size_t)q * B + e + P.ustride[q]], sq[kq + 1]));
+            for (int i = 0; i < NPD; ++i) cfma_conj(gb, ld(bi + NQ + i), h[i]);
+            g0a[le] = cadd(g0a[le], gb);
           }
         }
-        st(gf0 + e, acc);
+        wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
       }
       __syncthreads();
+      for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) {
+        int rem = e;
+        const int le = e - e_own0;
+        cx<R> v = g0a[le];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int kq = rem / P.ustride[q];
+          rem -= kq * P.ustride[q];
+          if (kq + 1 < P.udims[q]) v = cadd(v, cscale(qv[(size_t)q * nrow2 + le + P.ustride[q]], sq[kq + 1]));
+        }
+        g0a[le] = v;
+      }
     }
+    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) st(V.gcur[0] + rB + e, g0a[e - e_own0]);
+    __syncthreads();
   }
-  flush_pairs(pm, partial + (size_t)blockIdx.x * pm.P, a0, a1, red);
+  // fold the per-lane pair sums over the waves (fixed order) into this block's slot
+  cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
+  __syncthreads();
+#pragma unroll
+  for (int pp = 0; pp < PPL; ++pp) red[(size_t)(threadIdx.x >> 6) * 64 * PPL + pp * 64 + (threadIdx.x & 63)] = acc[pp];
+  __syncthreads();
+  double2* slot = partial + (size_t)blockIdx.x * (NPOS * NR);
+  for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
+    const int pp = p / 64, lane = p - pp * 64;
+    double sx = 0.0, sy = 0.0;
+    for (int wv = 0; wv < kThreads / 64; ++wv) {
+      sx += red[(size_t)wv * 64 * PPL + pp * 64 + lane].x;
+      sy += red[(size_t)wv * 64 * PPL + pp * 64 + lane].y;
+    }
+    const int i = p / NR, l = p - (p / NR) * NR;
+    const int q = (NQ + i) * NR + l;
+    const double2 v = slot[q];
+    slot[q] = make_double2(v.x + sx, v.y + sy);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -709,6 +809,17 @@ __global__ __launch_bounds__(kThreads) void k_vjp_final(const double2* __restric
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
+static ChunkGeo chunk_geo_v(const Plan& Pl) {
+  ChunkGeo G;
+  G.C0 = Pl.udims[0];
+  G.R0 = Pl.B / G.C0;
+  int rc = std::max(1, kThreads / G.R0 - 2);
+  rc = std::min(rc, G.C0);
+  G.nchunks = (G.C0 + rc - 1) / rc;
+  G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
+  return G;
+}
+
 template <typename R>
 static const cx<R>* fptr(const Plan& Pl, const char* base, size_t off, int g, int S) {
   if (S < 0 || off == 0) return nullptr;
@@ -808,9 +919,12 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       }
 #undef FD_VJP_POINT
     } else {
-      const size_t shm = (size_t)(1 + Pl.nq) * Pl.B * sizeof(cx<R>) + (size_t)(2 * Pl.npos + 1) * kRS * sizeof(cx<R>) +
-                         kThreads * sizeof(cx<double>) + tab;
-      const int grid = std::min(nwork, kPartialSlots - 1);
+      const ChunkGeo G = chunk_geo_v(Pl);
+      const int NPD = 2 * MD, NR = Pl.npos + 1;
+      const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
+                          (size_t)G.RC * G.R0 + (size_t)(kThreads / 64) * kWRec * (NPD + NR);
+      const size_t shm = std::max(ents * sizeof(cx<R>), (size_t)kThreads * 4 * sizeof(cx<double>) + 64) + tab;
+      const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \
     if (Pl.nq == 2) {                                                                                           \
@@ -818,13 +932,13 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R>),                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
       hipLaunchKernelGGL((k_vjp_block<MDV, 2, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
-                         nwork, partial);                                                                       \
+                         nwork, G, partial);                                                                    \
     } else {                                                                                                    \
       if (shm > 65536)                                                                                          \
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R>),                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
       hipLaunchKernelGGL((k_vjp_block<MDV, 4, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
-                         nwork, partial);                                                                       \
+                         nwork, G, partial);                                                                    \
     }                                                                                                           \
     break;
       switch (MD) {
