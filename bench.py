@@ -101,6 +101,8 @@ def main():
         F.fock_diag_fwd(plan, A, b, c, rho, ws, saved)
         F.fock_diag_vjp(plan, A, b, c, saved, g, dA, db, dc, ws)
 
+    # the timed steps replay one captured graph per sweep (buffers are fixed)
+    F.fd_plan_use_graphs(plan, True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -117,7 +119,8 @@ def main():
     out_elems = plan.query(F.FD_Q_OUT_ELEMS)
     value = out_elems * args.steps / sec
 
-    # same steps again with HIP events around every level-sweep launch
+    # same steps again, launched kernel by kernel with HIP events around every
+    # level-sweep launch (graph replay is off while timing is on)
     F.fd_plan_timing(plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_VJP_LEVEL))
     torch.cuda.synchronize()
     t2 = time.perf_counter()

@@ -170,6 +170,16 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
                               const void* const* b, const void* const* c, void* const* rho,
                               void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
 
+/* Graph replay (for callers that reuse their buffers): with enable != 0, the
+ * first fock_diag_fwd / fock_diag_vjp call with a given set of pointers is
+ * captured once into a HIP graph (on a private capture stream, nothing runs
+ * during capture) and every call with the same pointers launches the
+ * instantiated graph on the caller's stream: one launch instead of one per
+ * photon-number level.  Contents of the buffers may change between calls.
+ * At most 8 graphs are kept per plan (least recently used dropped); disabling
+ * drops them.  Ignored while per-kernel timing is enabled. */
+fd_status fd_plan_use_graphs(fd_plan p, int enable);
+
 /* Per-kernel timing for reports: with bit k of kind_mask set, every launch of
  * kernel kind k made through this plan is bracketed by two HIP events on its
  * stream (fd_plan_timing also drops earlier records).  fd_plan_kernel_times

@@ -1,5 +1,6 @@
 // extern "C" entry points declared in include/fockdiag.h: argument checks on
 // the host, workspace carving, schedule choice, then the kernel launchers.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -49,6 +50,67 @@ fd_status decide_b_zero(const fd::Plan& P, const void* b, hipStream_t s, bool* b
   return FD_OK;
 }
 
+constexpr size_t kGraphCache = 8;
+
+// Runs `body(stream)` directly, or -- when the plan replays graphs and no
+// per-kernel timing is on -- captures it once per pointer set into a graph
+// (on a private capture stream) and launches the instantiated graph on `s`.
+template <typename F>
+hipError_t run_maybe_graph(fd::Plan& P, int kind, bool odd, std::initializer_list<const void*> ptrs, hipStream_t s,
+                           F body) {
+  if (!P.use_graphs || P.timing.mask != 0) return body(s);
+  const void* key[12] = {};
+  int n = 0;
+  for (const void* q : ptrs) key[n++] = q;
+  for (fd::GraphEntry& g : P.graphs) {
+    if (g.kind == kind && g.odd == odd && std::equal(key, key + 12, g.ptr)) {
+      g.last_use = ++P.graph_clock;
+      return hipGraphLaunch(g.exec, s);
+    }
+  }
+  hipError_t e;
+  if (!P.capture_stream && (e = hipStreamCreateWithFlags(&P.capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  if ((e = hipStreamBeginCapture(P.capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipError_t eb = body(P.capture_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(P.capture_stream, &graph);
+  if (eb != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return eb;
+  }
+  if (e != hipSuccess) return e;
+  hipGraphExec_t exec = nullptr;
+  if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return e;
+  }
+  if (P.graphs.size() >= kGraphCache) {
+    auto it = std::min_element(P.graphs.begin(), P.graphs.end(),
+                               [](const fd::GraphEntry& a, const fd::GraphEntry& b) { return a.last_use < b.last_use; });
+    (void)hipGraphExecDestroy(it->exec);
+    (void)hipGraphDestroy(it->graph);
+    P.graphs.erase(it);
+  }
+  fd::GraphEntry g;
+  g.kind = kind;
+  g.odd = odd;
+  std::copy(key, key + 12, g.ptr);
+  g.graph = graph;
+  g.exec = exec;
+  g.last_use = ++P.graph_clock;
+  P.graphs.push_back(g);
+  return hipGraphLaunch(exec, s);
+}
+
+void drop_graphs(fd::Plan& P) {
+  for (fd::GraphEntry& g : P.graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  P.graphs.clear();
+}
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 fd_status check_ptrs(const fd::Plan& P, std::initializer_list<const void*> ps) {
@@ -93,6 +155,8 @@ fd_status fd_plan_destroy(fd_plan p) {
     (void)hipFree(P.d_woff);
     (void)hipSetDevice(cur);
   }
+  drop_graphs(P);
+  if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
   for (auto& v : P.timing.rec)
     for (auto& pr : v) {
       (void)hipEventDestroy(pr.first);
@@ -167,7 +231,9 @@ fd_status fock_diag_fwd(fd_plan p, const void* A, const void* b, const void* c, 
   }
   std::string err;
   if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
-  hipError_t e = fd::run_forward(P, odd, A, b, c, rho, workspace, saved, stream);
+  hipError_t e = run_maybe_graph(P, 0, odd, {A, b, c, rho, workspace, saved}, stream, [&](hipStream_t st) {
+    return fd::run_forward(P, odd, A, b, c, rho, workspace, saved, st);
+  });
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return ok();
 }
@@ -200,6 +266,7 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
   const void* sv = saved;
   std::string err;
   if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  void* region = nullptr;
   if (saved) {
     if (saved_bytes < sneed) return fail(FD_ERR_WORKSPACE, "saved buffer too small");
     if (ws_bytes < vneed) return fail(FD_ERR_WORKSPACE, "workspace too small");
@@ -207,12 +274,17 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
     // recompute the forward intermediates behind the reverse sweep's workspace
     const size_t off = (vneed + 255) & ~size_t(255);
     if (ws_bytes < off + sneed) return fail(FD_ERR_WORKSPACE, "workspace too small (saved == NULL)");
-    void* region = static_cast<char*>(workspace) + off;
-    hipError_t e = fd::run_forward(P, odd, A, b, c, nullptr, workspace, region, stream);
-    if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("forward recompute failed: ") + hipGetErrorString(e));
+    region = static_cast<char*>(workspace) + off;
     sv = region;
   }
-  hipError_t e = fd::run_vjp(P, odd, A, b, c, sv, drho, dA, db, dc, workspace, stream);
+  hipError_t e = run_maybe_graph(P, 1, odd, {A, b, c, saved, drho, dA, db, dc, workspace}, stream,
+                                 [&](hipStream_t st) {
+                                   if (region) {
+                                     hipError_t ef = fd::run_forward(P, odd, A, b, c, nullptr, workspace, region, st);
+                                     if (ef != hipSuccess) return ef;
+                                   }
+                                   return fd::run_vjp(P, odd, A, b, c, sv, drho, dA, db, dc, workspace, st);
+                                 });
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return ok();
 }
@@ -226,6 +298,13 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
     fd_status s = fock_diag_fwd(plans[i], A[i], b[i], c[i], rho[i], workspace[i], ws_bytes[i], nullptr, 0, stream);
     if (s != FD_OK) return s;
   }
+  return ok();
+}
+
+fd_status fd_plan_use_graphs(fd_plan p, int enable) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  p->P.use_graphs = enable != 0;
+  if (!enable) drop_graphs(p->P);
   return ok();
 }
 

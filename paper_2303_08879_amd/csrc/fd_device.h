@@ -77,6 +77,16 @@ struct LevelPtrs {
   cx<R>* f0nxt;
 };
 
+// Orders LDS traffic between the lanes of one wavefront: LDS operations of a
+// wavefront execute in order, so only compiler reordering has to be stopped.
+__device__ __forceinline__ void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Split of a node's undetected block into chunks of whole rows of the first
 // undetected coordinate (rows of R0 = B / C0 entries).
 struct ChunkGeo {

@@ -93,6 +93,16 @@ struct Timing {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[KK_COUNT];
 };
 
+// Cached instantiated graph of one whole sweep, keyed by every pointer it uses.
+struct GraphEntry {
+  int kind = 0;                      // 0 forward, 1 reverse
+  bool odd = false;
+  const void* ptr[12] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
 struct Plan {
   // caller's view
   int M = 0;
@@ -125,6 +135,11 @@ struct Plan {
   int* d_elist = nullptr;
   int* d_woff = nullptr;
   mutable Timing timing;
+  // hipGraph replay of whole sweeps (opt-in)
+  bool use_graphs = false;
+  std::vector<GraphEntry> graphs;
+  hipStream_t capture_stream = nullptr;
+  uint64_t graph_clock = 0;
   bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
 };
 
@@ -147,7 +162,6 @@ struct VjpLayout {
   size_t g0 = 0;                     // drho in level-major node order
   std::vector<size_t> gfam;          // cotangent rings per family (F0 too)
   size_t partial = 0;                // kPartialSlots x (npos x (npos+1)) complex (double)
-  size_t ufin = 0;                   // B entries: reverse of the undetected block fill
   size_t total = 0;
 };
 size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel

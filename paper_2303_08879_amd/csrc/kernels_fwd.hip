@@ -62,37 +62,48 @@ __global__ void k_prep(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
 // ---------------------------------------------------------------------------
 // Step 1 of Algorithm 2: the whole undetected block at zero detections.
 // Entry kappa != 0 is pulled from its parent kappa - 1_q, q = first non-zero
-// coordinate, by Eq. recrel restricted to the undetected positions.  The
-// entries are visited by weight (host-built list), one barrier per weight.
+// coordinate, by Eq. recrel restricted to the undetected positions.  One
+// wavefront, the block in LDS, entries visited by weight (host-built list).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_ufill(DevPlan P, const cx<R>* __restrict__ Ai,
-                                                    const cx<R>* __restrict__ bi, cx<R>* G,
-                                                    const int* __restrict__ elist, const int* __restrict__ woff,
-                                                    int wmax) {
-  const int nq = P.nq, npos = P.npos;
+__global__ __launch_bounds__(64) void k_ufill(DevPlan P, const cx<R>* __restrict__ Ai,
+                                              const cx<R>* __restrict__ bi, cx<R>* G,
+                                              const int* __restrict__ elist, const int* __restrict__ woff,
+                                              int wmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* g = reinterpret_cast<cx<R>*>(smem_raw);
+  const int nq = P.nq, npos = P.npos, B = P.B;
+  const int lane = threadIdx.x;
+  if (lane == 0) g[0] = ld(G);   // c, written by the prep kernel
+  wave_sync();
   for (int w = 1; w <= wmax; ++w) {
-    for (int t = woff[w] + threadIdx.x; t < woff[w + 1]; t += blockDim.x) {
+    for (int t = woff[w] + lane; t < woff[w + 1]; t += 64) {
       const int e = elist[t];
       int kap[kMaxUq];
       int rem = e;
-      for (int q = 0; q < nq; ++q) {
-        kap[q] = rem / P.ustride[q];
-        rem -= kap[q] * P.ustride[q];
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        kap[q] = q < nq ? rem / P.ustride[q] : 0;
+        rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
       }
-      int qf = 0;
-      while (kap[qf] == 0) ++qf;
+      int qf = nq;
+#pragma unroll
+      for (int q = kMaxUq - 1; q >= 0; --q)
+        if (q < nq && kap[q] > 0) qf = q;
       const int pe = e - P.ustride[qf];
       cx<R> acc = czero<R>();
-      cfma(acc, ld(bi + qf), ld(G + pe));
-      for (int q = 0; q < nq; ++q) {
+      cfma(acc, ld(bi + qf), g[pe]);
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        if (q >= nq) continue;
         const int pq = kap[q] - (q == qf ? 1 : 0);
-        if (pq > 0) cfma(acc, ld(Ai + qf * npos + q), cscale(ld(G + pe - P.ustride[q]), sqrt(R(pq))));
+        if (pq > 0) cfma(acc, ld(Ai + qf * npos + q), cscale(g[pe - P.ustride[q]], sqrt(R(pq))));
       }
-      st(G + e, cscale(acc, R(1) / sqrt(R(kap[qf]))));
+      g[e] = cscale(acc, R(1) / sqrt(R(kap[qf])));
     }
-    __syncthreads();
+    wave_sync();
   }
+  for (int e = lane; e < B; e += 64) st(G + e, g[e]);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +575,11 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
     KTimer kt(Pl, KK_UFILL, st);
-    hipLaunchKernelGGL((k_ufill<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff,
+    const size_t shm = (size_t)Pl.B * sizeof(cx<R>);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ufill<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((k_ufill<R>), dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff,
                        Pl.wmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

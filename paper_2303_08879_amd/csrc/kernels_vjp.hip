@@ -338,14 +338,6 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 // ---------------------------------------------------------------------------
 constexpr int kWRec = 32;
 
-__device__ __forceinline__ void wave_sync() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // records: H rows NPD (detected write positions), X rows NR (NQ undetected
 // reads, NPD detected reads, pivot value).  Pair p = i * NR + l.
 template <typename R, int NPD, int NR, int PPL>
@@ -645,25 +637,32 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
 
 // ---------------------------------------------------------------------------
 // Reverse of step 1 of Algorithm 2 (undetected block at zero detections), by
-// weight from the top: an entry's cotangent gathers from the targets that
-// used it as pivot (x + 1_q with first non-zero coordinate q) or as a read
+// weight from the top, one wavefront with the block's forward values and
+// cotangents in LDS: an entry's cotangent gathers from the targets that used
+// it as pivot (x + 1_q with first non-zero coordinate q) or as a read
 // (x + 1_q2 + 1_q with parent x + 1_q2, first non-zero coordinate q).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_ufill_vjp(DevPlan P, const cx<R>* __restrict__ Ai,
-                                                        const cx<R>* __restrict__ bi, const cx<R>* __restrict__ G,
-                                                        const cx<R>* __restrict__ gin, cx<R>* gfin,
-                                                        const int* __restrict__ elist, const int* __restrict__ woff,
-                                                        int wmax, double2* slot, cx<R>* cbar) {
-  const int nq = P.nq, npos = P.npos;
+__global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __restrict__ Ai,
+                                                  const cx<R>* __restrict__ bi, const cx<R>* __restrict__ G,
+                                                  const cx<R>* __restrict__ gin, const int* __restrict__ elist,
+                                                  const int* __restrict__ woff, int wmax, double2* slot,
+                                                  cx<R>* cbar) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nq = P.nq, npos = P.npos, B = P.B;
   const int NR = npos + 1;
+  const int lane = threadIdx.x;
+  cx<R>* Gl = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* gf = Gl + B;
+  for (int e = lane; e < B; e += 64) Gl[e] = ld(G + e);
+  wave_sync();
   cx<double> ab[kMaxUq][kMaxUq + 1];
 #pragma unroll
   for (int a = 0; a < kMaxUq; ++a)
 #pragma unroll
     for (int c = 0; c <= kMaxUq; ++c) ab[a][c] = cmake<double>(0.0, 0.0);
   for (int w = wmax; w >= 0; --w) {
-    for (int t = woff[w] + threadIdx.x; t < woff[w + 1]; t += blockDim.x) {
+    for (int t = woff[w] + lane; t < woff[w + 1]; t += 64) {
       const int e = elist[t];
       int x[kMaxUq];
       int rem = e;
@@ -681,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_ufill_vjp(DevPlan P, const cx<R>* 
       for (int q = 0; q < kMaxUq; ++q) {
         if (q >= nq || q > first0) continue;
         if (x[q] + 1 < P.udims[q]) {
-          const cx<R> ht = cscale(ld(gfin + e + P.ustride[q]), R(1) / sqrt(R(x[q] + 1)));
+          const cx<R> ht = cscale(gf[e + P.ustride[q]], R(1) / sqrt(R(x[q] + 1)));
           cfma_conj(acc, ld(bi + q), ht);
         }
 #pragma unroll
@@ -690,20 +689,19 @@ __global__ __launch_bounds__(kThreads) void k_ufill_vjp(DevPlan P, const cx<R>* 
           const int p2 = x[q2] + 1;                  // parent coordinate along q2
           const int pq = x[q] + (q2 == q ? 1 : 0);   // parent coordinate along q
           if (p2 >= P.udims[q2] || pq + 1 >= P.udims[q]) continue;
-          const cx<R> ht = cscale(ld(gfin + e + P.ustride[q2] + P.ustride[q]), R(1) / sqrt(R(pq + 1)));
+          const cx<R> ht = cscale(gf[e + P.ustride[q2] + P.ustride[q]], R(1) / sqrt(R(pq + 1)));
           cx<R> u = czero<R>();
           cfma_conj(u, ld(Ai + q * npos + q2), ht);
           acc = cadd(acc, cscale(u, sqrt(R(p2))));
         }
       }
-      st(gfin + e, acc);
+      gf[e] = acc;
       if (e > 0) {
         // this entry as a target: parent x - 1_first0, direction first0
         const int qf = first0;
         const int pe = e - P.ustride[qf];
-        const R s = R(1) / sqrt(R(x[qf]));
-        const cx<R> h = cscale(acc, s);
-        const cx<R> gp = ld(G + pe);
+        const cx<R> h = cscale(acc, R(1) / sqrt(R(x[qf])));
+        const cx<R> gp = Gl[pe];
 #pragma unroll
         for (int a = 0; a < kMaxUq; ++a) {
           if (a != qf) continue;
@@ -714,40 +712,35 @@ __global__ __launch_bounds__(kThreads) void k_ufill_vjp(DevPlan P, const cx<R>* 
             if (q2 >= nq) continue;
             const int pq2 = x[q2] - (q2 == qf ? 1 : 0);
             if (pq2 <= 0) continue;
-            const cx<R> g2 = cscale(ld(G + pe - P.ustride[q2]), sqrt(R(pq2)));
+            const cx<R> g2 = cscale(Gl[pe - P.ustride[q2]], sqrt(R(pq2)));
             ab[a][q2].x += (double)g2.x * h.x + (double)g2.y * h.y;
             ab[a][q2].y += (double)g2.x * h.y - (double)g2.y * h.x;
           }
         }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
-  // workgroup reduction of ab (fixed order) into the slot
-  __shared__ cx<double> red[kThreads];
+  // butterfly sums over the wavefront (fixed order), lane 0 adds to the slot
 #pragma unroll
   for (int a = 0; a < kMaxUq; ++a) {
 #pragma unroll
     for (int c = 0; c <= kMaxUq; ++c) {
       if (a >= nq || (c >= nq && c != kMaxUq)) continue;   // uniform
-      red[threadIdx.x] = ab[a][c];
-      __syncthreads();
-      for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-          red[threadIdx.x].x += red[threadIdx.x + w].x;
-          red[threadIdx.x].y += red[threadIdx.x + w].y;
-        }
-        __syncthreads();
+      double vx = ab[a][c].x, vy = ab[a][c].y;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        vx += __shfl_xor(vx, off, 64);
+        vy += __shfl_xor(vy, off, 64);
       }
-      if (threadIdx.x == 0) {
+      if (lane == 0) {
         const int p = a * NR + (c == kMaxUq ? npos : c);
         double2 v = slot[p];
-        slot[p] = make_double2(v.x + red[0].x, v.y + red[0].y);
+        slot[p] = make_double2(v.x + vx, v.y + vy);
       }
-      __syncthreads();
     }
   }
-  if (threadIdx.x == 0) st(cbar, ld(gfin));
+  if (lane == 0) st(cbar, gf[0]);
 }
 
 // Final: sum the partial slots in order, symmetrise Abar, scatter to the
@@ -961,10 +954,13 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   const cx<R>* gseed = MD > 0 ? gptr<R>(Pl, ws, V.gfam[0], 0, 0) : g0;
   const cx<R>* cbar_src = gseed;
   if (Pl.B > 1) {
-    cx<R>* gfin = reinterpret_cast<cx<R>*>(ws + V.ufin);
     const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + Ls.f0);
     KTimer kt(Pl, KK_UFILL_VJP, st);
-    hipLaunchKernelGGL((k_ufill_vjp<R>), dim3(1), dim3(kThreads), 0, st, P, Ai, bi, G0blk, gseed, gfin, Pl.d_elist,
+    const size_t shm = 2 * (size_t)Pl.B * sizeof(cx<R>);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ufill_vjp<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL((k_ufill_vjp<R>), dim3(1), dim3(64), shm, st, P, Ai, bi, G0blk, gseed, Pl.d_elist,
                        Pl.d_woff, Pl.wmax, partial + (size_t)(kPartialSlots - 1) * PP, cb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cbar_src = cb;

@@ -281,8 +281,6 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   }
   L.partial = off;
   off = align256(off + (size_t)kPartialSlots * P.npos * (P.npos + 1) * 16);
-  L.ufin = off;
-  off = align256(off + (size_t)P.B * eb);
   L.total = off;
   return L;
 }

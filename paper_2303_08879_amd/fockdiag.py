@@ -24,7 +24,7 @@ FD_B_AUTO, FD_B_ZERO, FD_B_GENERAL = 0, 1, 2
 EXPORTS = [
     "fd_plan_create", "fd_plan_destroy", "fd_plan_workspace", "fd_plan_query", "fock_diag_fwd",
     "fock_diag_vjp", "detection_probs", "fock_diag_fwd_batch", "fd_last_error", "fd_device_status",
-    "fd_plan_timing", "fd_plan_kernel_times",
+    "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO) = range(9)
@@ -61,6 +61,7 @@ def lib():
     L.fd_last_error.restype = ctypes.c_char_p
     L.fd_device_status.argtypes = [vp, vp]
     L.fd_plan_timing.argtypes = [vp, u32]
+    L.fd_plan_use_graphs.argtypes = [vp, i32]
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         if name != "fd_last_error":
@@ -155,6 +156,10 @@ def fock_diag_fwd_batch(plans, As, bs, cs, rhos, workspaces, stream=None):
 
 def fd_device_status(plan, stream=None):
     _check(lib().fd_device_status(plan.handle, _stream(stream)))
+
+
+def fd_plan_use_graphs(plan, enable=True):
+    _check(lib().fd_plan_use_graphs(plan.handle, int(bool(enable))))
 
 
 def fd_plan_timing(plan, kind_mask):
