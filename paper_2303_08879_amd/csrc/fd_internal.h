@@ -45,8 +45,9 @@ constexpr int kMaxPos = kMaxUq + 2 * kMaxD;   // positions of the active index
 constexpr int kMaxFam = 1 + 3 * kMaxD + kMaxD * (kMaxD - 1);
 constexpr int kMaxSmax = kMaxD * (kMaxCut - 1);
 constexpr int kPnMax = (kMaxD + 1) * (kMaxSmax + 3);
-constexpr int kPartialSlots = 1024;      // deterministic VJP partial accumulators
+constexpr int kPartialSlots = 4096;      // deterministic VJP partial accumulators
 constexpr int kThreads = 256;
+constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
 
 enum FamType { F_F0 = 0, F_F1K, F_F1B, F_F2, F_1010, F_1001 };
 

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
 // [k0-1, k1), for every bridge K applied at m.
 // ---------------------------------------------------------------------------
 template <int MD, int NQ, typename R>
-__global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
+__global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         ChunkGeo G) {
   constexpr int NPD = 2 * MD;
@@ -249,10 +249,13 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> 
   const int B = P.B, R0 = G.R0;
   cx<R>* lf0 = reinterpret_cast<cx<R>*>(smem_raw);             // (RC + 2) rows
   cx<R>* lpk = lf0 + (size_t)(G.RC + 2) * R0;                  // MD x (RC + 1) rows
-  R* sq = reinterpret_cast<R*>(lpk + (size_t)MD * (G.RC + 1) * R0);
+  cx<R>* sA = lpk + (size_t)MD * (G.RC + 1) * R0;      // A (NPOS x NPOS) then b (NPOS)
+  const cx<R>* sb = sA + NPOS * NPOS;
+  R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables(P, spn, sq, isq);
+  for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
   __syncthreads();
   const int pnw = P.pnw;
   const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
@@ -315,11 +318,11 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> 
             if (!(ok && own) && !bridge) continue;
             const int row = (NQ + i) * NPOS;
             cx<R> acc = czero<R>();
-            cfma(acc, ld(bi + NQ + i), piv);
+            cfma(acc, sb[NQ + i], piv);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) cfma(acc, ld(Ai + row + q), un[q]);
+            for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
 #pragma unroll
-            for (int l = 0; l < NPD; ++l) cfma(acc, ld(Ai + row + NQ + l), x[l]);
+            for (int l = 0; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
             acc = cscale(acc, isq[m[j] + 1]);
             if (ok && own) st(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)] + rB + e, acc);
             if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
@@ -381,11 +384,11 @@ __global__ __launch_bounds__(kThreads) void k_fwd_block(DevPlan P, LevelPtrs<R> 
           if (!ok) continue;
           const int row = (NQ + i) * NPOS;
           cx<R> acc = czero<R>();
-          cfma(acc, ld(bi + NQ + i), piv);
+          cfma(acc, sb[NQ + i], piv);
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) cfma(acc, ld(Ai + row + q), un[q]);
+          for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
 #pragma unroll
-          for (int l = 2 * K; l < NPD; ++l) cfma(acc, ld(Ai + row + NQ + l), x[l]);
+          for (int l = 2 * K; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
           st(dst, cscale(acc, scale));
         }
       }
@@ -436,13 +439,13 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Rows of the first undetected coordinate per chunk: as many as fit one
-// 256-thread pass together with the recomputed halo row, spread evenly.
+// Rows of the first undetected coordinate per chunk: about one wavefront of
+// own entries, spread evenly over the rows.
 static ChunkGeo chunk_geo(const Plan& Pl) {
   ChunkGeo G;
   G.C0 = Pl.udims[0];
   G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, kThreads / G.R0 - 1);
+  int rc = std::max(1, (kBT + G.R0 / 2) / G.R0);
   rc = std::min(rc, G.C0);
   G.nchunks = (G.C0 + rc - 1) / rc;
   G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
@@ -485,7 +488,8 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
 #undef FD_LAUNCH_POINT
   } else {
     const ChunkGeo G = chunk_geo(Pl);
-    const size_t shm = ((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 * sizeof(cx<R>) + tab;
+    const size_t shm = (((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
+                           sizeof(cx<R>) + tab;
     const int grid = nwork * G.nchunks;
 #define FD_LAUNCH_BLOCK(MDV)                                                                               \
   case MDV:                                                                                                \
@@ -493,13 +497,13 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
       if (shm > 65536)                                                                                     \
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 2, R>),                 \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
-      hipLaunchKernelGGL((k_fwd_block<MDV, 2, R>), dim3(grid), dim3(kThreads), shm, st, P, L, A, b, S,    \
+      hipLaunchKernelGGL((k_fwd_block<MDV, 2, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S,         \
                          nwork, G);                                                                        \
     } else {                                                                                               \
       if (shm > 65536)                                                                                     \
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 4, R>),                 \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
-      hipLaunchKernelGGL((k_fwd_block<MDV, 4, R>), dim3(grid), dim3(kThreads), shm, st, P, L, A, b, S,    \
+      hipLaunchKernelGGL((k_fwd_block<MDV, 4, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S,         \
                          nwork, G);                                                                        \
     }                                                                                                      \
     break;

@@ -24,7 +24,6 @@
 
 namespace fd {
 
-constexpr int kRS = 64;     // records staged per sub-round
 
 template <typename R>
 struct VjpPtrs {
@@ -73,102 +72,53 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
   }
 }
 
-// ---------------------------------------------------------------------------
-// Outer-product accumulation Abar[i][l] += sum_records conj(X[l]) H[i].
-// Pairs p = i * NR + l (NR = npos + 1, column npos = b term).  With P pairs,
-// G = 256 / P record groups share a pair (P <= 256), else each thread owns
-// pairs t and t + 256.  Accumulators live in registers (double).
-// ---------------------------------------------------------------------------
-struct PairMap {
-  int P, NR, G;
-};
+constexpr int kWRec = 32;
 
-__device__ __forceinline__ PairMap pair_map(int npos) {
-  PairMap m;
-  m.NR = npos + 1;
-  m.P = npos * m.NR;
-  m.G = m.P >= kThreads ? 1 : kThreads / m.P;
-  return m;
-}
+// records: H rows NPD (detected write positions), X rows NR (NQ undetected
+// reads, NPD detected reads, pivot value).  Pair p = i * NR + l.  Rows are
+// kWRec + 1 elements apart so that the rows read together by one wavefront
+// fall in different LDS banks; four partial sums per pair keep the FMA chain
+// short (combined in a fixed order).
+constexpr int kWStride = kWRec + 1;
 
-template <typename R>
-__device__ __forceinline__ void accumulate_records(const PairMap& pm, const cx<R>* Hs, const cx<R>* Xs, int E,
-                                                   cx<double>& a0, cx<double>& a1) {
-  const int t = threadIdx.x;
-  if (t < pm.P * pm.G) {
-    const int p = t % pm.P, g = t / pm.P;
-    const int i = p / pm.NR, l = p % pm.NR;
-    const cx<R>* h = Hs + i * kRS;
-    const cx<R>* x = Xs + l * kRS;
-    for (int e = g; e < E; e += pm.G) {
-      const cx<R> hv = h[e], xv = x[e];
-      a0.x += (double)xv.x * hv.x + (double)xv.y * hv.y;
-      a0.y += (double)xv.x * hv.y - (double)xv.y * hv.x;
-    }
-  }
-  if (pm.P > kThreads && t + kThreads < pm.P) {
-    const int p = t + kThreads;
-    const int i = p / pm.NR, l = p % pm.NR;
-    const cx<R>* h = Hs + i * kRS;
-    const cx<R>* x = Xs + l * kRS;
-    for (int e = 0; e < E; ++e) {
-      const cx<R> hv = h[e], xv = x[e];
-      a1.x += (double)xv.x * hv.x + (double)xv.y * hv.y;
-      a1.y += (double)xv.x * hv.y - (double)xv.y * hv.x;
-    }
-  }
-}
-
-// Every thread holds one record (h over npos write positions, x over npos
-// read positions + the pivot value); the workgroup folds them in sub-rounds
-// of kRS records.  Must be reached by every thread of the workgroup.
-template <typename R, int NW>
-__device__ __forceinline__ void stage_accumulate(const PairMap& pm, int npos, const cx<R>* h, const cx<R>* x,
-                                                 cx<R>* Hs, cx<R>* Xs, cx<double>& a0, cx<double>& a1) {
+template <typename R, int NPD, int NR, int PPL>
+__device__ __forceinline__ void wave_accum(cx<R>* recw, const cx<R>* h, const cx<R>* x, bool have,
+                                           cx<double>* acc) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long bal = __ballot(have);
 #pragma unroll 1
-  for (int s = 0; s < kThreads / kRS; ++s) {
-    const int t = (int)threadIdx.x - s * kRS;
-    if (t >= 0 && t < kRS) {
+  for (int half = 0; half < 64 / kWRec; ++half) {
+    const unsigned long long hm = (bal >> (half * kWRec)) & ((1ull << kWRec) - 1);
+    if (hm == 0ull) continue;   // uniform over the wave
+    if (lane / kWRec == half) {
+      const int e = lane % kWRec;
 #pragma unroll
-      for (int i = 0; i < NW; ++i)
-        if (i < npos) Hs[i * kRS + t] = h[i];
+      for (int i = 0; i < NPD; ++i) recw[i * kWStride + e] = have ? h[i] : czero<R>();
 #pragma unroll
-      for (int l = 0; l < NW + 1; ++l)
-        if (l <= npos) Xs[l * kRS + t] = x[l];
+      for (int l = 0; l < NR; ++l) recw[(NPD + l) * kWStride + e] = have ? x[l] : czero<R>();
     }
-    __syncthreads();
-    accumulate_records(pm, Hs, Xs, kRS, a0, a1);
-    __syncthreads();
-  }
-}
-
-// Adds the workgroup's pair sums to its partial slot (combining record groups
-// in a fixed order).
-__device__ __forceinline__ void flush_pairs(const PairMap& pm, double2* slot, cx<double> a0, cx<double> a1,
-                                            cx<double>* red) {
-  const int t = threadIdx.x;
-  __syncthreads();
-  if (pm.G > 1) {
-    if (t < pm.P * pm.G) red[t] = a0;
-    __syncthreads();
-    if (t < pm.P) {
-      cx<double> s = cmake<double>(0.0, 0.0);
-      for (int g = 0; g < pm.G; ++g) {
-        s.x += red[g * pm.P + t].x;
-        s.y += red[g * pm.P + t].y;
+    wave_sync();
+#pragma unroll
+    for (int pp = 0; pp < PPL; ++pp) {
+      const int p = lane + 64 * pp;
+      if (p < NPD * NR) {
+        const int i = p / NR, l = p - (p / NR) * NR;
+        const cx<R>* H = recw + i * kWStride;
+        const cx<R>* X = recw + (NPD + l) * kWStride;
+        double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < kWRec; ++e) {
+          const cx<R> hv = H[e], xv = X[e];
+          ax[e & 3] = fma((double)xv.x, (double)hv.x, ax[e & 3]);
+          ax[e & 3] = fma((double)xv.y, (double)hv.y, ax[e & 3]);
+          ay[e & 3] = fma((double)xv.x, (double)hv.y, ay[e & 3]);
+          ay[e & 3] = fma(-(double)xv.y, (double)hv.x, ay[e & 3]);
+        }
+        acc[pp].x += (ax[0] + ax[1]) + (ax[2] + ax[3]);
+        acc[pp].y += (ay[0] + ay[1]) + (ay[2] + ay[3]);
       }
-      double2 v = slot[t];
-      slot[t] = make_double2(v.x + s.x, v.y + s.y);
     }
-  } else {
-    if (t < pm.P) {
-      double2 v = slot[t];
-      slot[t] = make_double2(v.x + a0.x, v.y + a0.y);
-    }
-    if (t + kThreads < pm.P) {
-      double2 v = slot[t + kThreads];
-      slot[t + kThreads] = make_double2(v.x + a1.x, v.y + a1.y);
-    }
+    wave_sync();
   }
 }
 
@@ -190,17 +140,23 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         double2* __restrict__ partial) {
   constexpr int NP = 2 * MD;
+  constexpr int NR = NP + 1;
+  constexpr int NPAIR = NP * NR;
+  constexpr int PPL = (NPAIR + 63) / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* Hs = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* Xs = Hs + NP * kRS;
-  cx<double>* red = reinterpret_cast<cx<double>*>(Xs + (NP + 1) * kRS);
-  R* sq = reinterpret_cast<R*>(red + kThreads);
+  cx<R>* rec = reinterpret_cast<cx<R>*>(smem_raw);                   // waves x kWStride x (NP + NR)
+  cx<R>* sA = rec + (size_t)(kThreads / 64) * kWStride * (NP + NR);  // A (NP x NP) then b (NP)
+  const cx<R>* sb = sA + NP * NP;
+  R* sq = reinterpret_cast<R*>(sA + NP * NP + NP);
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables_v(P, spn, sq, isq);
+  for (int i = threadIdx.x; i < NP * NP + NP; i += blockDim.x) sA[i] = ld(Ai + i);
   __syncthreads();
-  const PairMap pm = pair_map(NP);
-  cx<double> a0 = cmake<double>(0.0, 0.0), a1 = a0;
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWStride * (NP + NR);
+  cx<double> acc[PPL];
+#pragma unroll
+  for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
   const int pnw = P.pnw;
 
   for (int base = blockIdx.x * kThreads; base < nwork; base += gridDim.x * kThreads) {
@@ -258,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         for (int l = 2 * K; l < NP; ++l) {
           cx<R> u = czero<R>();
 #pragma unroll
-          for (int i = 2 * K; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(u, sA[i * NP + l], h[i]);
           const int j = l >> 1;
           if (l == 2 * K) {
             g0acc = cadd(g0acc, cscale(u, sq[m[K] + 1]));
@@ -271,12 +227,12 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         if (ODD) {
           cx<R> gp = czero<R>();
 #pragma unroll
-          for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
           const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
           ykg[K] = has_diag_reader ? cadd(ld(V.gcur[fam_f1k(K)] + r), gp) : gp;
         }
       }
-      stage_accumulate<R, NP>(pm, NP, h, x, Hs, Xs, a0, a1);
+      wave_accum<R, NP, NR, PPL>(recw, h, x, valid, acc);
     }
 
     if (ODD) {
@@ -309,20 +265,36 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             if (m[j] == 0) continue;
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 0; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
+            for (int i = 0; i < NP; ++i) cfma_conj(u, sA[i * NP + l], h[i]);
             st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + rdn[j], cscale(u, sq[m[j]]));
           }
           cx<R> gp = czero<R>();
 #pragma unroll
-          for (int i = 0; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
+          for (int i = 0; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
           g0acc = cadd(g0acc, gp);
         }
-        stage_accumulate<R, NP>(pm, NP, h, x, Hs, Xs, a0, a1);
+        wave_accum<R, NP, NR, PPL>(recw, h, x, valid, acc);
       }
     }
     if (live) st(V.gcur[0] + r, g0acc);
   }
-  flush_pairs(pm, partial + (size_t)blockIdx.x * pm.P, a0, a1, red);
+  // fold the per-lane pair sums over the waves (fixed order) into this block's slot
+  cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
+  __syncthreads();
+#pragma unroll
+  for (int pp = 0; pp < PPL; ++pp) red[(size_t)(threadIdx.x >> 6) * 64 * PPL + pp * 64 + (threadIdx.x & 63)] = acc[pp];
+  __syncthreads();
+  double2* slot = partial + (size_t)blockIdx.x * NPAIR;
+  for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
+    const int pp = p / 64, lane = p - pp * 64;
+    double sx = 0.0, sy = 0.0;
+    for (int wv = 0; wv < kThreads / 64; ++wv) {
+      sx += red[(size_t)wv * 64 * PPL + pp * 64 + lane].x;
+      sy += red[(size_t)wv * 64 * PPL + pp * 64 + lane].y;
+    }
+    const double2 v = slot[p];
+    slot[p] = make_double2(v.x + sx, v.y + sy);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,51 +308,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 // time in its own LDS region and each lane accumulates fixed (i, l) pairs in
 // registers for the whole kernel; no workgroup barrier is involved.
 // ---------------------------------------------------------------------------
-constexpr int kWRec = 32;
-
-// records: H rows NPD (detected write positions), X rows NR (NQ undetected
-// reads, NPD detected reads, pivot value).  Pair p = i * NR + l.
-template <typename R, int NPD, int NR, int PPL>
-__device__ __forceinline__ void wave_accum(cx<R>* recw, const cx<R>* h, const cx<R>* x, bool have,
-                                           cx<double>* acc) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long bal = __ballot(have);
-#pragma unroll 1
-  for (int half = 0; half < 64 / kWRec; ++half) {
-    const unsigned long long hm = (bal >> (half * kWRec)) & ((1ull << kWRec) - 1);
-    if (hm == 0ull) continue;   // uniform over the wave
-    if (lane / kWRec == half) {
-      const int e = lane % kWRec;
-#pragma unroll
-      for (int i = 0; i < NPD; ++i) recw[i * kWRec + e] = have ? h[i] : czero<R>();
-#pragma unroll
-      for (int l = 0; l < NR; ++l) recw[(NPD + l) * kWRec + e] = have ? x[l] : czero<R>();
-    }
-    wave_sync();
-#pragma unroll
-    for (int pp = 0; pp < PPL; ++pp) {
-      const int p = lane + 64 * pp;
-      if (p < NPD * NR) {
-        const int i = p / NR, l = p - (p / NR) * NR;
-        const cx<R>* H = recw + i * kWRec;
-        const cx<R>* X = recw + (NPD + l) * kWRec;
-        double ax = acc[pp].x, ay = acc[pp].y;
-#pragma unroll 8
-        for (int e = 0; e < kWRec; ++e) {
-          const cx<R> hv = H[e], xv = X[e];
-          ax += (double)xv.x * hv.x + (double)xv.y * hv.y;
-          ay += (double)xv.x * hv.y - (double)xv.y * hv.x;
-        }
-        acc[pp].x = ax;
-        acc[pp].y = ay;
-      }
-    }
-    wave_sync();
-  }
-}
-
 template <int MD, int NQ, typename R>
-__global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
+__global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         ChunkGeo G, double2* __restrict__ partial) {
   constexpr int NPD = 2 * MD;
@@ -396,13 +325,16 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
   cx<R>* gbv = qv + (size_t)NQ * nrow2;              // rows [k0, k1+1)
   cx<R>* gpk = gbv + nrow1;                          // MD x rows [k0, k1+1)
   cx<R>* g0a = gpk + (size_t)MD * nrow1;             // own rows
-  cx<R>* rec = g0a + (size_t)RC * R0;                // 4 waves x kWRec x (NPD + NR)
-  R* sq = reinterpret_cast<R*>(rec + (size_t)(kThreads / 64) * kWRec * (NPD + NR));
+  cx<R>* rec = g0a + (size_t)RC * R0;                // waves x kWStride x (NPD + NR)
+  cx<R>* sA = rec + (size_t)(kBT / 64) * kWStride * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
+  const cx<R>* sb = sA + NPOS * NPOS;
+  R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables_v(P, spn, sq, isq);
+  for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
   __syncthreads();
-  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWRec * (NPD + NR);
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWStride * (NPD + NR);
   cx<double> acc[PPL];
 #pragma unroll
   for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
@@ -462,13 +394,13 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
           for (int q = 0; q < NQ; ++q) {
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + q), h[i]);
+            for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, sA[(NQ + i) * NPOS + q], h[i]);
             qv[(size_t)q * nrow2 + (e - e_own0)] = u;
           }
           if (e < eb1) {
             cx<R> gb = czero<R>();
 #pragma unroll
-            for (int i = 2 * K; i < NPD; ++i) cfma_conj(gb, ld(bi + NQ + i), h[i]);
+            for (int i = 2 * K; i < NPD; ++i) cfma_conj(gb, sb[NQ + i], h[i]);
             gbv[e - e_own0] = gb;
           }
           if (own) {
@@ -493,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
               if (l != 2 * K && m[j] == 0) continue;
               cx<R> u = czero<R>();
 #pragma unroll
-              for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + NQ + l), h[i]);
+              for (int i = 2 * K; i < NPD; ++i) cfma_conj(u, sA[(NQ + i) * NPOS + NQ + l], h[i]);
               if (l == 2 * K) {
                 g0a[e - e_own0] = cadd(g0a[e - e_own0], cscale(u, sq[m[K] + 1]));
               } else if (l == 2 * K + 1) {
@@ -564,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
           for (int q = 0; q < NQ; ++q) {
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + q), h[i]);
+            for (int i = 0; i < NPD; ++i) cfma_conj(u, sA[(NQ + i) * NPOS + q], h[i]);
             qv[(size_t)q * nrow2 + le] = u;
           }
           if (own) {
@@ -586,12 +518,12 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
               if (m[j] == 0) continue;
               cx<R> u = czero<R>();
 #pragma unroll
-              for (int i = 0; i < NPD; ++i) cfma_conj(u, ld(Ai + (NQ + i) * NPOS + NQ + l), h[i]);
+              for (int i = 0; i < NPD; ++i) cfma_conj(u, sA[(NQ + i) * NPOS + NQ + l], h[i]);
               st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + (size_t)rdn[j] * B + e, cscale(u, sq[m[j]]));
             }
             cx<R> gb = czero<R>();
 #pragma unroll
-            for (int i = 0; i < NPD; ++i) cfma_conj(gb, ld(bi + NQ + i), h[i]);
+            for (int i = 0; i < NPD; ++i) cfma_conj(gb, sb[NQ + i], h[i]);
             g0a[le] = cadd(g0a[le], gb);
           }
         }
@@ -624,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_block(DevPlan P, VjpPtrs<R> V,
   for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
     const int pp = p / 64, lane = p - pp * 64;
     double sx = 0.0, sy = 0.0;
-    for (int wv = 0; wv < kThreads / 64; ++wv) {
+    for (int wv = 0; wv < kBT / 64; ++wv) {
       sx += red[(size_t)wv * 64 * PPL + pp * 64 + lane].x;
       sy += red[(size_t)wv * 64 * PPL + pp * 64 + lane].y;
     }
@@ -806,7 +738,7 @@ static ChunkGeo chunk_geo_v(const Plan& Pl) {
   ChunkGeo G;
   G.C0 = Pl.udims[0];
   G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, kThreads / G.R0 - 2);
+  int rc = std::max(1, (kBT + G.R0 / 2) / G.R0);
   rc = std::min(rc, G.C0);
   G.nchunks = (G.C0 + rc - 1) / rc;
   G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
@@ -880,7 +812,10 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     KTimer kt(Pl, KK_VJP_LEVEL, st);
     if (Pl.B == 1) {
       const int NP = 2 * MD;
-      const size_t shm = (size_t)(2 * NP + 1) * kRS * sizeof(cx<R>) + kThreads * sizeof(cx<double>) + tab;
+      const size_t ppl = (size_t)(NP * (NP + 1) + 63) / 64;
+      const size_t shm = std::max(((size_t)(kThreads / 64) * (kWRec + 1) * (2 * NP + 1) + (size_t)NP * (NP + 1)) *
+                                      sizeof(cx<R>),
+                                  (size_t)kThreads * ppl * sizeof(cx<double>)) + tab;
       const int grid = (int)std::min<int64_t>((nwork + kThreads - 1) / kThreads, kPartialSlots - 1);
 #define FD_VJP_POINT(MDV)                                                                                        \
   case MDV:                                                                                                      \
@@ -915,8 +850,10 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       const ChunkGeo G = chunk_geo_v(Pl);
       const int NPD = 2 * MD, NR = Pl.npos + 1;
       const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                          (size_t)G.RC * G.R0 + (size_t)(kThreads / 64) * kWRec * (NPD + NR);
-      const size_t shm = std::max(ents * sizeof(cx<R>), (size_t)kThreads * 4 * sizeof(cx<double>) + 64) + tab;
+                          (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (kWRec + 1) * (NPD + NR);
+      const size_t ppl = (size_t)(NPD * NR + 63) / 64;
+      const size_t shm = std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * sizeof(cx<R>),
+                                  (size_t)kBT * ppl * sizeof(cx<double>)) + tab;
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \
@@ -924,13 +861,13 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       if (shm > 65536)                                                                                          \
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R>),                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,          \
                          nwork, G, partial);                                                                    \
     } else {                                                                                                    \
       if (shm > 65536)                                                                                          \
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R>),                      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,     \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,          \
                          nwork, G, partial);                                                                    \
     }                                                                                                           \
     break;
