@@ -162,13 +162,43 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
                           void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Batched forward over n independent circuits, each with its own plan and
- * buffers (arrays of n host-side entries holding device pointers).  Every
- * circuit's workspace must satisfy its own plan (with_vjp = 0).  All circuits
- * are swept level by level in shared launches on one stream (the per-level
- * independence of Sec. 2.2 applied across circuits). */
+ * buffers (arrays of n host-side entries holding device pointers), in one
+ * persistent sweep launch.  All pivots of one weight are independent
+ * (Sec. 2.2) and circuits are independent of each other: step S of every
+ * circuit is swept together, by a cooperative grid that fills the device and
+ * takes (circuit, step, tile) work items from a per-step queue, with a grid
+ * barrier between steps.  Launches: prep (+ undetected block fill), the
+ * sweep, the output permutation.
+ *   plans      n plans of one dtype, created on the current device
+ *   workspace  per circuit, >= fd_plan_workspace(plan, 0) bytes, 256-byte
+ *              aligned; the n workspaces must not overlap (FD_ERR_INVALID_ARG)
+ *   rho        per circuit, as for fock_diag_fwd
+ * Results equal fock_diag_fwd's bit for bit.  The library keeps the work-item
+ * table, per-circuit descriptors and the sweep's control words of the last 8
+ * (plan set, pointer set) combinations in device memory (freed with the
+ * plans); two batched calls with the same plans and pointers must not overlap
+ * in time.  A circuit whose block is too large for the sweep's LDS staging,
+ * or a device without cooperative launches, gives FD_ERR_UNSUPPORTED.  A
+ * barrier wait that exceeds its bound (a few seconds) is reported by
+ * fd_device_status of the first plan as FD_ERR_HIP. */
 fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
                               const void* const* b, const void* const* c, void* const* rho,
                               void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
+
+/* Scheduling knobs of fock_diag_fwd_batch (process-wide; a schedule built
+ * under other knobs is rebuilt on next use): every step of a circuit is cut
+ * into items of units / (items_per_wave x resident wavefronts) units, at
+ * least min_block_units (lattice point, row chunk) units (Algorithm 2) or
+ * min_point_units lattice points (Algorithm 1).  Defaults {2, 64, 4}; the
+ * package's autotuner picks them per batch by timing.  Values below 1 give
+ * FD_ERR_INVALID_ARG. */
+typedef struct {
+  int32_t min_block_units;
+  int32_t min_point_units;
+  int32_t items_per_wave;
+} fd_batch_tuning;
+fd_status fd_batch_set_tuning(const fd_batch_tuning* t);
+fd_status fd_batch_get_tuning(fd_batch_tuning* t);
 
 /* Graph replay (for callers that reuse their buffers): with enable != 0, the
  * first fock_diag_fwd / fock_diag_vjp call with a given set of pointers is
@@ -187,9 +217,12 @@ fd_status fd_plan_use_graphs(fd_plan p, int enable);
  * summed duration in milliseconds, then drops the records.  Kinds:
  * 0 input prep, 1 undetected-block fill, 2 forward level sweep, 3 output
  * permutation, 4 cotangent permutation, 5 reverse level sweep, 6 reverse of
- * the undetected-block fill, 7 gradient reduction, 8 accumulator clear. */
+ * the undetected-block fill, 7 gradient reduction, 8 accumulator clear,
+ * 9 batched prep, 10 batched persistent sweep, 11 batched output permutation
+ * (batched kinds are recorded on the first plan of the batch). */
 enum { FD_K_PREP = 0, FD_K_UFILL = 1, FD_K_FWD_LEVEL = 2, FD_K_OUT_PERM = 3, FD_K_PERM_IN = 4,
-       FD_K_VJP_LEVEL = 5, FD_K_UFILL_VJP = 6, FD_K_VJP_FINAL = 7, FD_K_ZERO = 8 };
+       FD_K_VJP_LEVEL = 5, FD_K_UFILL_VJP = 6, FD_K_VJP_FINAL = 7, FD_K_ZERO = 8,
+       FD_K_BATCH_PREP = 9, FD_K_BATCH_SWEEP = 10, FD_K_BATCH_OUT = 11 };
 fd_status fd_plan_timing(fd_plan p, uint32_t kind_mask);
 fd_status fd_plan_kernel_times(fd_plan p, int kind, int64_t* launches, double* total_ms);
 
@@ -198,7 +231,8 @@ const char* fd_last_error(void);
 
 /* Reads and clears the plan's device status word (synchronises `stream`):
  * FD_OK, or FD_ERR_NONFINITE if a non-finite input or output was seen, or
- * FD_ERR_INVALID_ARG if a plan made with FD_B_ZERO received a non-zero b. */
+ * FD_ERR_INVALID_ARG if a plan made with FD_B_ZERO received a non-zero b, or
+ * FD_ERR_HIP if a batched sweep gave up waiting at a step barrier. */
 fd_status fd_device_status(fd_plan p, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfockdiag.so")
-SOURCES = ["planner.cpp", "abi.cpp", "kernels_fwd.hip", "kernels_vjp.hip"]
+SOURCES = ["planner.cpp", "abi.cpp", "kernels_fwd.hip", "kernels_vjp.hip", "kernels_batch.hip",
+           "kernels_batch_md6.hip", "kernels_batch_md8.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device pass.
@@ -21,7 +22,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = min(8, os.cpu_count() or 4)) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []

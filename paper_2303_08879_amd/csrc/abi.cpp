@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "fd_internal.h"
 
@@ -156,6 +158,7 @@ fd_status fd_plan_destroy(fd_plan p) {
     (void)hipSetDevice(cur);
   }
   drop_graphs(P);
+  fd::batch_forget(P.uid);
   if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
   for (auto& v : P.timing.rec)
     for (auto& pr : v) {
@@ -294,10 +297,49 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
                               const size_t* ws_bytes, hipStream_t stream) {
   if (n < 0 || (n > 0 && (!plans || !A || !b || !c || !rho || !workspace || !ws_bytes)))
     return fail(FD_ERR_INVALID_ARG, "bad batch arguments");
+  if (n == 0) return ok();
+  std::vector<fd::Plan*> P(n);
+  std::unique_ptr<bool[]> odd(new bool[n]);
+  std::vector<std::pair<uintptr_t, uintptr_t>> spans(n);
+  std::string err;
+  // host-side checks of every circuit first, then the device-side ones
   for (int i = 0; i < n; ++i) {
-    fd_status s = fock_diag_fwd(plans[i], A[i], b[i], c[i], rho[i], workspace[i], ws_bytes[i], nullptr, 0, stream);
+    if (!plans[i]) return fail(FD_ERR_INVALID_ARG, "a plan of the batch is NULL");
+    P[i] = &plans[i]->P;
+    if (P[i]->dt != P[0]->dt) return fail(FD_ERR_INVALID_ARG, "every plan of a batch must have the same dtype");
+    fd_status s = check_ptrs(*P[i], {A[i], b[i], c[i], rho[i], workspace[i]});
     if (s != FD_OK) return s;
+    if (!aligned(workspace[i], 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   }
+  for (int i = 0; i < n; ++i) {
+    fd_status s;
+    bool b_zero = false;
+    if ((s = decide_b_zero(*P[i], b[i], stream, &b_zero)) != FD_OK) return s;
+    odd[i] = P[i]->odd_for(b_zero);
+    const size_t need = fd::fwd_layout(*P[i], odd[i], false, 0).total;
+    if (ws_bytes[i] < need) return fail(FD_ERR_WORKSPACE, "workspace of circuit " + std::to_string(i) + " too small");
+    spans[i] = {reinterpret_cast<uintptr_t>(workspace[i]), reinterpret_cast<uintptr_t>(workspace[i]) + need};
+    if ((s = fd::ensure_device(P[i], &err)) != FD_OK) return fail(s, err);
+    if (P[i]->device != P[0]->device) return fail(FD_ERR_INVALID_ARG, "every plan of a batch must be on one device");
+  }
+  std::sort(spans.begin(), spans.end());
+  for (int i = 1; i < n; ++i)
+    if (spans[i].first < spans[i - 1].second)
+      return fail(FD_ERR_INVALID_ARG, "the workspaces of a batch must not overlap");
+  fd_status s = fd::run_forward_batch(n, P.data(), odd.get(), A, b, c, rho, workspace, stream, &err);
+  if (s != FD_OK) return fail(s, err);
+  return ok();
+}
+
+fd_status fd_batch_set_tuning(const fd_batch_tuning* t) {
+  if (!t) return fail(FD_ERR_INVALID_ARG, "tuning is NULL");
+  if (fd::batch_set_tuning(*t) != FD_OK) return fail(FD_ERR_INVALID_ARG, "batch tuning values out of range");
+  return ok();
+}
+
+fd_status fd_batch_get_tuning(fd_batch_tuning* t) {
+  if (!t) return fail(FD_ERR_INVALID_ARG, "tuning is NULL");
+  *t = fd::batch_get_tuning();
   return ok();
 }
 
@@ -356,6 +398,7 @@ fd_status fd_device_status(fd_plan p, hipStream_t stream) {
     return fail(FD_ERR_HIP, "reading the device status failed");
   if (h & 1) return fail(FD_ERR_NONFINITE, "non-finite value seen on the device");
   if (h & 2) return fail(FD_ERR_INVALID_ARG, "plan made with FD_B_ZERO received a non-zero b");
+  if (h & 4) return fail(FD_ERR_HIP, "a batched sweep gave up waiting at a step barrier (results invalid)");
   return ok();
 }
 

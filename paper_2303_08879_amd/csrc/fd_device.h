@@ -87,12 +87,6 @@ __device__ __forceinline__ void wave_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Split of a node's undetected block into chunks of whole rows of the first
-// undetected coordinate (rows of R0 = B / C0 entries).
-struct ChunkGeo {
-  int C0, R0, RC, nchunks;   // rows, entries per row, rows per chunk, chunks per node
-};
-
 // PN[d][x] for x in [-1, smax+1]; table row width pnw.
 __device__ __forceinline__ int pnv(const int* spn, int pnw, int d, int x) { return spn[d * pnw + x + 1]; }
 

@@ -32,7 +32,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/fockdiag.h"
+#include "fockdiag.h"
 
 namespace fd {
 
@@ -76,6 +76,12 @@ struct DevPlan {
   int64_t ringN[kMaxD];      // ring slot stride in nodes per group (ring mode)
 };
 
+// Split of a node's undetected block into chunks of whole rows of the first
+// undetected coordinate (rows of R0 = B / C0 entries).
+struct ChunkGeo {
+  int C0, R0, RC, nchunks;   // rows, entries per row, rows per chunk, chunks per node
+};
+
 // Device pointers of one set of family arrays (forward values or cotangents).
 template <typename R>
 struct FamPtrs {
@@ -86,7 +92,7 @@ struct FamPtrs {
 // Optional per-launch HIP-event timing, by kernel kind.
 enum KernelKind {
   KK_PREP = 0, KK_UFILL, KK_FWD_LEVEL, KK_OUT_PERM, KK_PERM_IN, KK_VJP_LEVEL, KK_UFILL_VJP, KK_VJP_FINAL,
-  KK_ZERO, KK_COUNT
+  KK_ZERO, KK_BATCH_PREP, KK_BATCH_SWEEP, KK_BATCH_OUT, KK_COUNT
 };
 struct Timing {
   uint32_t mask = 0;
@@ -105,6 +111,7 @@ struct GraphEntry {
 };
 
 struct Plan {
+  uint64_t uid = 0;                  // unique per plan (keys of cached batch schedules)
   // caller's view
   int M = 0;
   std::vector<int> cut;
@@ -170,6 +177,14 @@ constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);
 size_t prep_bytes(const Plan& P);
 void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
+// Batched forward (one persistent sweep launch over every circuit); plans
+// already on the current device, workspaces checked by the caller.
+fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                            const void* const* b, const void* const* c, void* const* rho, void* const* ws,
+                            hipStream_t st, std::string* err);
+void batch_forget(uint64_t plan_uid);   // drops cached batch schedules that use this plan
+fd_status batch_set_tuning(const fd_batch_tuning& T);
+fd_batch_tuning batch_get_tuning();
 
 // Brackets one launch with events when its kind is enabled on the plan.
 struct KTimer {
@@ -204,6 +219,7 @@ struct KTimer {
 // kernels (kernels_fwd.hip / kernels_vjp.hip)
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
                        void* saved, hipStream_t st);
+ChunkGeo chunk_geo(const Plan& P);   // forward block kernels
 hipError_t launch_prep(const Plan& P, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
                        hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,

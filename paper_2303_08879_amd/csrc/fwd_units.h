@@ -1,0 +1,409 @@
+// Per-unit device code of the forward sweep, shared by the per-circuit level
+// kernels and the batched persistent kernel.
+//
+// One sweep step S handles every lattice point m with |m| = S of the detected
+// box.  At m it applies, in this order (Algorithm 1, Sec. 3.1.3; Algorithm 2,
+// Sec. 3.2, where every node is a block of undetected-mode entries):
+//   * the diagonal pivot d(m) (needed when b != 0 or modes are undetected):
+//     it writes the type-1 offsets d(m) + 1_i at weight 2S+1, reading its own
+//     value (the b term of Eq. recrel, and the undetected neighbours of the
+//     block) and the type-1 offsets of the previous step;
+//   * the off-diagonal / bridge pivots d(m) + 1_ket(K) for K up to the first
+//     non-zero mode of m: they write F0(m + 1_K), F2(K)(m), F1010(K,.)(m) and
+//     F1001(K,.)(m) at weight 2S+2 from the previous step's even families.
+// Every target is written by exactly one pivot (its canonical parent), so the
+// units are pure gathers with no atomics.  All targets of one step are
+// independent (Sec. 2.2, the two parallelisations).
+//
+// `LP` is any type with L.rd[f] / L.wr[f] (node-0 pointers of family f at the
+// levels S-1 / S) and L.f0cur / L.f0nxt (F0 at levels S / S+1).
+#pragma once
+
+#include "fd_device.h"
+
+namespace fd {
+
+static_assert(kBT == 64, "block units assume one wavefront per (node, chunk)");
+
+// ---------------------------------------------------------------------------
+// prep: caller's triple (block order) -> interleaved internal positions,
+// A symmetrised; input finiteness and the b = 0 promise checked on device.
+// ---------------------------------------------------------------------------
+struct PrepArgs {
+  int pos2blk[kMaxPos];
+  int npos, M2, check_b_zero;
+};
+
+template <typename R>
+__device__ __forceinline__ void prep_body(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
+                                          const cx<R>* __restrict__ c, cx<R>* __restrict__ Ai,
+                                          cx<R>* __restrict__ bi, cx<R>* __restrict__ ci,
+                                          cx<R>* __restrict__ f0node0, const PrepArgs& a, int* status) {
+  const int npos = a.npos, M2 = a.M2;
+  int bad = 0;
+  for (int idx = threadIdx.x; idx < npos * npos; idx += blockDim.x) {
+    const int p = idx / npos, q = idx % npos;
+    const int pb = a.pos2blk[p], qb = a.pos2blk[q];
+    const cx<R> u = ld(A + (size_t)pb * M2 + qb), v = ld(A + (size_t)qb * M2 + pb);
+    const cx<R> s = cmake<R>(R(0.5) * (u.x + v.x), R(0.5) * (u.y + v.y));
+    if (!isfinite(s.x) || !isfinite(s.y)) bad |= 1;
+    st(Ai + idx, s);
+  }
+  for (int p = threadIdx.x; p < npos; p += blockDim.x) st(bi + p, ld(b + a.pos2blk[p]));
+  for (int p = threadIdx.x; p < M2; p += blockDim.x) {
+    const cx<R> v = ld(b + p);
+    if (!isfinite(v.x) || !isfinite(v.y)) bad |= 1;
+    if (a.check_b_zero && (v.x != R(0) || v.y != R(0))) bad |= 2;
+  }
+  if (threadIdx.x == 0) {
+    const cx<R> cv = ld(c);
+    if (!isfinite(cv.x) || !isfinite(cv.y)) bad |= 1;
+    st(ci, cv);
+    if (f0node0) st(f0node0, cv);  // G_0 = c (Sec. 2.2 vacuum amplitude)
+  }
+  if (bad) atomicOr(status, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 of Algorithm 2: the whole undetected block at zero detections.
+// Entry kappa != 0 is pulled from its parent kappa - 1_q, q = first non-zero
+// coordinate, by Eq. recrel restricted to the undetected positions.  One
+// wavefront, the block in LDS, entries visited by weight (host-built list).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __restrict__ Ai,
+                                           const cx<R>* __restrict__ bi, cx<R>* G, const int* __restrict__ elist,
+                                           const int* __restrict__ woff, int wmax, cx<R>* g) {
+  const int nq = P.nq, npos = P.npos, B = P.B;
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) g[0] = ld(G);   // c, written by the prep kernel
+  wave_sync();
+  for (int w = 1; w <= wmax; ++w) {
+    for (int t = woff[w] + lane; t < woff[w + 1]; t += 64) {
+      const int e = elist[t];
+      int kap[kMaxUq];
+      int rem = e;
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        kap[q] = q < nq ? rem / P.ustride[q] : 0;
+        rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
+      }
+      int qf = nq;
+#pragma unroll
+      for (int q = kMaxUq - 1; q >= 0; --q)
+        if (q < nq && kap[q] > 0) qf = q;
+      const int pe = e - P.ustride[qf];
+      cx<R> acc = czero<R>();
+      cfma(acc, ld(bi + qf), g[pe]);
+#pragma unroll
+      for (int q = 0; q < kMaxUq; ++q) {
+        if (q >= nq) continue;
+        const int pq = kap[q] - (q == qf ? 1 : 0);
+        if (pq > 0) cfma(acc, ld(Ai + qf * npos + q), cscale(g[pe - P.ustride[q]], sqrt(R(pq))));
+      }
+      g[e] = cscale(acc, R(1) / sqrt(R(kap[qf])));
+    }
+    wave_sync();
+  }
+  for (int e = lane; e < B; e += 64) st(G + e, g[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Shared-memory prologue: PN table and sqrt tables.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void load_tables(const DevPlan& P, int* spn, R* sq, R* isq) {
+  const int n = (P.MD + 1) * P.pnw;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) spn[i] = P.pn[i];
+  for (int v = threadIdx.x; v < kMaxCut + 4; v += blockDim.x) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 (every mode detected): one thread per lattice point.
+// ---------------------------------------------------------------------------
+template <int MD, bool ODD, typename R, typename LP>
+__device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, const cx<R>* __restrict__ Ai,
+                                               const cx<R>* __restrict__ bi, const int* spn, const R* sq,
+                                               const R* isq, int S, int r) {
+  constexpr int NP = 2 * MD;
+  const int pnw = P.pnw;
+  int m[MD], s[MD + 1], rdn[MD], rup[MD];
+  unrank<MD>(spn, pnw, P.CD, S, r, m, s);
+  neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+
+  const cx<R> g0 = ld(L.f0cur + r);
+  cx<R> yk[MD];
+#pragma unroll
+  for (int K = 0; K < MD; ++K) yk[K] = czero<R>();
+
+  if (ODD && m[0] <= P.CD[0] - 2) {
+    // diagonal pivot d(m): reads d(m) - 1_l, writes d(m) + 1_i (type-1 offsets)
+    cx<R> x[NP];
+#pragma unroll
+    for (int j = 0; j < MD; ++j) {
+      if (m[j] > 0) {
+        x[2 * j] = cscale(ld(L.rd[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]);   // d(m)-1_ket(j) = F1b(j)(m-1_j)
+        x[2 * j + 1] = cscale(ld(L.rd[fam_f1k(j)] + rdn[j]), sq[m[j]]);   // d(m)-1_bra(j) = F1k(j)(m-1_j)
+      } else {
+        x[2 * j] = czero<R>();
+        x[2 * j + 1] = czero<R>();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MD; ++j) {
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int i = 2 * j + side;
+        cx<R> acc = czero<R>();
+        cfma(acc, ld(bi + i), g0);
+#pragma unroll
+        for (int l = 0; l < NP; ++l) cfma(acc, ld(Ai + i * NP + l), x[l]);
+        acc = cscale(acc, isq[m[j] + 1]);
+        if (side == 0) {
+          yk[j] = acc;
+          if (j == 0 || m[j] <= P.CD[j] - 2) st(L.wr[fam_f1k(j)] + r, acc);
+        } else {
+          const bool ok = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
+          if (ok) st(L.wr[fam_f1b(MD, j)] + r, acc);
+        }
+      }
+    }
+  }
+
+  int K0 = MD;
+#pragma unroll
+  for (int d = MD - 1; d >= 0; --d)
+    if (m[d] > 0) K0 = d;
+#pragma unroll
+  for (int K = 0; K < MD; ++K) {
+    if (K > K0) break;
+    if (m[K] > P.CD[K] - 2) continue;
+    // pivot p = d(m) + 1_ket(K): reads p - 1_l for l >= ket(K)
+    cx<R> x[NP];
+    x[2 * K] = cscale(g0, sq[m[K] + 1]);                                    // p - 1_ket(K) = d(m)
+    x[2 * K + 1] = (m[K] > 0) ? cscale(ld(L.rd[fam_f2(MD, K)] + rdn[K]), sq[m[K]]) : czero<R>();
+#pragma unroll
+    for (int j = K + 1; j < MD; ++j) {
+      if (m[j] > 0) {
+        x[2 * j] = cscale(ld(L.rd[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]);
+        x[2 * j + 1] = cscale(ld(L.rd[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]);
+      } else {
+        x[2 * j] = czero<R>();
+        x[2 * j + 1] = czero<R>();
+      }
+    }
+    // writes p + 1_i
+#pragma unroll
+    for (int i = 2 * K; i < NP; ++i) {
+      const int j = i >> 1;
+      bool ok;
+      R scale;
+      cx<R>* dst;
+      if (i == 2 * K + 1) {                 // d(m + 1_K): output amplitude
+        ok = true;
+        scale = isq[m[K] + 1];
+        dst = L.f0nxt + rup[K];
+      } else if (i == 2 * K) {              // F2(K)(m)
+        ok = (m[K] <= P.CD[K] - 3);
+        scale = isq[m[K] + 2];
+        dst = L.wr[fam_f2(MD, K)] + r;
+      } else {                              // F1010(K,j)(m) / F1001(K,j)(m)
+        ok = (m[j] <= P.CD[j] - 2);
+        scale = isq[m[j] + 1];
+        dst = L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)] + r;
+      }
+      if (!ok) continue;
+      cx<R> acc = czero<R>();
+      if (ODD) cfma(acc, ld(bi + i), yk[K]);
+#pragma unroll
+      for (int l = 2 * K; l < NP; ++l) cfma(acc, ld(Ai + i * NP + l), x[l]);
+      st(dst, cscale(acc, scale));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 (undetected modes present).  A node's block of B entries is
+// split into chunks of whole rows of the first undetected coordinate (rows of
+// R0 = B / C0 entries); one wavefront handles one (lattice point, chunk).
+// The pivot's undetected neighbours reach one row back, so a chunk computes
+// the pivot rows it needs one row above its own (recomputed, not stored).
+// LDS: F0(m) rows [k0-2, k1) and the bridge pivot blocks F1k(K)(m), rows
+// [k0-1, k1), for every bridge K applied at m.
+// ---------------------------------------------------------------------------
+template <int MD, int NQ, typename R, typename LP>
+__device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const cx<R>* sA, const cx<R>* sb,
+                                               const int* spn, const R* sq, const R* isq, int S, int r, int c,
+                                               const ChunkGeo& G, cx<R>* lf0, cx<R>* lpk) {
+  constexpr int NPD = 2 * MD;
+  constexpr int NPOS = NQ + NPD;
+  const int B = P.B, R0 = G.R0;
+  const int lane = threadIdx.x & 63;
+  const int pnw = P.pnw;
+  const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
+  {
+    const int k0 = c * G.RC, k1 = min(G.C0, k0 + G.RC);
+    int m[MD], s[MD + 1], rdn[MD], rup[MD];
+    unrank<MD>(spn, pnw, P.CD, S, r, m, s);
+    neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+    int K0 = MD;
+#pragma unroll
+    for (int d = MD - 1; d >= 0; --d)
+      if (m[d] > 0) K0 = d;
+    if (m[0] > P.CD[0] - 2) return;   // no pivot at this point (uniform)
+    const size_t rB = (size_t)r * B;
+    // F0(m), rows [k0-2, k1)
+    {
+      const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
+      const int base = (k0 - 2) * R0;
+      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = ld(L.f0cur + rB + e);
+    }
+    wave_sync();
+    // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
+    // the halo row only keeps the bridge pivot blocks
+    {
+      const int e0 = max(0, k0 - 1) * R0, e1 = k1 * R0;
+      for (int e = e0 + lane; e < e1; e += kBT) {
+        const bool own = e >= k0 * R0;
+        int kap[NQ];
+        int rem = e;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          kap[q] = rem / P.ustride[q];
+          rem -= kap[q] * P.ustride[q];
+        }
+        const int le = e - (k0 - 2) * R0;
+        const cx<R> piv = lf0[le];
+        cx<R> un[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(lf0[le - P.ustride[q]], sq[kap[q]]) : czero<R>();
+        cx<R> x[NPD];
+#pragma unroll
+        for (int j = 0; j < MD; ++j) {
+          if (m[j] > 0) {
+            x[2 * j] = cscale(ld(L.rd[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            x[2 * j + 1] = cscale(ld(L.rd[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+          } else {
+            x[2 * j] = czero<R>();
+            x[2 * j + 1] = czero<R>();
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < MD; ++j) {
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int i = 2 * j + side;
+            const bool ok = side == 0 ? (j == 0 || m[j] <= P.CD[j] - 2)
+                                      : ((j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2));
+            const bool bridge = side == 0 && j <= K0 && m[j] <= P.CD[j] - 2;
+            if (!(ok && own) && !bridge) continue;
+            const int row = (NQ + i) * NPOS;
+            cx<R> acc = czero<R>();
+            cfma(acc, sb[NQ + i], piv);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
+#pragma unroll
+            for (int l = 0; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
+            acc = cscale(acc, isq[m[j] + 1]);
+            if (ok && own) st(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)] + rB + e, acc);
+            if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
+          }
+        }
+      }
+    }
+    wave_sync();
+    // bridges d(m) + 1_ket(K), own rows
+#pragma unroll
+    for (int K = 0; K < MD; ++K) {
+      if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
+      const cx<R>* pv = lpk + (size_t)K * pk1;
+      for (int e = k0 * R0 + lane; e < k1 * R0; e += kBT) {
+        int kap[NQ];
+        int rem = e;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          kap[q] = rem / P.ustride[q];
+          rem -= kap[q] * P.ustride[q];
+        }
+        const int lp = e - (k0 - 1) * R0;
+        const cx<R> piv = pv[lp];
+        cx<R> un[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : czero<R>();
+        cx<R> x[NPD];
+        x[2 * K] = cscale(lf0[e - (k0 - 2) * R0], sq[m[K] + 1]);
+        x[2 * K + 1] = (m[K] > 0) ? cscale(ld(L.rd[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]) : czero<R>();
+#pragma unroll
+        for (int j = K + 1; j < MD; ++j) {
+          if (m[j] > 0) {
+            x[2 * j] = cscale(ld(L.rd[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            x[2 * j + 1] = cscale(ld(L.rd[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+          } else {
+            x[2 * j] = czero<R>();
+            x[2 * j + 1] = czero<R>();
+          }
+        }
+#pragma unroll
+        for (int i = 2 * K; i < NPD; ++i) {
+          const int j = i >> 1;
+          bool ok;
+          R scale;
+          cx<R>* dst;
+          if (i == 2 * K + 1) {
+            ok = true;
+            scale = isq[m[K] + 1];
+            dst = L.f0nxt + (size_t)rup[K] * B + e;
+          } else if (i == 2 * K) {
+            ok = (m[K] <= P.CD[K] - 3);
+            scale = isq[m[K] + 2];
+            dst = L.wr[fam_f2(MD, K)] + rB + e;
+          } else {
+            ok = (m[j] <= P.CD[j] - 2);
+            scale = isq[m[j] + 1];
+            dst = L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)] + rB + e;
+          }
+          if (!ok) continue;
+          const int row = (NQ + i) * NPOS;
+          cx<R> acc = czero<R>();
+          cfma(acc, sb[NQ + i], piv);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
+#pragma unroll
+          for (int l = 2 * K; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
+          st(dst, cscale(acc, scale));
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// F0 (level-major nodes of B entries) -> rho, C order [kappa][n_D]: the value
+// of output element idx (spn = PN table, slv = level node offsets of F0).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ cx<R> out_perm_elem(const DevPlan& P, const int* spn, const int64_t* slv,
+                                               const cx<R>* __restrict__ f0, int64_t N, int64_t idx) {
+  const int MD = P.MD, B = P.B, pnw = P.pnw;
+  const int64_t kap = idx / N;
+  int64_t rem = idx - kap * N;
+  int n[kMaxD];
+  int S = 0;
+  for (int d = MD - 1; d >= 0; --d) {
+    n[d] = (int)(rem % P.CD[d]);
+    rem /= P.CD[d];
+    S += n[d];
+  }
+  int rank = 0, sd = S;
+  for (int d = 0; d < MD; ++d) {
+    rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - n[d]);
+    sd -= n[d];
+  }
+  return ld(f0 + (size_t)(slv[S] + rank) * B + kap);
+}
+
+}  // namespace fd

@@ -1,0 +1,419 @@
+// Batched forward: prep and permutation kernels of a batch and the host-side
+// schedule (work items, per-circuit descriptors), cached per plan set and
+// pointer set.  The persistent sweep kernel itself is in batch_sweep.h.
+//
+// Launch sequence per batch: prep (+ undetected block fill), one workgroup
+// per circuit; the persistent sweep; the F0 -> rho permutation of every
+// circuit in one launch.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+
+#include "batch_sweep.h"
+
+namespace fd {
+
+// Prep of every circuit (one workgroup each), then step 1 of Algorithm 2 by
+// the first wavefront when the circuit has undetected modes.  Workgroup 0
+// also clears the sweep's control words (queue heads, barrier count).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_batch_prep(const BatchCirc<R>* __restrict__ circs, unsigned* ctl,
+                                                         int nctl) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BatchCirc<R>* __restrict__ C = circs + blockIdx.x;
+  cx<R>* Ai = load_global(&C->Ai);
+  cx<R>* f0 = load_global(&C->f0);
+  const int npos = C->P.npos;
+  prep_body<R>(load_global(&C->A), load_global(&C->b), load_global(&C->c), Ai, Ai + npos * npos,
+               Ai + npos * npos + npos, f0, C->pa, load_global(&C->status));
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nctl; i += blockDim.x) ctl[i] = 0u;
+  if (C->P.B == 1) return;
+  __syncthreads();
+  if (threadIdx.x < 64)
+    ufill_body<R>(C->P, Ai, Ai + npos * npos, f0, load_global(&C->elist), load_global(&C->woff), C->wmax,
+                  reinterpret_cast<cx<R>*>(smem_raw));
+}
+
+// F0 -> rho of every circuit; block b belongs to the circuit c with
+// boff[c] <= b < boff[c + 1].
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_batch_out(const BatchCirc<R>* __restrict__ circs,
+                                                        const int64_t* __restrict__ boff, int n, int pn_bytes) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boff[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const BatchCirc<R>* __restrict__ C = circs + lo;
+  int* spn = reinterpret_cast<int*>(smem_raw);
+  int64_t* slv = reinterpret_cast<int64_t*>(smem_raw + pn_bytes);
+  const int npn = (C->P.MD + 1) * C->P.pnw;
+  const int* pn = load_global(&C->P.pn);
+  const int64_t* lvl = load_global(&C->P.lvl);
+  for (int i = threadIdx.x; i < npn; i += blockDim.x) spn[i] = pn[i];
+  for (int i = threadIdx.x; i <= C->P.smax; i += blockDim.x) slv[i] = C->P.MD > 0 ? lvl[i] : 0;
+  __syncthreads();
+  const int64_t base = (blk - boff[lo]) * (int64_t)kThreads * kOutIter;
+  const cx<R>* f0 = load_global(&C->f0);
+  cx<R>* rho = load_global(&C->rho);
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < kOutIter; ++k) {
+    const int64_t idx = base + (int64_t)k * kThreads + threadIdx.x;
+    if (idx < C->out_elems) {
+      const cx<R> v = out_perm_elem<R>(C->P, spn, slv, f0, C->N, idx);
+      if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+      st(rho + idx, v);
+    }
+  }
+  if (bad) atomicOr(load_global(&C->status), 1);
+}
+
+// ---------------------------------------------------------------------------
+// host side: schedule construction (cached per plan set and pointer set)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchSched {
+  int device = -1;
+  std::vector<uint64_t> key;
+  std::vector<uint64_t> uids;
+  void* d_circs = nullptr;
+  void* d_items = nullptr;
+  void* d_boff = nullptr;
+  void* d_steps = nullptr;             // step offsets into the item table
+  void* d_ctl = nullptr;               // queue heads of every step, then the barrier count
+  int nitems = 0, nsteps = 0;
+  int64_t out_blocks = 0;
+  BatchLds lds{};
+  size_t shm_prep = 0, shm_sweep = 0, shm_out = 0;
+  int out_pn_bytes = 0;
+  int grid = 0;
+  int mdmax = 8;
+  uint64_t last_use = 0;
+  std::vector<unsigned char> h_circs;   // host images kept alive for the asynchronous uploads
+  std::vector<BatchItem> h_items;
+  std::vector<int64_t> h_boff;
+  std::vector<int> h_steps;
+};
+
+std::mutex g_mu;
+std::vector<BatchSched> g_cache;
+fd_batch_tuning g_tuning = {2, 64, 4};
+
+fd_batch_tuning batch_tuning() { return g_tuning; }
+uint64_t g_clock = 0;
+constexpr size_t kBatchCache = 8;
+
+void free_sched(BatchSched& s) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(s.device);
+  (void)hipFree(s.d_circs);
+  (void)hipFree(s.d_items);
+  (void)hipFree(s.d_boff);
+  (void)hipFree(s.d_steps);
+  (void)hipFree(s.d_ctl);
+  (void)hipSetDevice(cur);
+  s.d_circs = s.d_items = s.d_boff = s.d_steps = s.d_ctl = nullptr;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <typename R>
+fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* const* A, const void* const* b,
+                 const void* const* c, void* const* rho, void* const* ws, hipStream_t st, BatchSched* S,
+                 std::string* err) {
+  const size_t eb = sizeof(cx<R>);
+  std::vector<BatchCirc<R>> hc(n);
+  BatchLds lds{16, 0, 0, 4};
+  int out_pn = 16;
+  int64_t out_slv = 8;
+  size_t ufill_lds = 0;
+  std::vector<double> work(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const Plan& Pl = *plans[i];
+    BatchCirc<R>& C = hc[i];
+    std::memset(&C, 0, sizeof(C));
+    C.P = make_devplan(Pl, odd[i]);
+    C.kind = Pl.B > 1 ? 1 : 0;
+    if (C.kind) C.G = chunk_geo(Pl);
+    for (int p = 0; p < Pl.npos; ++p) C.pa.pos2blk[p] = Pl.pos2blk[p];
+    C.pa.npos = Pl.npos;
+    C.pa.M2 = 2 * Pl.M;
+    C.pa.check_b_zero = Pl.flags == FD_B_ZERO ? 1 : 0;
+    C.steps = Pl.MD > 0 ? Pl.smax + 1 : 0;
+    C.wmax = Pl.wmax;
+    const FwdLayout Lw = fwd_layout(Pl, odd[i], false, 0);
+    char* w = static_cast<char*>(ws[i]);
+    for (int f = 1; f < Pl.nfam; ++f) {
+      if (Lw.fam[f] == 0) continue;
+      C.fam[f] = reinterpret_cast<cx<R>*>(w + Lw.fam[f]);
+      C.fstride[f] = Pl.maxN[Pl.fam_group[f]] * (int64_t)Pl.B;
+    }
+    C.f0 = reinterpret_cast<cx<R>*>(w + Lw.f0);
+    C.Ai = reinterpret_cast<cx<R>*>(w + Lw.prep);
+    C.A = static_cast<const cx<R>*>(A[i]);
+    C.b = static_cast<const cx<R>*>(b[i]);
+    C.c = static_cast<const cx<R>*>(c[i]);
+    C.rho = static_cast<cx<R>*>(rho[i]);
+    C.elist = Pl.d_elist;
+    C.woff = Pl.d_woff;
+    C.status = Pl.d_status;
+    C.out_elems = Pl.out_elems;
+    C.N = Pl.nodes_total;
+    const int pnb = (int)align16((size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int));
+    lds.pn_bytes = std::max(lds.pn_bytes, pnb);
+    out_pn = std::max(out_pn, pnb);
+    out_slv = std::max<int64_t>(out_slv, (int64_t)(Pl.smax + 2) * 8);
+    if (C.kind) {
+      lds.sa_bytes = std::max(lds.sa_bytes, (int)align16((size_t)Pl.npos * (Pl.npos + 1) * eb));
+      ufill_lds = std::max(ufill_lds, (size_t)Pl.B * eb);
+    }
+    for (int s = 0; s < C.steps; ++s) work[i] += (double)Pl.ncnt[s] * Pl.B;
+  }
+  // per-wave bytes: PN, A/b, then the block unit rows (largest circuit)
+  size_t rows = 0;
+  for (int i = 0; i < n; ++i)
+    if (hc[i].kind) {
+      const ChunkGeo& G = hc[i].G;
+      rows = std::max(rows, ((size_t)(G.RC + 2) + (size_t)hc[i].P.MD * (G.RC + 1)) * G.R0 * eb);
+    }
+  lds.wave_bytes = (int)align16((size_t)lds.pn_bytes + lds.sa_bytes + rows);
+  lds.waves = 4;
+  while (lds.waves > 1 && kTabBytes + (size_t)lds.waves * lds.wave_bytes > kMaxLds) --lds.waves;
+  if (kTabBytes + (size_t)lds.wave_bytes > kMaxLds || ufill_lds > kMaxLds) {
+    *err = "a circuit's undetected block is too large for the batched sweep's LDS staging";
+    return FD_ERR_UNSUPPORTED;
+  }
+  S->lds = lds;
+  S->shm_sweep = kTabBytes + (size_t)lds.waves * lds.wave_bytes;
+  S->shm_prep = ufill_lds;
+  S->out_pn_bytes = out_pn;
+  S->shm_out = (size_t)out_pn + out_slv;
+
+  // persistent grid: every workgroup that fits at once
+  bool small = true;   // within the (6, 5, 2) build
+  for (int i = 0; i < n; ++i)
+    small = small && (hc[i].kind ? (hc[i].P.MD <= 5 && hc[i].P.nq <= 2) : hc[i].P.MD <= 6);
+  S->mdmax = small ? 6 : 8;
+  if (S->shm_prep > 65536 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_prep<R>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)S->shm_prep) != hipSuccess) {
+    *err = "hipFuncSetAttribute failed";
+    return FD_ERR_HIP;
+  }
+  int per_cu = 0, cus = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  BatchSweepArgs qa{};
+  qa.lds = lds;
+  qa.shm = S->shm_sweep;
+  const bool c64 = sizeof(R) == 4;
+  const hipError_t qe = S->mdmax == 6 ? batch_sweep_md6(c64, &qa, &per_cu, nullptr)
+                                      : batch_sweep_md8(c64, &qa, &per_cu, nullptr);
+  if (qe == hipSuccess && per_cu == -1) {
+    *err = "the batched sweep kernel was built with scratch memory; refusing its cooperative launch";
+    return FD_ERR_UNSUPPORTED;
+  }
+  if (qe != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      per_cu < 1) {
+    *err = "occupancy query for the batched sweep failed";
+    return FD_ERR_HIP;
+  }
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+    *err = "the device does not support cooperative launches";
+    return FD_ERR_UNSUPPORTED;
+  }
+  S->grid = per_cu * cus;
+  const int64_t waves = (int64_t)S->grid * lds.waves;
+
+  // work items, step-major; within a step larger circuits first, each step
+  // of a circuit cut into items of units / (items_per_wave x wavefronts)
+  // units, at least min_block_units / min_point_units
+  const fd_batch_tuning T = batch_tuning();
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  int max_steps = 0;
+  for (int i = 0; i < n; ++i) max_steps = std::max(max_steps, hc[i].steps);
+  const int64_t div = std::max<int64_t>(1, (int64_t)T.items_per_wave * waves);
+  S->h_items.clear();
+  S->h_steps.assign(1, 0);
+  for (int s = 0; s < max_steps; ++s) {
+    for (int i : order) {
+      if (s >= hc[i].steps) continue;
+      const int64_t pts = plans[i]->ncnt[s];
+      if (pts <= 0) continue;
+      const int64_t units = hc[i].kind ? pts * hc[i].G.nchunks : pts;
+      int64_t per = std::max<int64_t>(hc[i].kind ? T.min_block_units : T.min_point_units, (units + div - 1) / div);
+      if (!hc[i].kind) per = (per + 63) / 64 * 64;   // whole wavefronts of lattice points
+      for (int64_t u0 = 0; u0 < units; u0 += per) {
+        BatchItem I;
+        I.circ = i;
+        I.step = s;
+        I.u0 = (int)u0;
+        I.u1 = (int)std::min(units, u0 + per);
+        S->h_items.push_back(I);
+      }
+    }
+    S->h_steps.push_back((int)S->h_items.size());
+  }
+  S->nsteps = max_steps;
+  S->nitems = (int)S->h_items.size();
+  // permutation blocks
+  S->h_boff.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int64_t per_blk = (int64_t)kThreads * kOutIter;
+    S->h_boff[i + 1] = S->h_boff[i] + (hc[i].out_elems + per_blk - 1) / per_blk;
+  }
+  S->out_blocks = S->h_boff[n];
+  if (S->out_blocks > 0x7fffffff) {
+    *err = "batch output too large for one permutation launch";
+    return FD_ERR_UNSUPPORTED;
+  }
+  // upload
+  S->h_circs.resize(sizeof(BatchCirc<R>) * n);
+  std::memcpy(S->h_circs.data(), hc.data(), S->h_circs.size());
+  S->device = dev;
+  if (hipMalloc(&S->d_circs, S->h_circs.size()) != hipSuccess ||
+      hipMalloc(&S->d_items, std::max<size_t>(1, S->h_items.size()) * sizeof(BatchItem)) != hipSuccess ||
+      hipMalloc(&S->d_boff, S->h_boff.size() * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&S->d_steps, S->h_steps.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&S->d_ctl, ((size_t)S->nsteps + 1) * sizeof(unsigned)) != hipSuccess) {
+    free_sched(*S);
+    *err = "device allocation of the batch schedule failed";
+    return FD_ERR_OOM;
+  }
+  if (hipMemcpyAsync(S->d_circs, S->h_circs.data(), S->h_circs.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (S->nitems > 0 && hipMemcpyAsync(S->d_items, S->h_items.data(), S->h_items.size() * sizeof(BatchItem),
+                                       hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipMemcpyAsync(S->d_boff, S->h_boff.data(), S->h_boff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(S->d_steps, S->h_steps.data(), S->h_steps.size() * sizeof(int), hipMemcpyHostToDevice, st) !=
+          hipSuccess) {
+    free_sched(*S);
+    *err = "upload of the batch schedule failed";
+    return FD_ERR_HIP;
+  }
+  return FD_OK;
+}
+
+template <typename R>
+hipError_t launch_batch(const BatchSched& S, int n, const Plan& P0, hipStream_t st) {
+  const BatchCirc<R>* circs = static_cast<const BatchCirc<R>*>(S.d_circs);
+  unsigned* ctl = static_cast<unsigned*>(S.d_ctl);
+  {
+    KTimer kt(P0, KK_BATCH_PREP, st);
+    hipLaunchKernelGGL((k_batch_prep<R>), dim3(n), dim3(kThreads), S.shm_prep, st, circs, ctl, S.nsteps + 1);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (S.nitems > 0) {
+    KTimer kt(P0, KK_BATCH_SWEEP, st);
+    BatchSweepArgs a{};
+    a.circs = circs;
+    a.items = S.d_items;
+    a.step_off = static_cast<const int*>(S.d_steps);
+    a.nsteps = S.nsteps;
+    a.ctl = ctl;
+    a.status = P0.d_status;
+    a.lds = S.lds;
+    a.grid = S.grid;
+    a.shm = S.shm_sweep;
+    const bool c64 = sizeof(R) == 4;
+    e = S.mdmax == 6 ? batch_sweep_md6(c64, &a, nullptr, st) : batch_sweep_md8(c64, &a, nullptr, st);
+    if (e != hipSuccess) return e;
+  }
+  {
+    KTimer kt(P0, KK_BATCH_OUT, st);
+    hipLaunchKernelGGL((k_batch_out<R>), dim3((unsigned)S.out_blocks), dim3(kThreads), S.shm_out, st, circs,
+                       static_cast<const int64_t*>(S.d_boff), n, S.out_pn_bytes);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                            const void* const* b, const void* const* c, void* const* rho, void* const* ws,
+                            hipStream_t st, std::string* err) {
+  if (n == 0) return FD_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<uint64_t> key;
+  key.reserve(2 + 7 * (size_t)n);
+  key.push_back((uint64_t)dev);
+  key.push_back((uint64_t)n);
+  for (int i = 0; i < n; ++i) {
+    key.push_back(plans[i]->uid);
+    key.push_back(odd[i] ? 1 : 0);
+    for (const void* p : {A[i], b[i], c[i], (const void*)rho[i], (const void*)ws[i]})
+      key.push_back((uint64_t)reinterpret_cast<uintptr_t>(p));
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  key.push_back((uint64_t)g_tuning.min_block_units);
+  key.push_back((uint64_t)g_tuning.min_point_units);
+  key.push_back((uint64_t)g_tuning.items_per_wave);
+  BatchSched* S = nullptr;
+  for (BatchSched& s : g_cache)
+    if (s.key == key) S = &s;
+  if (!S) {
+    BatchSched ns;
+    ns.key = key;
+    for (int i = 0; i < n; ++i) ns.uids.push_back(plans[i]->uid);
+    const fd_status bs = plans[0]->dt == FD_C64 ? build_sched<float>(n, plans, odd, A, b, c, rho, ws, st, &ns, err)
+                                                : build_sched<double>(n, plans, odd, A, b, c, rho, ws, st, &ns, err);
+    if (bs != FD_OK) return bs;
+    if (g_cache.size() >= kBatchCache) {
+      auto it = std::min_element(g_cache.begin(), g_cache.end(),
+                                 [](const BatchSched& x, const BatchSched& y) { return x.last_use < y.last_use; });
+      free_sched(*it);
+      g_cache.erase(it);
+    }
+    g_cache.push_back(std::move(ns));
+    S = &g_cache.back();
+  }
+  S->last_use = ++g_clock;
+  const hipError_t e = plans[0]->dt == FD_C64 ? launch_batch<float>(*S, n, *plans[0], st)
+                                              : launch_batch<double>(*S, n, *plans[0], st);
+  if (e != hipSuccess) {
+    *err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+    return FD_ERR_HIP;
+  }
+  return FD_OK;
+}
+
+fd_status batch_set_tuning(const fd_batch_tuning& T) {
+  if (T.min_block_units < 1 || T.min_point_units < 1 || T.items_per_wave < 1)
+    return FD_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tuning = T;
+  return FD_OK;
+}
+
+fd_batch_tuning batch_get_tuning() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return g_tuning;
+}
+
+void batch_forget(uint64_t uid) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (size_t i = 0; i < g_cache.size();) {
+    if (std::find(g_cache[i].uids.begin(), g_cache[i].uids.end(), uid) != g_cache[i].uids.end()) {
+      free_sched(g_cache[i]);
+      g_cache.erase(g_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+}  // namespace fd

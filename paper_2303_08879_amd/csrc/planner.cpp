@@ -3,6 +3,7 @@
 // the undetected block of Algorithm 2).  Host-only: no device call here
 // except in ensure_device(), which uploads the tables on first use.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 
 #include "fd_internal.h"
@@ -15,6 +16,8 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
                      std::string* err) {
+  static std::atomic<uint64_t> next_uid{1};
+  P->uid = next_uid.fetch_add(1);
   if (M < 1 || M > kMaxModes) {
     *err = "M must be in [1, 16]";
     return FD_ERR_INVALID_ARG;

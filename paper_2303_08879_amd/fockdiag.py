@@ -24,12 +24,21 @@ FD_B_AUTO, FD_B_ZERO, FD_B_GENERAL = 0, 1, 2
 EXPORTS = [
     "fd_plan_create", "fd_plan_destroy", "fd_plan_workspace", "fd_plan_query", "fock_diag_fwd",
     "fock_diag_vjp", "detection_probs", "fock_diag_fwd_batch", "fd_last_error", "fd_device_status",
-    "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs",
+    "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs", "fd_batch_set_tuning", "fd_batch_get_tuning",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
- FD_K_VJP_FINAL, FD_K_ZERO) = range(9)
+ FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
 
 _lib = None
+
+
+class BatchTuning(ctypes.Structure):
+    """fd_batch_tuning: scheduling knobs of fock_diag_fwd_batch."""
+    _fields_ = [("min_block_units", ctypes.c_int32), ("min_point_units", ctypes.c_int32),
+                ("items_per_wave", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.min_block_units, self.min_point_units, self.items_per_wave)
 
 
 class FockDiagError(RuntimeError):
@@ -63,6 +72,8 @@ def lib():
     L.fd_plan_timing.argtypes = [vp, u32]
     L.fd_plan_use_graphs.argtypes = [vp, i32]
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
+    L.fd_batch_set_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+    L.fd_batch_get_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     for name in EXPORTS:
         if name != "fd_last_error":
             getattr(L, name).restype = i32
@@ -152,6 +163,17 @@ def fock_diag_fwd_batch(plans, As, bs, cs, rhos, workspaces, stream=None):
     sizes = (ctypes.c_size_t * n)(*[_nbytes(w) for w in workspaces])
     _check(lib().fock_diag_fwd_batch(n, P, mk(As), mk(bs), mk(cs), mk(rhos), mk(workspaces), sizes,
                                      _stream(stream)))
+
+
+def fd_batch_set_tuning(min_block_units, min_point_units, items_per_wave):
+    t = BatchTuning(int(min_block_units), int(min_point_units), int(items_per_wave))
+    _check(lib().fd_batch_set_tuning(ctypes.byref(t)))
+
+
+def fd_batch_get_tuning():
+    t = BatchTuning()
+    _check(lib().fd_batch_get_tuning(ctypes.byref(t)))
+    return t.as_tuple()
 
 
 def fd_device_status(plan, stream=None):

@@ -52,6 +52,17 @@ def detection_probs(A, b, c, cutoffs, dtype=torch.complex128, b_mode="auto", dev
     return probs
 
 
+def fock_diag_batch(triples, shapes, dtype=torch.complex128, b_mode="auto", device="cuda"):
+    """rho of every circuit of a batch in one batched call.  ``triples`` is a
+    list of (A, b, c), ``shapes`` a list of (cutoffs, detected_mask)."""
+    plans = [get_plan(cut, mask, dtype, b_mode) for cut, mask in shapes]
+    ins = [_as_inputs(A, b, c, dtype, device) for A, b, c in triples]
+    ws = [_workspace(p.workspace(False)[0], device) for p in plans]
+    rho = [torch.empty(p.out_shape, dtype=dtype, device=device) for p in plans]
+    F.fock_diag_fwd_batch(plans, [x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins], rho, ws)
+    return rho
+
+
 class FockDiagFunction(torch.autograd.Function):
     """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
     intermediate amplitudes (PyTorch's complex-gradient convention: the

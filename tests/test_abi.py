@@ -103,3 +103,35 @@ def test_planner_shapes_and_workspace():
     r = F.Plan([1, 5, 1], 0b101)
     assert r.out_shape == (5, 5, 1, 1)
     assert r.query(F.FD_Q_BLOCK) == 25
+
+
+def test_batch_rejects_bad_arguments_on_the_host():
+    L = F.lib()
+    assert L.fock_diag_fwd_batch(0, None, None, None, None, None, None, None, None) == F.FD_OK
+    assert L.fock_diag_fwd_batch(-1, None, None, None, None, None, None, None, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_diag_fwd_batch(2, None, None, None, None, None, None, None, None) == F.FD_ERR_INVALID_ARG
+    p = F.Plan([3, 3], 0b11)
+    q = F.Plan([3, 3], 0b11, dtype=__import__("torch").complex64)
+    n = 2
+    P = (ctypes.c_void_p * n)(p.handle.value, q.handle.value)
+    ptr = (ctypes.c_void_p * n)(256, 512)
+    sizes = (ctypes.c_size_t * n)(1 << 20, 1 << 20)
+    # mixed dtypes are refused before any device work
+    assert L.fock_diag_fwd_batch(n, P, ptr, ptr, ptr, ptr, ptr, sizes, None) == F.FD_ERR_INVALID_ARG
+    assert "dtype" in F.fd_last_error()
+    Pn = (ctypes.c_void_p * n)(p.handle.value, None)
+    assert L.fock_diag_fwd_batch(n, Pn, ptr, ptr, ptr, ptr, ptr, sizes, None) == F.FD_ERR_INVALID_ARG
+
+
+def test_batch_tuning_round_trip_and_range_checks():
+    old = F.fd_batch_get_tuning()
+    try:
+        F.fd_batch_set_tuning(3, 128, 5)
+        assert F.fd_batch_get_tuning() == (3, 128, 5)
+        for bad in [(0, 64, 2), (2, 0, 2), (2, 64, 0), (-4, 64, 2)]:
+            with pytest.raises(F.FockDiagError) as e:
+                F.fd_batch_set_tuning(*bad)
+            assert e.value.status == F.FD_ERR_INVALID_ARG
+        assert F.fd_batch_get_tuning() == (3, 128, 5)
+    finally:
+        F.fd_batch_set_tuning(*old)
