@@ -8,7 +8,12 @@ kept for the reverse sweep) + reverse sweep with a dense seeded cotangent,
 complex128.  `value` = output Fock amplitudes (entries of rho) per second of
 whole-step wall time, inputs already resident in HBM.
 
-Prints one JSON line.  See the design doc for the roofline accounting.
+Roofline: the dominant level kernel's algorithmic bytes (32 B per computed
+amplitude forward, 48 B reverse, complex128) over its HIP-event time, against
+8 TB/s.  The `batched` object times the 256-circuit uneven batch through the
+persistent batched launch and through a loop of per-circuit calls.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -61,6 +66,43 @@ def cpu_baseline(circ, rho_gpu, g_full, corner):
                 seconds=dt, sample_rel_err_gpu_vs_oracle=err)
 
 
+def batched_leg(reps=1):
+    """The uneven batch (256 circuits, M 3..6, cutoffs 8..16, 0 or 1 undetected
+    mode with cutoff 20..40, b = 0, complex128): batched persistent launches
+    (one per memory group) against a loop of per-circuit fock_diag_fwd calls on
+    the same stream, same buffers."""
+    import torch
+    from paper_2303_08879_amd import batching as Bt
+    from paper_2303_08879_amd import workloads as W
+    circs = W.config3()
+    runner = Bt.BatchRunner([(c.cutoffs, c.detected_mask) for c in circs], [(c.A, c.b, c.c) for c in circs],
+                            budget_bytes=int(150e9))
+    best, tune = Bt.autotune(runner, candidates=[(2, 64, 4), (4, 128, 2)], reps=1)
+    runner.check_status()
+
+    def timed(batched):
+        runner.run(batched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            runner.run(batched)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    tb = timed(True)
+    tl = timed(False)
+    runner.check_status()
+    n = len(circs)
+    out = dict(workload="config3: 256 circuits, M~U{3..6}, C_D~U{8..16}, 0/1 undetected mode C_U~U{20..40}, b=0, "
+                        "complex128", circuits=n, memory_groups=len(runner.groups),
+               batched_circuits_per_s=n / tb, loop_circuits_per_s=n / tl, speedup_vs_loop=tl / tb,
+               batched_s=tb, loop_s=tl, tuning=list(best),
+               tuning_trials_s={str(list(k)): v for k, v in tune.items()})
+    del runner
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +111,9 @@ def main():
     ap.add_argument("--workload", default="config2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-corner", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device-to-device copies (the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this library runs each circuit on a single device and "
@@ -79,6 +124,16 @@ def main():
     import torch
     from paper_2303_08879_amd import fockdiag as F
     from paper_2303_08879_amd import workloads as W
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: each copy reads and writes 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 5}), flush=True)
+        return
 
     circ, desc = workload(args.workload)
     dev = "cuda"
@@ -179,6 +234,8 @@ def main():
             "events_pass_ms_per_step": 1e3 * (t3 - t2) / args.steps,
         },
     }
+    if not args.no_batched:
+        line["batched"] = batched_leg()
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         step()

@@ -1,6 +1,13 @@
-"""Print the per-kernel table of a rocprofv3 SQLite output (kernel trace)."""
+"""Summaries of rocprofv3 output for the profiles/ notes.
+
+    python rocpd_summary.py <results.db>              per-kernel table (kernel trace)
+    python rocpd_summary.py --pmc <counter_collection.csv> [name-filter ...]
+                                                      mean counter value per dispatch
+"""
+import csv
 import sqlite3
 import sys
+from collections import defaultdict
 
 
 def summary(db):
@@ -14,5 +21,31 @@ def summary(db):
     return "\n".join(out)
 
 
+def pmc_summary(path, filters=()):
+    """Mean and total of every counter per kernel name over its dispatches
+    (rocprofv3 --output-format csv counter collection file)."""
+    acc = defaultdict(lambda: defaultdict(list))
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name", "")
+            if filters and not any(k in name for k in filters):
+                continue
+            short = name.split("(")[0].replace("void ", "")
+            acc[short][row["Counter_Name"]].append((row.get("Dispatch_Id"), float(row["Counter_Value"])))
+    out = ["| kernel | counter | dispatches | mean per dispatch | total |", "|---|---|---|---|---|"]
+    for name in sorted(acc):
+        for cn in sorted(acc[name]):
+            # one value per dispatch (values of one dispatch are summed over their dimensions)
+            per = defaultdict(float)
+            for d, v in acc[name][cn]:
+                per[d] += v
+            vals = list(per.values())
+            out.append(f"| `{name}` | {cn} | {len(vals)} | {sum(vals) / len(vals):.1f} | {sum(vals):.1f} |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
-    print(summary(sys.argv[1]))
+    if sys.argv[1] == "--pmc":
+        print(pmc_summary(sys.argv[2], sys.argv[3:]))
+    else:
+        print(summary(sys.argv[1]))

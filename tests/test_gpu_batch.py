@@ -146,3 +146,23 @@ def test_batch_rejects_overlapping_workspaces():
     with pytest.raises(F.FockDiagError) as e:
         F.fock_diag_fwd_batch(plans, [x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins], rho, [ws, ws])
     assert e.value.status == F.FD_ERR_INVALID_ARG
+
+
+def test_batch_runner_memory_groups_and_autotune():
+    from paper_2303_08879_amd import batching as Bt
+    circs = small_batch(351, 12)
+    runner = Bt.BatchRunner([(c.cutoffs, c.detected_mask) for c in circs], [(c.A, c.b, c.c) for c in circs],
+                            budget_bytes=1)            # the largest circuit alone sets the group size
+    assert len(runner.groups) > 1
+    old = F.fd_batch_get_tuning()
+    try:
+        best, times = Bt.autotune(runner, candidates=[(2, 64, 4), (1, 64, 1)])
+        assert best in times and F.fd_batch_get_tuning() == best
+        got = {}
+        runner.run(True, callback=lambda k, rho: got.update({i: r.cpu().numpy() for i, r in rho.items()}))
+        runner.check_status()
+        assert sorted(got) == list(range(len(circs)))
+        for i, c in enumerate(circs):
+            np.testing.assert_array_equal(got[i], run_single(c))
+    finally:
+        F.fd_batch_set_tuning(*old)
