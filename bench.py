@@ -43,6 +43,33 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a plain copy of known size), or None when the kernel
+    sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(HERE, "profiles", "hbm_traffic_config2.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_2303_08879_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 2 and parts[0] in ("source_sha256_16", "fetch_scale", "write_scale"):
+            vals[parts[0]] = parts[1]
+        elif len(parts) == 4 and parts[0] == "kib":
+            vals[parts[1]] = (float(parts[2]), float(parts[3]))
+    if vals.get("source_sha256_16") != h.hexdigest()[:16] or kernel not in vals:
+        return None
+    fetch, write = vals[kernel]
+    return 1024.0 * (fetch * float(vals["fetch_scale"]) + write * float(vals["write_scale"]))
+
+
 def cpu_baseline(circ, rho_gpu, g_full, corner):
     """The oracle, unchanged, on a bounded sample of the same workload: all
     conditional blocks rho[:, :, n] with every detected n_j < corner, forward
@@ -199,15 +226,21 @@ def main():
     vjp_gbs = vjp_bytes / (ms_v * 1e-3) / 1e9
     kind = "block" if plan.query(F.FD_Q_BLOCK) > 1 else "point"
     if ms_v >= ms_f:
-        dom = dict(kernel=f"k_vjp_{kind} (reverse level sweep)", achieved=vjp_gbs, launches=n_v,
-                   avg_launch_us=1e3 * ms_v / max(n_v, 1), bytes_per_unit=48)
+        dom = dict(kernel=f"k_vjp_{kind} (reverse level sweep)", short=f"k_vjp_{kind}", achieved=vjp_gbs,
+                   launches=n_v, avg_launch_us=1e3 * ms_v / max(n_v, 1), bytes_per_unit=48)
     else:
-        dom = dict(kernel=f"k_fwd_{kind} (forward level sweep)", achieved=fwd_gbs, launches=n_f,
-                   avg_launch_us=1e3 * ms_f / max(n_f, 1), bytes_per_unit=32)
+        dom = dict(kernel=f"k_fwd_{kind} (forward level sweep)", short=f"k_fwd_{kind}", achieved=fwd_gbs,
+                   launches=n_f, avg_launch_us=1e3 * ms_f / max(n_f, 1), bytes_per_unit=32)
+    # algorithmic bytes of one launch: bytes per computed amplitude x amplitudes per level launch
+    alg_per_launch = dom["bytes_per_unit"] * targets / max(dom["launches"] / args.steps, 1)
+    traffic = measured_traffic(dom["short"]) if args.workload == "config2" else None
     roof = {"bound": "hbm", "achieved": round(dom["achieved"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom["kernel"],
+            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 5),
+            "traffic": None if traffic is None else round(traffic), "kernel": dom["kernel"],
             "avg_launch_us": round(dom["avg_launch_us"], 3), "launches": dom["launches"],
-            "algorithmic_bytes_per_amplitude": dom["bytes_per_unit"]}
+            "algorithmic_bytes_per_amplitude": dom["bytes_per_unit"],
+            "algorithmic_bytes_per_launch": round(alg_per_launch),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_per_launch, 3)}
     flops_fwd = 8.0 * terms
     line = {
         "metric": METRIC,
