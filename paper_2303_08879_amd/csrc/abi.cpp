@@ -155,6 +155,7 @@ fd_status fd_plan_destroy(fd_plan p) {
     (void)hipFree(P.d_status);
     (void)hipFree(P.d_elist);
     (void)hipFree(P.d_woff);
+    (void)hipFree(P.d_node);
     (void)hipSetDevice(cur);
   }
   drop_graphs(P);

@@ -92,6 +92,7 @@ struct BatchLevel {
   BatchRing<R> rd, wr;
   const cx<R>* f0cur;
   cx<R>* f0nxt;
+  const int* node;
 };
 
 template <typename R>
@@ -106,6 +107,8 @@ __device__ __forceinline__ BatchLevel<R> batch_level(const BatchCirc<R>* __restr
   cx<R>* f0 = load_global(&C->f0);
   L.f0cur = f0 + (size_t)lvl[S] * B;
   L.f0nxt = S < C->P.smax ? f0 + (size_t)lvl[S + 1] * B : nullptr;
+  const int* node = load_global(&C->P.node);
+  L.node = node ? node + (size_t)lvl[S] * kNodeStride : nullptr;
   return L;
 }
 
@@ -129,7 +132,7 @@ __device__ __forceinline__ void run_block_item(const BatchCirc<R>* __restrict__ 
   cx<R>* lpk = lf0 + (size_t)(G.RC + 2) * G.R0;
   for (int u = I.u0; u < I.u1; ++u) {
     const int r = u / G.nchunks, ch = u - r * G.nchunks;
-    fwd_block_unit<MD, NQ, R>(C->P, L, sA, sA + NPOS * NPOS, spn, sq, isq, I.step, r, ch, G, lf0, lpk);
+    fwd_block_unit<MD, NQ, R>(C->P, L, sA, sA + NPOS * NPOS, sq, isq, I.step, r, ch, G, lf0, lpk);
   }
 }
 

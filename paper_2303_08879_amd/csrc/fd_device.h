@@ -68,14 +68,29 @@ __device__ __forceinline__ void st(cx<float>* p, const cx<float>& a) {
 
 // Per-launch node-0 pointers of every family at the levels a sweep step
 // touches: rd = level S-1 (reads), wr = level S (writes), plus F0 at S and
-// S+1.  Entries of families not used by the schedule are null.
+// S+1, and the node records of level S (Algorithm 2 plans).  Entries of
+// families not used by the schedule are null.
 template <typename R>
 struct LevelPtrs {
   const cx<R>* rd[kMaxFam];
   cx<R>* wr[kMaxFam];
   const cx<R>* f0cur;
   cx<R>* f0nxt;
+  const int* node;
 };
+
+// Node record of lattice point r of the level: m, the ranks of m - 1_j at
+// level S-1 and of m + 1_j at level S+1 (one scalar load per unit).
+template <int MD>
+__device__ __forceinline__ void node_record(const int* node, int r, int* m, int* rdn, int* rup) {
+  const int* nr = node + (size_t)r * kNodeStride;
+#pragma unroll
+  for (int j = 0; j < MD; ++j) {
+    m[j] = nr[j];
+    rdn[j] = nr[MD + j];
+    rup[j] = nr[2 * MD + j];
+  }
+}
 
 // Orders LDS traffic between the lanes of one wavefront: LDS operations of a
 // wavefront execute in order, so only compiler reordering has to be stopped.
@@ -86,6 +101,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+
+// Coordinate q of an undetected-block entry: floor(rem / ustride[q]) for
+// 0 <= rem < 4096 without an integer division.  (rem + 1/2) / ustride lies at
+// least 1 / (2 ustride) >= 2^-13 away from an integer, while one double
+// multiply by the rounded reciprocal is off by under 2^-38 for rem < 4096, so
+// truncating the product is exact.
+__device__ __forceinline__ int ucoord(const DevPlan& P, int rem, int q) { return (int)((rem + 0.5) * P.uinv[q]); }
 
 // PN[d][x] for x in [-1, smax+1]; table row width pnw.
 __device__ __forceinline__ int pnv(const int* spn, int pnw, int d, int x) { return spn[d * pnw + x + 1]; }

@@ -48,6 +48,7 @@ constexpr int kPnMax = (kMaxD + 1) * (kMaxSmax + 3);
 constexpr int kPartialSlots = 4096;      // deterministic VJP partial accumulators
 constexpr int kThreads = 256;
 constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
+constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
 
 enum FamType { F_F0 = 0, F_F1K, F_F1B, F_F2, F_1010, F_1001 };
 
@@ -71,8 +72,10 @@ struct DevPlan {
   int CD[kMaxD];             // detected cutoffs (all >= 2)
   int udims[kMaxUq];         // U block dims [C_u.., C_u..]
   int ustride[kMaxUq];
+  double uinv[kMaxUq];       // 1 / ustride (exact coordinate split, see ucoord)
   const int* pn;             // [(MD+1) x pnw]: PN[d][s+1] = #points of sub-box d with sum <= s
   const int64_t* lvl;        // [(MD) x (smax+2)]: node offset of level S for group g (store-all)
+  const int* node;           // Algorithm 2 plans: node records in level-major order (else null)
   int64_t ringN[kMaxD];      // ring slot stride in nodes per group (ring mode)
 };
 
@@ -136,6 +139,7 @@ struct Plan {
   int device = -1;
   int* d_pn = nullptr;
   int64_t* d_lvl = nullptr;
+  int* d_node = nullptr;             // node records (Algorithm 2 plans)
   int* d_status = nullptr;
   // undetected-block fill order (step 1 of Algorithm 2): entries sorted by weight
   std::vector<int> elist, woff;

@@ -85,7 +85,7 @@ __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __rest
       int rem = e;
 #pragma unroll
       for (int q = 0; q < kMaxUq; ++q) {
-        kap[q] = q < nq ? rem / P.ustride[q] : 0;
+        kap[q] = q < nq ? ucoord(P, rem, q) : 0;
         rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
       }
       int qf = nq;
@@ -236,19 +236,17 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 // ---------------------------------------------------------------------------
 template <int MD, int NQ, typename R, typename LP>
 __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const cx<R>* sA, const cx<R>* sb,
-                                               const int* spn, const R* sq, const R* isq, int S, int r, int c,
-                                               const ChunkGeo& G, cx<R>* lf0, cx<R>* lpk) {
+                                               const R* sq, const R* isq, int S, int r, int c, const ChunkGeo& G,
+                                               cx<R>* lf0, cx<R>* lpk) {
   constexpr int NPD = 2 * MD;
   constexpr int NPOS = NQ + NPD;
   const int B = P.B, R0 = G.R0;
   const int lane = threadIdx.x & 63;
-  const int pnw = P.pnw;
   const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
   {
     const int k0 = c * G.RC, k1 = min(G.C0, k0 + G.RC);
-    int m[MD], s[MD + 1], rdn[MD], rup[MD];
-    unrank<MD>(spn, pnw, P.CD, S, r, m, s);
-    neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+    int m[MD], rdn[MD], rup[MD];
+    node_record<MD>(L.node, r, m, rdn, rup);
     int K0 = MD;
 #pragma unroll
     for (int d = MD - 1; d >= 0; --d)
@@ -272,7 +270,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
         int rem = e;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          kap[q] = rem / P.ustride[q];
+          kap[q] = ucoord(P, rem, q);
           rem -= kap[q] * P.ustride[q];
         }
         const int le = e - (k0 - 2) * R0;
@@ -325,7 +323,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
         int rem = e;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          kap[q] = rem / P.ustride[q];
+          kap[q] = ucoord(P, rem, q);
           rem -= kap[q] * P.ustride[q];
         }
         const int lp = e - (k0 - 1) * R0;

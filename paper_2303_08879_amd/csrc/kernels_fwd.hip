@@ -53,13 +53,16 @@ __global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, co
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
-  int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
-  load_tables(P, spn, sq, isq);
+  for (int v = threadIdx.x; v < kMaxCut + 4; v += blockDim.x) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
   for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
-  __syncthreads();
+  // one wavefront per workgroup: the unit's first wave_sync orders these
+  // LDS writes before their reads
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
-    fwd_block_unit<MD, NQ, R>(P, L, sA, sb, spn, sq, isq, S, r, c, G, lf0, lpk);
+    fwd_block_unit<MD, NQ, R>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk);
   }
 }
 
@@ -138,7 +141,7 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
   } else {
     const ChunkGeo G = chunk_geo(Pl);
     const size_t shm = (((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
-                           sizeof(cx<R>) + tab;
+                           sizeof(cx<R>) + 2 * (kMaxCut + 4) * sizeof(R);
     const int grid = nwork * G.nchunks;
 #define FD_LAUNCH_BLOCK(MDV)                                                                               \
   case MDV:                                                                                                \
@@ -246,6 +249,7 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
       L.wr[f] = fam_level_ptr<R>(Pl, fb, LF.fam[f], g, S, !store_all);
     }
     L.f0cur = fam_level_ptr<R>(Pl, fb, LF.f0, 0, S, false);
+    L.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
     L.f0nxt = S < Pl.smax ? fam_level_ptr<R>(Pl, fb, LF.f0, 0, S + 1, false) : nullptr;
     {
       KTimer kt(Pl, KK_FWD_LEVEL, st);

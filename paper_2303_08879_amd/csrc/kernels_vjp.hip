@@ -33,6 +33,7 @@ struct VjpPtrs {
   cx<R>* gcur[kMaxFam];         // cotangent ring slot of level S (gcur[0] = F0)
   const cx<R>* gf0nxt;          // F0 cotangents, level S+1
   const cx<R>* d0cur;           // drho in node order, level S
+  const int* node;              // node records of level S (Algorithm 2 plans)
 };
 
 __global__ void k_zero_d2(double2* p, int64_t n) {
@@ -330,23 +331,24 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
-  int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
-  load_tables_v(P, spn, sq, isq);
+  for (int v = threadIdx.x; v < kMaxCut + 4; v += blockDim.x) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
   for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
-  __syncthreads();
+  // (one wavefront per workgroup: every phase of a unit starts with a staging
+  // loop and a barrier before it reads these tables)
   cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWStride * (NPD + NR);
   cx<double> acc[PPL];
 #pragma unroll
   for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
-  const int pnw = P.pnw;
 
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
     const int k0 = c * RC, k1 = min(G.C0, k0 + RC);
     const int e_own0 = k0 * R0, e_own1 = k1 * R0;
-    int m[MD], s[MD + 1], rdn[MD], rup[MD];
-    unrank<MD>(spn, pnw, P.CD, S, r, m, s);
-    neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
+    int m[MD], rdn[MD], rup[MD];
+    node_record<MD>(V.node, r, m, rdn, rup);
     int K0 = MD;
 #pragma unroll
     for (int d = MD - 1; d >= 0; --d)
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
           int rem = e;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            kap[q] = rem / P.ustride[q];
+            kap[q] = ucoord(P, rem, q);
             rem -= kap[q] * P.ustride[q];
           }
           h[2 * K + 1] = cscale(ld(V.gf0nxt + (size_t)rup[K] * B + e), isq[m[K] + 1]);
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
         if (has_diag_reader) v = cadd(v, ld(V.gcur[fam_f1k(K)] + rB + e));
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const int kq = rem / P.ustride[q];
+          const int kq = ucoord(P, rem, q);
           rem -= kq * P.ustride[q];
           if (kq + 1 < P.udims[q]) v = cadd(v, cscale(qv[(size_t)q * nrow2 + le + P.ustride[q]], sq[kq + 1]));
         }
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
           int rem = e;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            kap[q] = rem / P.ustride[q];
+            kap[q] = ucoord(P, rem, q);
             rem -= kap[q] * P.ustride[q];
           }
           const int le = e - e_own0;
@@ -536,7 +538,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
         cx<R> v = g0a[le];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          const int kq = rem / P.ustride[q];
+          const int kq = ucoord(P, rem, q);
           rem -= kq * P.ustride[q];
           if (kq + 1 < P.udims[q]) v = cadd(v, cscale(qv[(size_t)q * nrow2 + le + P.ustride[q]], sq[kq + 1]));
         }
@@ -600,7 +602,7 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
       int rem = e;
 #pragma unroll
       for (int q = 0; q < kMaxUq; ++q) {
-        x[q] = q < nq ? rem / P.ustride[q] : 0;
+        x[q] = q < nq ? ucoord(P, rem, q) : 0;
         rem -= x[q] * (q < nq ? P.ustride[q] : 0);
       }
       int first0 = nq;
@@ -808,6 +810,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     Vp.gf0nxt = gptr<R>(Pl, ws, V.gfam[0], 0, S + 1);
     Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
                                               (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
+    Vp.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
     const int nwork = (int)Pl.ncnt[S];
     KTimer kt(Pl, KK_VJP_LEVEL, st);
     if (Pl.B == 1) {
@@ -853,7 +856,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
                           (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (kWRec + 1) * (NPD + NR);
       const size_t ppl = (size_t)(NPD * NR + 63) / 64;
       const size_t shm = std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * sizeof(cx<R>),
-                                  (size_t)kBT * ppl * sizeof(cx<double>)) + tab;
+                                  (size_t)kBT * ppl * sizeof(cx<double>)) + 2 * (kMaxCut + 4) * sizeof(R);
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \

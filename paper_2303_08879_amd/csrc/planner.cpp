@@ -109,6 +109,10 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     }
   }
   P->nodes_total = nt;
+  if (P->B > 1 && nt > (int64_t(1) << 22)) {
+    *err = "with undetected modes the product of detected cutoffs must be <= 2^22 (node records)";
+    return FD_ERR_UNSUPPORTED;
+  }
   const int MD = P->MD;
   int smax = 0;
   for (int c : P->CD) smax += c - 1;
@@ -231,9 +235,11 @@ DevPlan make_devplan(const Plan& P, bool odd) {
   for (int q = 0; q < P.nq; ++q) {
     d.udims[q] = P.udims[q];
     d.ustride[q] = P.ustride[q];
+    d.uinv[q] = 1.0 / P.ustride[q];
   }
   d.pn = P.d_pn;
   d.lvl = P.d_lvl;
+  d.node = P.d_node;
   for (int g = 0; g < std::max(P.MD, 1); ++g) d.ringN[g] = P.maxN[g];
   return d;
 }
@@ -295,6 +301,55 @@ size_t vjp_lds_bytes(const Plan& P) {
          2 * (kMaxCut + 4) * rdt + (size_t)(P.MD + 1) * (P.smax + 3) * 4;
 }
 
+// Rank of lattice point v within its level (lexicographic, first mode
+// slowest): sum over d of #points of sub-box d+1 whose sum lies in
+// (s_d - v_d, s_d], with s_d the sum of v over modes d...MD-1.
+static int64_t host_rank(const Plan& P, const int* v) {
+  const int pnw = P.smax + 3;
+  int sd = 0;
+  for (int j = 0; j < P.MD; ++j) sd += v[j];
+  int64_t r = 0;
+  for (int d = 0; d < P.MD; ++d) {
+    r += P.pn[(size_t)(d + 1) * pnw + sd + 1] - P.pn[(size_t)(d + 1) * pnw + sd - v[d] + 1];
+    sd -= v[d];
+  }
+  return r;
+}
+
+// Node records of an Algorithm 2 plan: for every lattice point m (level-major
+// order) m itself, the rank of m - 1_j at level |m| - 1 (-1 if m_j = 0) and
+// the rank of m + 1_j at level |m| + 1 (-1 outside the box).  The block
+// kernels read a unit's record with one scalar load instead of unranking.
+static bool build_node_table(const Plan& P, std::vector<int>* out, std::string* err) {
+  const int MD = P.MD;
+  out->assign((size_t)P.nodes_total * kNodeStride, -1);
+  std::vector<int> m(MD, 0), v(MD);
+  for (int64_t it = 0; it < P.nodes_total; ++it) {
+    int S = 0;
+    for (int j = 0; j < MD; ++j) S += m[j];
+    const int64_t r = host_rank(P, m.data());
+    const int64_t id = P.lvl[S] + r;
+    if (r < 0 || r >= P.ncnt[S] || id >= P.nodes_total || (*out)[(size_t)id * kNodeStride] != -1) {
+      *err = "internal: lattice ranks are not a bijection";
+      return false;
+    }
+    int* rec = out->data() + (size_t)id * kNodeStride;
+    for (int j = 0; j < MD; ++j) {
+      rec[j] = m[j];
+      v = m;
+      v[j] -= 1;
+      rec[MD + j] = m[j] > 0 ? (int)host_rank(P, v.data()) : -1;
+      v[j] += 2;
+      rec[2 * MD + j] = m[j] + 1 < P.CD[j] ? (int)host_rank(P, v.data()) : -1;
+    }
+    for (int j = MD - 1; j >= 0; --j) {
+      if (++m[j] < P.CD[j]) break;
+      m[j] = 0;
+    }
+  }
+  return true;
+}
+
 fd_status ensure_device(Plan* P, std::string* err) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
@@ -322,6 +377,18 @@ fd_status ensure_device(Plan* P, std::string* err) {
       hipMemset(P->d_status, 0, 256) != hipSuccess) {
     *err = "upload of plan tables failed";
     return FD_ERR_HIP;
+  }
+  if (P->B > 1 && P->MD > 0) {
+    std::vector<int> nt;
+    if (!build_node_table(*P, &nt, err)) return FD_ERR_HIP;
+    if (hipMalloc((void**)&P->d_node, nt.size() * sizeof(int)) != hipSuccess) {
+      *err = "hipMalloc of the node table failed";
+      return FD_ERR_OOM;
+    }
+    if (hipMemcpy(P->d_node, nt.data(), nt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      *err = "upload of the node table failed";
+      return FD_ERR_HIP;
+    }
   }
   P->device = dev;
   return FD_OK;

@@ -135,3 +135,14 @@ def test_batch_tuning_round_trip_and_range_checks():
         assert F.fd_batch_get_tuning() == (3, 128, 5)
     finally:
         F.fd_batch_set_tuning(*old)
+
+
+def test_exact_reciprocal_coordinate_split():
+    # the device splits an undetected-block entry index into coordinates with
+    # trunc((rem + 0.5) * (1 / stride)) in double precision instead of an
+    # integer division; exhaustively equal to floor division on its range
+    import numpy as np
+    rem = np.arange(4096, dtype=np.float64)
+    for d in range(1, 4097):
+        q = ((rem + 0.5) * (1.0 / d)).astype(np.int64)
+        assert np.array_equal(q, np.arange(4096) // d), d
