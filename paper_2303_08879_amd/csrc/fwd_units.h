@@ -404,4 +404,55 @@ __device__ __forceinline__ cx<R> out_perm_elem(const DevPlan& P, const int* spn,
   return ld(f0 + (size_t)(slv[S] + rank) * B + kap);
 }
 
+// F0 -> rho for plans with undetected modes, one tile of kOutTN consecutive
+// C-order lattice points n by kOutTK consecutive block entries kappa, through
+// LDS: every node's kOutTK entries are read as one contiguous run and every
+// kappa's kOutTN outputs written as one (the element-wise gather reads a
+// 64-byte sector per 16-byte element).  256 threads; returns 1 if a
+// non-finite value was stored.
+constexpr int kOutTN = 64, kOutTK = 16;
+template <typename R>
+__device__ __forceinline__ int out_perm_tile(const DevPlan& P, const int* spn, const int64_t* slv,
+                                             const cx<R>* __restrict__ f0, cx<R>* __restrict__ rho, int64_t N,
+                                             int64_t tile, cx<R>* tl) {
+  const int MD = P.MD, B = P.B, pnw = P.pnw;
+  const int64_t ntn = (N + kOutTN - 1) / kOutTN;
+  const int64_t tn = tile % ntn, tk = tile / ntn;
+  const int64_t n0 = tn * kOutTN;
+  const int kap0 = (int)tk * kOutTK;
+  constexpr int LD = kOutTK + 1;   // padded row: the column reads of the write phase spread over banks
+  const int kl = threadIdx.x % kOutTK;
+  for (int nl = threadIdx.x / kOutTK; nl < kOutTN; nl += kThreads / kOutTK) {
+    const int64_t n = n0 + nl;
+    if (n < N && kap0 + kl < B) {
+      int64_t rem = n;
+      int v[kMaxD];
+      int S = 0;
+      for (int d = MD - 1; d >= 0; --d) {
+        v[d] = (int)(rem % P.CD[d]);
+        rem /= P.CD[d];
+        S += v[d];
+      }
+      int rank = 0, sd = S;
+      for (int d = 0; d < MD; ++d) {
+        rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - v[d]);
+        sd -= v[d];
+      }
+      tl[nl * LD + kl] = ld(f0 + (size_t)(slv[S] + rank) * B + kap0 + kl);
+    }
+  }
+  __syncthreads();
+  int bad = 0;
+  const int nl = threadIdx.x % kOutTN;
+  for (int k = threadIdx.x / kOutTN; k < kOutTK; k += kThreads / kOutTN) {
+    if (n0 + nl < N && kap0 + k < B) {
+      const cx<R> v = tl[nl * LD + k];
+      if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+      st(rho + (size_t)(kap0 + k) * N + n0 + nl, v);
+    }
+  }
+  __syncthreads();
+  return bad;
+}
+
 }  // namespace fd

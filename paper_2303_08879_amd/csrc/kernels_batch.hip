@@ -37,10 +37,12 @@ __global__ __launch_bounds__(kThreads) void k_batch_prep(const BatchCirc<R>* __r
 }
 
 // F0 -> rho of every circuit; block b belongs to the circuit c with
-// boff[c] <= b < boff[c + 1].
+// boff[c] <= b < boff[c + 1] and is one LDS tile of it (undetected modes) or
+// kThreads x kOutIter consecutive outputs (every mode detected).
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_batch_out(const BatchCirc<R>* __restrict__ circs,
-                                                        const int64_t* __restrict__ boff, int n, int pn_bytes) {
+                                                        const int64_t* __restrict__ boff, int n, int pn_bytes,
+                                                        int slv_bytes) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t blk = blockIdx.x;
   int lo = 0, hi = n - 1;
@@ -60,9 +62,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_out(const BatchCirc<R>* __re
   for (int i = threadIdx.x; i < npn; i += blockDim.x) spn[i] = pn[i];
   for (int i = threadIdx.x; i <= C->P.smax; i += blockDim.x) slv[i] = C->P.MD > 0 ? lvl[i] : 0;
   __syncthreads();
-  const int64_t base = (blk - boff[lo]) * (int64_t)kThreads * kOutIter;
   const cx<R>* f0 = load_global(&C->f0);
   cx<R>* rho = load_global(&C->rho);
+  if (C->P.B > 1) {
+    cx<R>* tl = reinterpret_cast<cx<R>*>(smem_raw + pn_bytes + slv_bytes);
+    if (out_perm_tile<R>(C->P, spn, slv, f0, rho, C->N, blk - boff[lo], tl)) atomicOr(load_global(&C->status), 1);
+    return;
+  }
+  const int64_t base = (blk - boff[lo]) * (int64_t)kThreads * kOutIter;
   int bad = 0;
 #pragma unroll
   for (int k = 0; k < kOutIter; ++k) {
@@ -94,7 +101,7 @@ struct BatchSched {
   int64_t out_blocks = 0;
   BatchLds lds{};
   size_t shm_prep = 0, shm_sweep = 0, shm_out = 0;
-  int out_pn_bytes = 0;
+  int out_pn_bytes = 0, out_slv_bytes = 0;
   int grid = 0;
   int mdmax = 8;
   uint64_t last_use = 0;
@@ -197,7 +204,8 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
   S->shm_sweep = kTabBytes + (size_t)lds.waves * lds.wave_bytes;
   S->shm_prep = ufill_lds;
   S->out_pn_bytes = out_pn;
-  S->shm_out = (size_t)out_pn + out_slv;
+  S->out_slv_bytes = (int)align16((size_t)out_slv);
+  S->shm_out = (size_t)out_pn + S->out_slv_bytes + (size_t)kOutTN * (kOutTK + 1) * eb;
 
   // persistent grid: every workgroup that fits at once
   bool small = true;   // within the (6, 5, 2) build
@@ -272,7 +280,9 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
   S->h_boff.assign(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const int64_t per_blk = (int64_t)kThreads * kOutIter;
-    S->h_boff[i + 1] = S->h_boff[i] + (hc[i].out_elems + per_blk - 1) / per_blk;
+    const int64_t blocks = hc[i].P.B > 1 ? ((hc[i].N + kOutTN - 1) / kOutTN) * ((hc[i].P.B + kOutTK - 1) / kOutTK)
+                                         : (hc[i].out_elems + per_blk - 1) / per_blk;
+    S->h_boff[i + 1] = S->h_boff[i] + blocks;
   }
   S->out_blocks = S->h_boff[n];
   if (S->out_blocks > 0x7fffffff) {
@@ -335,7 +345,7 @@ hipError_t launch_batch(const BatchSched& S, int n, const Plan& P0, hipStream_t 
   {
     KTimer kt(P0, KK_BATCH_OUT, st);
     hipLaunchKernelGGL((k_batch_out<R>), dim3((unsigned)S.out_blocks), dim3(kThreads), S.shm_out, st, circs,
-                       static_cast<const int64_t*>(S.d_boff), n, S.out_pn_bytes);
+                       static_cast<const int64_t*>(S.d_boff), n, S.out_pn_bytes, S.out_slv_bytes);
   }
   return hipGetLastError();
 }

@@ -79,11 +79,17 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
   for (int i = threadIdx.x; i <= P.smax; i += blockDim.x) slv[i] = P.MD > 0 ? P.lvl[i] : 0;
   __syncthreads();
   int bad = 0;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const cx<R> v = out_perm_elem<R>(P, spn, slv, f0, N, idx);
-    if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
-    st(rho + idx, v);
+  if (P.B > 1) {
+    cx<R>* tl = reinterpret_cast<cx<R>*>(reinterpret_cast<unsigned char*>(slv) + 16 * (((P.smax + 2) * 8 + 15) / 16));
+    const int64_t tiles = ((N + kOutTN - 1) / kOutTN) * ((P.B + kOutTK - 1) / kOutTK);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) bad |= out_perm_tile<R>(P, spn, slv, f0, rho, N, t, tl);
+  } else {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+      const cx<R> v = out_perm_elem<R>(P, spn, slv, f0, N, idx);
+      if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+      st(rho + idx, v);
+    }
   }
   if (bad) atomicOr(status, 1);
 }
@@ -260,7 +266,8 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
   const int64_t total = Pl.out_elems;
   const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
-  const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;
+  const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) +
+                     16 * (((size_t)(Pl.smax + 2) * 8 + 15) / 16) + (size_t)kOutTN * (kOutTK + 1) * sizeof(cx<R>);
   KTimer kt(Pl, KK_OUT_PERM, st);
   hipLaunchKernelGGL((k_out_perm<R>), dim3(grid), dim3(kThreads), shm, st, P, f0, reinterpret_cast<cx<R>*>(rho),
                      (int64_t)Pl.nodes_total, total, Pl.d_status);
