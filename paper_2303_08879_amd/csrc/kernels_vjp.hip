@@ -747,6 +747,17 @@ static ChunkGeo chunk_geo_v(const Plan& Pl) {
   return G;
 }
 
+// Dynamic LDS of k_vjp_block for this plan (exact; the launcher uses it).
+size_t vjp_lds_bytes(const Plan& Pl) {
+  const ChunkGeo G = chunk_geo_v(Pl);
+  const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
+  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
+  const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
+                      (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (kWRec + 1) * (NPD + NR);
+  const size_t ppl = (size_t)(NPD * NR + 63) / 64;
+  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)kBT * ppl * 16) + 2 * (kMaxCut + 4) * rb;
+}
+
 template <typename R>
 static const cx<R>* fptr(const Plan& Pl, const char* base, size_t off, int g, int S) {
   if (S < 0 || off == 0) return nullptr;
@@ -851,12 +862,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
 #undef FD_VJP_POINT
     } else {
       const ChunkGeo G = chunk_geo_v(Pl);
-      const int NPD = 2 * MD, NR = Pl.npos + 1;
-      const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                          (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (kWRec + 1) * (NPD + NR);
-      const size_t ppl = (size_t)(NPD * NR + 63) / 64;
-      const size_t shm = std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * sizeof(cx<R>),
-                                  (size_t)kBT * ppl * sizeof(cx<double>)) + 2 * (kMaxCut + 4) * sizeof(R);
+      const size_t shm = vjp_lds_bytes(Pl);
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \

@@ -294,12 +294,6 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   return L;
 }
 
-size_t vjp_lds_bytes(const Plan& P) {
-  const size_t eb = elem_bytes(P.dt);
-  const size_t rdt = P.dt == FD_C64 ? 4 : 8;
-  return (size_t)(1 + P.nq) * P.B * eb + (size_t)(2 * P.npos + 1) * 64 * eb + 256 * 16 +
-         2 * (kMaxCut + 4) * rdt + (size_t)(P.MD + 1) * (P.smax + 3) * 4;
-}
 
 // Rank of lattice point v within its level (lexicographic, first mode
 // slowest): sum over d of #points of sub-box d+1 whose sum lies in
