@@ -187,6 +187,20 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
                               const void* const* b, const void* const* c, void* const* rho,
                               void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
 
+/* Batched reverse sweep: fock_diag_vjp for n circuits (arrays of n entries as
+ * in fock_diag_fwd_batch; saved may be NULL, or hold NULL entries, to
+ * recompute those circuits' forward values in their workspaces).  A reverse
+ * sweep keeps every forward intermediate of its circuit (9.9 GB for a
+ * 6-mode circuit with a 30-photon undetected mode and 8-photon detected
+ * modes) and fills the device on its own, so the circuits run one after
+ * another on `stream`; unlike the forward batch, circuits may share one
+ * workspace (the calls are stream-ordered).  Results equal fock_diag_vjp's
+ * bit for bit.  Stops at the first failing circuit and returns its status. */
+fd_status fock_diag_vjp_batch(int n, const fd_plan* plans, const void* const* A, const void* const* b,
+                              const void* const* c, const void* const* saved, const size_t* saved_bytes,
+                              const void* const* drho, void* const* dA, void* const* db, void* const* dc,
+                              void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
+
 /* Scheduling knobs of fock_diag_fwd_batch (process-wide; a schedule built
  * under other knobs is rebuilt on next use): every step of a circuit is cut
  * into items of units / (items_per_wave x resident wavefronts) units, at

@@ -332,6 +332,22 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
   return ok();
 }
 
+fd_status fock_diag_vjp_batch(int n, const fd_plan* plans, const void* const* A, const void* const* b,
+                              const void* const* c, const void* const* saved, const size_t* saved_bytes,
+                              const void* const* drho, void* const* dA, void* const* db, void* const* dc,
+                              void* const* workspace, const size_t* ws_bytes, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!plans || !A || !b || !c || !drho || !dA || !db || !dc || !workspace || !ws_bytes)))
+    return fail(FD_ERR_INVALID_ARG, "bad batch arguments");
+  for (int i = 0; i < n; ++i) {
+    const void* sv = saved ? saved[i] : nullptr;
+    const size_t sb = (saved && saved_bytes) ? saved_bytes[i] : 0;
+    fd_status s = fock_diag_vjp(plans[i], A[i], b[i], c[i], sv, sb, drho[i], dA[i], db[i], dc[i], workspace[i],
+                                ws_bytes[i], stream);
+    if (s != FD_OK) return fail(s, "circuit " + std::to_string(i) + ": " + g_err);
+  }
+  return ok();
+}
+
 fd_status fd_batch_set_tuning(const fd_batch_tuning* t) {
   if (!t) return fail(FD_ERR_INVALID_ARG, "tuning is NULL");
   if (fd::batch_set_tuning(*t) != FD_OK) return fail(FD_ERR_INVALID_ARG, "batch tuning values out of range");

@@ -25,6 +25,7 @@ EXPORTS = [
     "fd_plan_create", "fd_plan_destroy", "fd_plan_workspace", "fd_plan_query", "fock_diag_fwd",
     "fock_diag_vjp", "detection_probs", "fock_diag_fwd_batch", "fd_last_error", "fd_device_status",
     "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs", "fd_batch_set_tuning", "fd_batch_get_tuning",
+    "fock_diag_vjp_batch",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -66,6 +67,8 @@ def lib():
     L.fock_diag_fwd_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(sz), vp]
+    L.fock_diag_vjp_batch.argtypes = [i32] + [ctypes.POINTER(vp)] * 5 + [ctypes.POINTER(sz)] + \
+        [ctypes.POINTER(vp)] * 5 + [ctypes.POINTER(sz), vp]
     L.fd_last_error.argtypes = []
     L.fd_last_error.restype = ctypes.c_char_p
     L.fd_device_status.argtypes = [vp, vp]
@@ -174,6 +177,18 @@ def fd_batch_get_tuning():
     t = BatchTuning()
     _check(lib().fd_batch_get_tuning(ctypes.byref(t)))
     return t.as_tuple()
+
+
+def fock_diag_vjp_batch(plans, As, bs, cs, saveds, drhos, dAs, dbs, dcs, workspaces, stream=None):
+    """saveds: list of tensors or None entries (recompute), or None for all."""
+    n = len(plans)
+    arr = lambda ts: (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in ts])
+    szs = lambda ts: (ctypes.c_size_t * n)(*[_nbytes(t) for t in ts])
+    P = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    saveds = saveds if saveds is not None else [None] * n
+    _check(lib().fock_diag_vjp_batch(n, P, arr(As), arr(bs), arr(cs), arr(saveds), szs(saveds), arr(drhos),
+                                     arr(dAs), arr(dbs), arr(dcs), arr(workspaces), szs(workspaces),
+                                     _stream(stream)))
 
 
 def fd_device_status(plan, stream=None):

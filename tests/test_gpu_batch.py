@@ -166,3 +166,32 @@ def test_batch_runner_memory_groups_and_autotune():
             np.testing.assert_array_equal(got[i], run_single(c))
     finally:
         F.fd_batch_set_tuning(*old)
+
+
+def test_vjp_batch_matches_single_calls():
+    circs = small_batch(361, 6, b_general=True)
+    dt = torch.complex128
+    plans = [ops.get_plan(c.cutoffs, c.detected_mask, dt, "general") for c in circs]
+    ins = [ops._as_inputs(c.A, c.b, c.c, dt, "cuda") for c in circs]
+    saved, ws, g, outs = [], [], [], []
+    for k, (p, c) in enumerate(zip(plans, circs)):
+        wb, sb = p.workspace(True)
+        w = ops._workspace(wb + sb + 4096, "cuda")     # room to recompute when saved is None
+        s = ops._workspace(sb, "cuda")
+        rho = torch.empty(p.out_shape, dtype=dt, device="cuda")
+        F.fock_diag_fwd(p, *ins[k], rho, ops._workspace(wb, "cuda"), s)
+        saved.append(s if k % 2 == 0 else None)
+        ws.append(w)
+        g.append(torch.tensor(W.random_cotangent(p.out_shape, 50 + k), dtype=dt, device="cuda"))
+    dA = [torch.empty_like(x[0]) for x in ins]
+    db = [torch.empty_like(x[1]) for x in ins]
+    dc = [torch.empty_like(x[2]) for x in ins]
+    F.fock_diag_vjp_batch(plans, [x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins], saved, g,
+                          dA, db, dc, ws)
+    torch.cuda.synchronize()
+    for k, (p, c) in enumerate(zip(plans, circs)):
+        eA, eb, ec = torch.empty_like(dA[k]), torch.empty_like(db[k]), torch.empty_like(dc[k])
+        F.fock_diag_vjp(p, *ins[k], saved[k], g[k], eA, eb, ec, ws[k])
+        torch.cuda.synchronize()
+        for got, exp in ((dA[k], eA), (db[k], eb), (dc[k], ec)):
+            np.testing.assert_array_equal(got.cpu().numpy(), exp.cpu().numpy())
