@@ -123,6 +123,38 @@ __device__ __forceinline__ void wave_accum(cx<R>* recw, const cx<R>* h, const cx
   }
 }
 
+// Point reverse kernel: every lane owns one record column of its
+// wavefront's staging area (kPRec = 64 columns, rows kPRec + 1 apart), and
+// writes each value there as soon as it exists -- the read values X are never
+// held in registers, which keeps the 8-mode kernel out of scratch memory.
+constexpr int kPRec = 64;
+constexpr int kPStride = kPRec + 1;
+
+template <typename R, int NPD, int NR, int PPL>
+__device__ __forceinline__ void wave_accum_staged(const cx<R>* recw, cx<double>* acc) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int pp = 0; pp < PPL; ++pp) {
+    const int p = lane + 64 * pp;
+    if (p < NPD * NR) {
+      const int i = p / NR, l = p - (p / NR) * NR;
+      const cx<R>* H = recw + i * kPStride;
+      const cx<R>* X = recw + (NPD + l) * kPStride;
+      double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+      for (int e = 0; e < kPRec; ++e) {
+        const cx<R> hv = H[e], xv = X[e];
+        ax[e & 3] = fma((double)xv.x, (double)hv.x, ax[e & 3]);
+        ax[e & 3] = fma((double)xv.y, (double)hv.y, ax[e & 3]);
+        ay[e & 3] = fma((double)xv.x, (double)hv.y, ay[e & 3]);
+        ay[e & 3] = fma(-(double)xv.y, (double)hv.x, ay[e & 3]);
+      }
+      acc[pp].x += (ax[0] + ax[1]) + (ax[2] + ax[3]);
+      acc[pp].y += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+    }
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void load_tables_v(const DevPlan& P, int* spn, R* sq, R* isq) {
   const int n = (P.MD + 1) * P.pnw;
@@ -145,8 +177,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
   constexpr int NPAIR = NP * NR;
   constexpr int PPL = (NPAIR + 63) / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* rec = reinterpret_cast<cx<R>*>(smem_raw);                   // waves x kWStride x (NP + NR)
-  cx<R>* sA = rec + (size_t)(kThreads / 64) * kWStride * (NP + NR);  // A (NP x NP) then b (NP)
+  cx<R>* rec = reinterpret_cast<cx<R>*>(smem_raw);                   // waves x kPStride x (NP + NR)
+  cx<R>* sA = rec + (size_t)(kThreads / 64) * kPStride * (NP + NR);  // A (NP x NP) then b (NP)
   const cx<R>* sb = sA + NP * NP;
   R* sq = reinterpret_cast<R*>(sA + NP * NP + NP);
   R* isq = sq + (kMaxCut + 4);
@@ -154,11 +186,13 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
   load_tables_v(P, spn, sq, isq);
   for (int i = threadIdx.x; i < NP * NP + NP; i += blockDim.x) sA[i] = ld(Ai + i);
   __syncthreads();
-  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWStride * (NP + NR);
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kPStride * (NP + NR);
+  const int lane = threadIdx.x & 63;
   cx<double> acc[PPL];
 #pragma unroll
   for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
   const int pnw = P.pnw;
+  auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * kPStride + lane] = v; };
 
   for (int base = blockIdx.x * kThreads; base < nwork; base += gridDim.x * kThreads) {
     const int r = base + threadIdx.x;
@@ -185,11 +219,12 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
     for (int K = 0; K < MD; ++K) {
       const bool valid = live && K <= K0 && m[K] <= P.CD[K] - 2;
       if (!__syncthreads_or(valid)) continue;
-      cx<R> h[NP], x[NP + 1];
+      cx<R> h[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) h[i] = czero<R>();
+      // reads x: staged as they are formed (zero rows where this pivot reads nothing)
 #pragma unroll
-      for (int l = 0; l <= NP; ++l) x[l] = czero<R>();
+      for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
       if (valid) {
         h[2 * K + 1] = cscale(ld(V.gf0nxt + rup[K]), isq[m[K] + 1]);
         if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + r), isq[m[K] + 2]);
@@ -200,16 +235,16 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             h[2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + r), isq[m[j] + 1]);
           }
         }
-        x[2 * K] = cscale(G0, sq[m[K] + 1]);
-        if (m[K] > 0) x[2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + rdn[K]), sq[m[K]]);
+        stx(2 * K, cscale(G0, sq[m[K] + 1]));
+        if (m[K] > 0) stx(2 * K + 1, cscale(ld(V.fprev[fam_f2(MD, K)] + rdn[K]), sq[m[K]]));
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
           if (m[j] > 0) {
-            x[2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]);
-            x[2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]);
+            stx(2 * j, cscale(ld(V.fprev[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]));
+            stx(2 * j + 1, cscale(ld(V.fprev[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]));
           }
         }
-        if (ODD) x[NP] = ld(V.fcur[fam_f1k(K)] + r);
+        if (ODD) stx(NP, ld(V.fcur[fam_f1k(K)] + r));
         // adjoint of the reads
 #pragma unroll
         for (int l = 2 * K; l < NP; ++l) {
@@ -233,17 +268,21 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
           ykg[K] = has_diag_reader ? cadd(ld(V.gcur[fam_f1k(K)] + r), gp) : gp;
         }
       }
-      wave_accum<R, NP, NR, PPL>(recw, h, x, valid, acc);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) recw[i * kPStride + lane] = h[i];
+      wave_sync();
+      if (__ballot(valid) != 0) wave_accum_staged<R, NP, NR, PPL>(recw, acc);
+      wave_sync();
     }
 
     if (ODD) {
       const bool valid = live && m[0] <= P.CD[0] - 2;
       if (__syncthreads_or(valid)) {
-        cx<R> h[NP], x[NP + 1];
+        cx<R> h[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) h[i] = czero<R>();
 #pragma unroll
-        for (int l = 0; l <= NP; ++l) x[l] = czero<R>();
+        for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
         if (valid) {
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
@@ -255,11 +294,11 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
             if (okb) h[2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + r), isq[m[j] + 1]);
             if (m[j] > 0) {
-              x[2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]);
-              x[2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + rdn[j]), sq[m[j]]);
+              stx(2 * j, cscale(ld(V.fprev[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]));
+              stx(2 * j + 1, cscale(ld(V.fprev[fam_f1k(j)] + rdn[j]), sq[m[j]]));
             }
           }
-          x[NP] = G0;
+          stx(NP, G0);
 #pragma unroll
           for (int l = 0; l < NP; ++l) {
             const int j = l >> 1;
@@ -274,7 +313,11 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
           for (int i = 0; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
           g0acc = cadd(g0acc, gp);
         }
-        wave_accum<R, NP, NR, PPL>(recw, h, x, valid, acc);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) recw[i * kPStride + lane] = h[i];
+        wave_sync();
+        if (__ballot(valid) != 0) wave_accum_staged<R, NP, NR, PPL>(recw, acc);
+        wave_sync();
       }
     }
     if (live) st(V.gcur[0] + r, g0acc);
@@ -827,7 +870,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     if (Pl.B == 1) {
       const int NP = 2 * MD;
       const size_t ppl = (size_t)(NP * (NP + 1) + 63) / 64;
-      const size_t shm = std::max(((size_t)(kThreads / 64) * (kWRec + 1) * (2 * NP + 1) + (size_t)NP * (NP + 1)) *
+      const size_t shm = std::max(((size_t)(kThreads / 64) * kPStride * (2 * NP + 1) + (size_t)NP * (NP + 1)) *
                                       sizeof(cx<R>),
                                   (size_t)kThreads * ppl * sizeof(cx<double>)) + tab;
       const int grid = (int)std::min<int64_t>((nwork + kThreads - 1) / kThreads, kPartialSlots - 1);
