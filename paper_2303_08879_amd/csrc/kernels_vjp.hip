@@ -361,6 +361,13 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   constexpr int NR = NPOS + 1;
   constexpr int NPAIR = NPD * NR;
   constexpr int PPL = (NPAIR + 63) / 64;
+  // From records of 17 values on (four detected modes, or three with two
+  // undetected modes), the read values go straight to this lane's column of a
+  // 64-record staging area instead of registers (as in the point kernel): the
+  // wide units would otherwise spill.  Below that the kernel is LDS-bound and
+  // keeps the smaller 32-record staging.
+  constexpr bool STG = NPD + NR >= 17;
+  constexpr int RS = STG ? kPStride : kWStride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int B = P.B, R0 = G.R0, RC = G.RC;
   const int nrow1 = (RC + 1) * R0, nrow2 = (RC + 2) * R0;
@@ -369,8 +376,8 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   cx<R>* gbv = qv + (size_t)NQ * nrow2;              // rows [k0, k1+1)
   cx<R>* gpk = gbv + nrow1;                          // MD x rows [k0, k1+1)
   cx<R>* g0a = gpk + (size_t)MD * nrow1;             // own rows
-  cx<R>* rec = g0a + (size_t)RC * R0;                // waves x kWStride x (NPD + NR)
-  cx<R>* sA = rec + (size_t)(kBT / 64) * kWStride * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
+  cx<R>* rec = g0a + (size_t)RC * R0;                // waves x RS x (NPD + NR)
+  cx<R>* sA = rec + (size_t)(kBT / 64) * RS * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
@@ -381,7 +388,8 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
   // (one wavefront per workgroup: every phase of a unit starts with a staging
   // loop and a barrier before it reads these tables)
-  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kWStride * (NPD + NR);
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * RS * (NPD + NR);
+  const int lane = threadIdx.x & 63;
   cx<double> acc[PPL];
 #pragma unroll
   for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
@@ -413,11 +421,17 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
-        cx<R> h[NPD], x[NR];
+        cx<R> h[NPD], x[STG ? 1 : NR];
+        auto setx = [&](int l, const cx<R>& v) {
+          if constexpr (STG)
+            recw[(NPD + l) * kPStride + lane] = v;
+          else
+            x[l] = v;
+        };
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
 #pragma unroll
-        for (int l = 0; l < NR; ++l) x[l] = czero<R>();
+        for (int l = 0; l < NR; ++l) setx(l, czero<R>());
         if (live) {
           int kap[NQ];
           int rem = e;
@@ -452,16 +466,16 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             const int lf = e - (k0 - 1) * R0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-              if (kap[q] > 0) x[q] = cscale(lfw[lf - P.ustride[q]], sq[kap[q]]);
-            x[NPOS] = lfw[lf];
-            x[NQ + 2 * K] = cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]);
+              if (kap[q] > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kap[q]]));
+            setx(NPOS, lfw[lf]);
+            setx(NQ + 2 * K, cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]));
             if (m[K] > 0)
-              x[NQ + 2 * K + 1] = cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]);
+              setx(NQ + 2 * K + 1, cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]));
 #pragma unroll
             for (int j = K + 1; j < MD; ++j) {
               if (m[j] > 0) {
-                x[NQ + 2 * j] = cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-                x[NQ + 2 * j + 1] = cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+                setx(NQ + 2 * j, cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
+                setx(NQ + 2 * j + 1, cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
               }
             }
 #pragma unroll
@@ -482,7 +496,15 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             }
           }
         }
-        wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
+        if constexpr (STG) {
+#pragma unroll
+          for (int i = 0; i < NPD; ++i) recw[i * kPStride + lane] = (live && own) ? h[i] : czero<R>();
+          wave_sync();
+          if (__ballot(live && own) != 0) wave_accum_staged<R, NPD, NR, PPL>(recw, acc);
+          wave_sync();
+        } else {
+          wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
+        }
       }
       __syncthreads();
       // total cotangent of the bridge pivot block F1k(K)(m), rows [k0, k1+1)
@@ -513,11 +535,17 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
-        cx<R> h[NPD], x[NR];
+        cx<R> h[NPD], x[STG ? 1 : NR];
+        auto setx = [&](int l, const cx<R>& v) {
+          if constexpr (STG)
+            recw[(NPD + l) * kPStride + lane] = v;
+          else
+            x[l] = v;
+        };
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
 #pragma unroll
-        for (int l = 0; l < NR; ++l) x[l] = czero<R>();
+        for (int l = 0; l < NR; ++l) setx(l, czero<R>());
         if (live) {
           int kap[NQ];
           int rem = e;
@@ -548,13 +576,13 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             const int lf = e - (k0 - 1) * R0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-              if (kap[q] > 0) x[q] = cscale(lfw[lf - P.ustride[q]], sq[kap[q]]);
-            x[NPOS] = lfw[lf];
+              if (kap[q] > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kap[q]]));
+            setx(NPOS, lfw[lf]);
 #pragma unroll
             for (int j = 0; j < MD; ++j) {
               if (m[j] > 0) {
-                x[NQ + 2 * j] = cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-                x[NQ + 2 * j + 1] = cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+                setx(NQ + 2 * j, cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
+                setx(NQ + 2 * j + 1, cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
               }
             }
 #pragma unroll
@@ -572,7 +600,15 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             g0a[le] = cadd(g0a[le], gb);
           }
         }
-        wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
+        if constexpr (STG) {
+#pragma unroll
+          for (int i = 0; i < NPD; ++i) recw[i * kPStride + lane] = (live && own) ? h[i] : czero<R>();
+          wave_sync();
+          if (__ballot(live && own) != 0) wave_accum_staged<R, NPD, NR, PPL>(recw, acc);
+          wave_sync();
+        } else {
+          wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
+        }
       }
       __syncthreads();
       for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) {
@@ -796,7 +832,7 @@ size_t vjp_lds_bytes(const Plan& Pl) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
   const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
   const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                      (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (kWRec + 1) * (NPD + NR);
+                      (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (NPD + NR >= 17 ? kPStride : kWStride) * (NPD + NR);
   const size_t ppl = (size_t)(NPD * NR + 63) / 64;
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)kBT * ppl * 16) + 2 * (kMaxCut + 4) * rb;
 }
