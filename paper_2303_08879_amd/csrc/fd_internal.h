@@ -223,7 +223,8 @@ struct KTimer {
 // kernels (kernels_fwd.hip / kernels_vjp.hip)
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
                        void* saved, hipStream_t st);
-ChunkGeo chunk_geo(const Plan& P);   // forward block kernels
+ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
+constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
 hipError_t launch_prep(const Plan& P, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
                        hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,

@@ -97,13 +97,13 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Rows of the first undetected coordinate per chunk: about one wavefront of
-// own entries, spread evenly over the rows.
-ChunkGeo chunk_geo(const Plan& Pl) {
+// Rows of the first undetected coordinate per chunk: about `target` own
+// entries (default one wavefront), spread evenly over the rows.
+ChunkGeo chunk_geo(const Plan& Pl, int target) {
   ChunkGeo G;
   G.C0 = Pl.udims[0];
   G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, (kBT + G.R0 / 2) / G.R0);
+  int rc = std::max(1, (target + G.R0 / 2) / G.R0);
   rc = std::min(rc, G.C0);
   G.nchunks = (G.C0 + rc - 1) / rc;
   G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
@@ -145,7 +145,11 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
     }
 #undef FD_LAUNCH_POINT
   } else {
-    const ChunkGeo G = chunk_geo(Pl);
+    // a level with few units is latency-bound: halve the chunks to put more
+    // wavefronts in flight (config-2-sized levels: -7 %); a large level keeps
+    // whole-wavefront chunks (halving them costs 30-40 % there)
+    ChunkGeo G = chunk_geo(Pl);
+    if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
     const size_t shm = (((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
                            sizeof(cx<R>) + 2 * (kMaxCut + 4) * sizeof(R);
     const int grid = nwork * G.nchunks;
