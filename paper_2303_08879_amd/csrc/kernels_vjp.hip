@@ -815,26 +815,29 @@ __global__ __launch_bounds__(kThreads) void k_vjp_final(const double2* __restric
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
-static ChunkGeo chunk_geo_v(const Plan& Pl) {
+static ChunkGeo chunk_geo_v(const Plan& Pl, int target = kBT) {
   ChunkGeo G;
   G.C0 = Pl.udims[0];
   G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, (kBT + G.R0 / 2) / G.R0);
+  int rc = std::max(1, (target + G.R0 / 2) / G.R0);
   rc = std::min(rc, G.C0);
   G.nchunks = (G.C0 + rc - 1) / rc;
   G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
   return G;
 }
 
-// Dynamic LDS of k_vjp_block for this plan (exact; the launcher uses it).
-size_t vjp_lds_bytes(const Plan& Pl) {
-  const ChunkGeo G = chunk_geo_v(Pl);
+// Dynamic LDS of k_vjp_block for a chunk geometry (exact; the launcher uses
+// it); without one, the largest the launcher uses for this plan.
+static size_t vjp_lds_bytes_g(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
   const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
   const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
                       (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (NPD + NR >= 17 ? kPStride : kWStride) * (NPD + NR);
   const size_t ppl = (size_t)(NPD * NR + 63) / 64;
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)kBT * ppl * 16) + 2 * (kMaxCut + 4) * rb;
+}
+size_t vjp_lds_bytes(const Plan& Pl) {
+  return std::max(vjp_lds_bytes_g(Pl, chunk_geo_v(Pl)), vjp_lds_bytes_g(Pl, chunk_geo_v(Pl, kBT / 2)));
 }
 
 template <typename R>
@@ -940,8 +943,10 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       }
 #undef FD_VJP_POINT
     } else {
-      const ChunkGeo G = chunk_geo_v(Pl);
-      const size_t shm = vjp_lds_bytes(Pl);
+      // as in the forward sweep: half-size row chunks on levels with few units
+      ChunkGeo G = chunk_geo_v(Pl);
+      if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo_v(Pl, kBT / 2);
+      const size_t shm = vjp_lds_bytes_g(Pl, G);
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \
