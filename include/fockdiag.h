@@ -170,7 +170,10 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
  * circuit is swept together, by a cooperative grid that fills the device and
  * takes (circuit, step, tile) work items from a per-step queue, with a grid
  * barrier between steps.  Launches: prep (+ undetected block fill), the
- * sweep, the output permutation.
+ * sweep, the output permutation.  A circuit whose levels average at least
+ * 2048 wavefront-sized units fills the device by itself and runs its own
+ * level launches first (as fock_diag_fwd); the persistent sweep takes the
+ * rest.
  *   plans      n plans of one dtype, created on the current device
  *   workspace  per circuit, >= fd_plan_workspace(plan, 0) bytes, 256-byte
  *              aligned; the n workspaces must not overlap (FD_ERR_INVALID_ARG)

@@ -36,7 +36,7 @@ constexpr int kTabBytes = 2 * (kMaxCut + 4) * 8;   // sqrt tables at the start o
 template <typename R>
 struct BatchCirc {
   DevPlan P;
-  ChunkGeo G;
+  ChunkGeo G, Gh;              // row chunks of a unit: whole-wavefront, and halved for small levels
   PrepArgs pa;
   int kind;                    // 0: Algorithm 1 (point units), 1: Algorithm 2 (block units)
   int steps;                   // sweep steps (0 when no mode is detected)
@@ -55,9 +55,12 @@ struct BatchCirc {
   int64_t out_elems, N;        // output elements; nodes (prod of detected cutoffs)
 };
 
-// A work item: units [u0, u1) of step `step` of circuit `circ`.
+// A work item: units [u0, u1) of step `step` of circuit `circ`; `half`
+// selects the halved row chunks (Algorithm 2 levels with few units, as in
+// the per-circuit level launches).
 struct BatchItem {
   int circ, step, u0, u1;
+  int half, pad[3];
 };
 
 // Per-wavefront LDS of the sweep kernel: PN table, then (block circuits) A
@@ -128,7 +131,7 @@ __device__ __forceinline__ void run_block_item(const BatchCirc<R>* __restrict__ 
                                                cx<R>* lf0) {
   constexpr int NPOS = NQ + 2 * MD;
   const BatchLevel<R> L = batch_level(C, I.step);
-  const ChunkGeo G = C->G;
+  const ChunkGeo G = I.half ? C->Gh : C->G;
   cx<R>* lpk = lf0 + (size_t)(G.RC + 2) * G.R0;
   for (int u = I.u0; u < I.u1; ++u) {
     const int r = u / G.nchunks, ch = u - r * G.nchunks;

@@ -7,6 +7,7 @@
 // circuit in one launch.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <numeric>
 
@@ -151,7 +152,10 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
     std::memset(&C, 0, sizeof(C));
     C.P = make_devplan(Pl, odd[i]);
     C.kind = Pl.B > 1 ? 1 : 0;
-    if (C.kind) C.G = chunk_geo(Pl);
+    if (C.kind) {
+      C.G = chunk_geo(Pl);
+      C.Gh = chunk_geo(Pl, kBT / 2);
+    }
     for (int p = 0; p < Pl.npos; ++p) C.pa.pos2blk[p] = Pl.pos2blk[p];
     C.pa.npos = Pl.npos;
     C.pa.M2 = 2 * Pl.M;
@@ -260,15 +264,18 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
       if (s >= hc[i].steps) continue;
       const int64_t pts = plans[i]->ncnt[s];
       if (pts <= 0) continue;
-      const int64_t units = hc[i].kind ? pts * hc[i].G.nchunks : pts;
+      const bool half = hc[i].kind && pts * hc[i].G.nchunks < kSmallLevelUnits;
+      const int64_t units = hc[i].kind ? pts * (half ? hc[i].Gh.nchunks : hc[i].G.nchunks) : pts;
       int64_t per = std::max<int64_t>(hc[i].kind ? T.min_block_units : T.min_point_units, (units + div - 1) / div);
       if (!hc[i].kind) per = (per + 63) / 64 * 64;   // whole wavefronts of lattice points
       for (int64_t u0 = 0; u0 < units; u0 += per) {
         BatchItem I;
+        std::memset(&I, 0, sizeof(I));
         I.circ = i;
         I.step = s;
         I.u0 = (int)u0;
         I.u1 = (int)std::min(units, u0 + per);
+        I.half = half ? 1 : 0;
         S->h_items.push_back(I);
       }
     }
@@ -352,9 +359,62 @@ hipError_t launch_batch(const BatchSched& S, int n, const Plan& P0, hipStream_t 
 
 }  // namespace
 
+// A circuit fills the device on its own when its levels average at least
+// kFillWaves wavefront-sized units (about what the device holds at once):
+// such circuits run their own level launches, interleaving them with other
+// large circuits only multiplies the working set the L2s and the MALL hold.
+constexpr double kFillWaves = 2048.0;
+static bool fills_device(const Plan& Pl) {
+  if (Pl.MD == 0) return false;
+  double units = 0.0;
+  const ChunkGeo G = Pl.B > 1 ? chunk_geo(Pl) : ChunkGeo{1, 1, 1, 1};
+  for (int s = 0; s <= Pl.smax; ++s)
+    units += Pl.B > 1 ? (double)Pl.ncnt[s] * G.nchunks : (double)Pl.ncnt[s] / 64.0;
+  return units / (Pl.smax + 1) >= kFillWaves;
+}
+
+static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                                         const void* const* b, const void* const* c, void* const* rho,
+                                         void* const* ws, hipStream_t st, std::string* err);
+
 fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
                             const void* const* b, const void* const* c, void* const* rho, void* const* ws,
                             hipStream_t st, std::string* err) {
+  // circuits that fill the device: their own level launches, largest first;
+  // the others: one persistent sweep
+  std::vector<int> big, small;
+  for (int i = 0; i < n; ++i) (fills_device(*plans[i]) ? big : small).push_back(i);
+  for (int i : big) {
+    const hipError_t e = run_forward(*plans[i], odd[i], A[i], b[i], c[i], rho[i], ws[i], nullptr, st);
+    if (e != hipSuccess) {
+      *err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+      return FD_ERR_HIP;
+    }
+  }
+  if (small.empty()) return FD_OK;
+  if (big.empty()) return run_forward_batch_small(n, plans, odd, A, b, c, rho, ws, st, err);
+  const size_t m = small.size();
+  std::vector<Plan*> p2(m);
+  std::unique_ptr<bool[]> o2(new bool[m]);
+  std::vector<const void*> A2(m), b2(m), c2(m);
+  std::vector<void*> r2(m), w2(m);
+  for (size_t k = 0; k < m; ++k) {
+    const int i = small[k];
+    p2[k] = plans[i];
+    o2[k] = odd[i];
+    A2[k] = A[i];
+    b2[k] = b[i];
+    c2[k] = c[i];
+    r2[k] = rho[i];
+    w2[k] = ws[i];
+  }
+  return run_forward_batch_small((int)m, p2.data(), o2.get(), A2.data(), b2.data(), c2.data(), r2.data(), w2.data(),
+                                 st, err);
+}
+
+static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                                         const void* const* b, const void* const* c, void* const* rho,
+                                         void* const* ws, hipStream_t st, std::string* err) {
   if (n == 0) return FD_OK;
   int dev = 0;
   (void)hipGetDevice(&dev);
