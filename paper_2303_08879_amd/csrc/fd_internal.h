@@ -174,8 +174,13 @@ struct VjpLayout {
   size_t g0 = 0;                     // drho in level-major node order
   std::vector<size_t> gfam;          // cotangent rings per family (F0 too)
   size_t partial = 0;                // kPartialSlots x (npos x (npos+1)) complex (double)
+  size_t priv = 0;                   // block plans: kPartialSlots x vjp_private_entries (per workgroup)
   size_t total = 0;
 };
+// Entries of one workgroup's private slot of the block reverse kernel: the
+// pivot cotangent blocks (MD rows sets), their b-terms and the own F0
+// cotangent rows, each read only by the lane that wrote it.
+size_t vjp_private_entries(const Plan& P);
 size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel
 constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);

@@ -34,6 +34,8 @@ struct VjpPtrs {
   const cx<R>* gf0nxt;          // F0 cotangents, level S+1
   const cx<R>* d0cur;           // drho in node order, level S
   const int* node;              // node records of level S (Algorithm 2 plans)
+  cx<R>* priv;                  // per-workgroup private slots (Algorithm 2 plans)
+  int64_t priv_stride;          // entries per slot
 };
 
 __global__ void k_zero_d2(double2* p, int64_t n) {
@@ -373,10 +375,13 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   const int nrow1 = (RC + 1) * R0, nrow2 = (RC + 2) * R0;
   cx<R>* lfw = reinterpret_cast<cx<R>*>(smem_raw);   // forward pivot rows [k0-1, k1)
   cx<R>* qv = lfw + nrow1;                           // NQ x rows [k0, k1+2)
-  cx<R>* gbv = qv + (size_t)NQ * nrow2;              // rows [k0, k1+1)
-  cx<R>* gpk = gbv + nrow1;                          // MD x rows [k0, k1+1)
-  cx<R>* g0a = gpk + (size_t)MD * nrow1;             // own rows
-  cx<R>* rec = g0a + (size_t)RC * R0;                // waves x RS x (NPD + NR)
+  cx<R>* rec = qv + (size_t)NQ * nrow2;              // waves x RS x (NPD + NR)
+  // entries each lane reads back only itself (same entry-to-lane map in every
+  // loop of a unit): the workgroup's private slot in global memory, which
+  // leaves the LDS to the shared rows and raises the wavefronts per CU
+  cx<R>* gpk = V.priv + (size_t)blockIdx.x * V.priv_stride;   // MD x rows [k0, k1+1)
+  cx<R>* gbv = gpk + (size_t)MD * nrow1;                       // rows [k0, k1+1)
+  cx<R>* g0a = gbv + nrow1;                                    // own rows
   cx<R>* sA = rec + (size_t)(kBT / 64) * RS * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
@@ -831,8 +836,8 @@ static ChunkGeo chunk_geo_v(const Plan& Pl, int target = kBT) {
 static size_t vjp_lds_bytes_g(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
   const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
-  const size_t ents = (size_t)(G.RC + 1) * G.R0 * (2 + MD) + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                      (size_t)G.RC * G.R0 + (size_t)(kBT / 64) * (NPD + NR >= 17 ? kPStride : kWStride) * (NPD + NR);
+  const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
+                      (size_t)(kBT / 64) * (NPD + NR >= 17 ? kPStride : kWStride) * (NPD + NR);
   const size_t ppl = (size_t)(NPD * NR + 63) / 64;
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)kBT * ppl * 16) + 2 * (kMaxCut + 4) * rb;
 }
@@ -904,6 +909,8 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
                                               (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
     Vp.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
+    Vp.priv = V.priv ? reinterpret_cast<cx<R>*>(ws + V.priv) : nullptr;
+    Vp.priv_stride = (int64_t)vjp_private_entries(Pl);
     const int nwork = (int)Pl.ncnt[S];
     KTimer kt(Pl, KK_VJP_LEVEL, st);
     if (Pl.B == 1) {

@@ -290,8 +290,18 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   }
   L.partial = off;
   off = align256(off + (size_t)kPartialSlots * P.npos * (P.npos + 1) * 16);
+  if (P.B > 1 && P.MD > 0) {
+    L.priv = off;
+    off = align256(off + (size_t)kPartialSlots * vjp_private_entries(P) * eb);
+  }
   L.total = off;
   return L;
+}
+
+size_t vjp_private_entries(const Plan& P) {
+  if (P.B == 1 || P.MD == 0) return 0;
+  const ChunkGeo G = chunk_geo(P);   // the larger of the two chunk heights the launcher uses
+  return (size_t)(P.MD + 1) * (G.RC + 1) * G.R0 + (size_t)G.RC * G.R0;
 }
 
 
