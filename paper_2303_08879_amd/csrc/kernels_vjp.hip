@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
   }
 }
 
-constexpr int kWRec = 32;
+constexpr int kWRec = 16;
 
 // records: H rows NPD (detected write positions), X rows NR (NQ undetected
 // reads, NPD detected reads, pivot value).  Pair p = i * NR + l.  Rows are
