@@ -130,6 +130,47 @@ def batched_leg(reps=1):
     return out
 
 
+def gradient_leg(n=64):
+    """The batched gradient workload: n circuits with M = 6, mode 0 undetected
+    (cutoff 30), five detected modes (cutoff 8), b = 0, complex128; per circuit
+    one forward keeping every intermediate and one reverse sweep with a seeded
+    dense cotangent, circuits one after another (each sweep fills the device;
+    a circuit's intermediates take 9.9 GB, so the saved buffer and the
+    workspace are reused)."""
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+    circs = W.config5b(n=n)
+    dt, dev = torch.complex128, "cuda"
+    plan = F.Plan(circs[0].cutoffs, circs[0].detected_mask, dt, "zero")
+    wb, sb = plan.workspace(True)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    saved = torch.empty(sb, dtype=torch.uint8, device=dev)
+    rho = torch.empty(plan.out_shape, dtype=dt, device=dev)
+    g = torch.tensor(W.random_cotangent(plan.out_shape, seed=11), dtype=dt, device=dev)
+    ins = [(torch.tensor(c.A, dtype=dt, device=dev), torch.tensor(c.b, dtype=dt, device=dev),
+            torch.tensor([c.c], dtype=dt, device=dev)) for c in circs]
+    grads = [(torch.empty_like(A), torch.empty_like(b), torch.empty_like(c)) for A, b, c in ins]
+
+    def step():
+        for (A, b, c), (dA, db, dc) in zip(ins, grads):
+            F.fock_diag_fwd(plan, A, b, c, rho, ws, saved)
+            F.fock_diag_vjp(plan, A, b, c, saved, g, dA, db, dc, ws)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    F.fd_device_status(plan)
+    targets = plan.query(F.FD_Q_TARGETS)
+    return dict(workload="config5b: 64 circuits, M=6, mode 0 undetected C_U=30, 5 detected C_D=8, b=0, complex128; "
+                         "forward (intermediates kept) + VJP per circuit",
+                circuits=n, seconds=sec, circuits_per_s=n / sec, computed_amplitudes_per_circuit=targets,
+                output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +180,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-corner", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
+    ap.add_argument("--gradient-leg", action="store_true",
+                    help="also time the 64-circuit gradient workload (forward + VJP per circuit)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device-to-device copies (the reference for HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +312,8 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = batched_leg()
+    if args.gradient_leg:
+        line["gradient_batch"] = gradient_leg()
     if not args.no_cpu_baseline:
         torch.cuda.synchronize()
         step()
