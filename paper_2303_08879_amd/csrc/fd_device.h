@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fd_internal.h"
 
 namespace fd {
@@ -48,6 +50,18 @@ __device__ __forceinline__ cx<R> cscale(const cx<R>& a, R s) {
 template <typename R>
 __device__ __forceinline__ cx<R> cadd(const cx<R>& a, const cx<R>& b) {
   return cmake<R>(a.x + b.x, a.y + b.y);
+}
+
+// Element idx of one level's slab of a family through a 32-bit byte offset
+// from the level's base: the memory instruction then takes the base from
+// scalar registers and one 32-bit offset register instead of a 64-bit
+// address per lane (fewer registers and address instructions).  The planner
+// keeps every level of a block plan below 2^28 amplitudes, so the offset
+// cannot wrap.
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, uint32_t idx) {
+  using Byte = typename std::conditional<std::is_const<T>::value, const unsigned char, unsigned char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<Byte*>(base) + (uint64_t)(idx * (uint32_t)sizeof(T)));
 }
 
 // 16-byte / 8-byte vector load and store of one complex element.

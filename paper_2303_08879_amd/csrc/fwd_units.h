@@ -257,7 +257,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
     {
       const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
       const int base = (k0 - 2) * R0;
-      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = ld(L.f0cur + rB + e);
+      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = ld(at32(L.f0cur, (uint32_t)(r * B + e)));
     }
     wave_sync();
     // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
@@ -282,8 +282,8 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
         for (int j = 0; j < MD; ++j) {
           if (m[j] > 0) {
-            x[2 * j] = cscale(ld(L.rd[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-            x[2 * j + 1] = cscale(ld(L.rd[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            x[2 * j] = cscale(ld(at32(L.rd[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            x[2 * j + 1] = cscale(ld(at32(L.rd[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
           } else {
             x[2 * j] = czero<R>();
             x[2 * j + 1] = czero<R>();
@@ -306,7 +306,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
             for (int l = 0; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
             acc = cscale(acc, isq[m[j] + 1]);
-            if (ok && own) st(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)] + rB + e, acc);
+            if (ok && own) st(at32(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)], (uint32_t)(r * B + e)), acc);
             if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
           }
         }
@@ -333,12 +333,12 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
         for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : czero<R>();
         cx<R> x[NPD];
         x[2 * K] = cscale(lf0[e - (k0 - 2) * R0], sq[m[K] + 1]);
-        x[2 * K + 1] = (m[K] > 0) ? cscale(ld(L.rd[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]) : czero<R>();
+        x[2 * K + 1] = (m[K] > 0) ? cscale(ld(at32(L.rd[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]) : czero<R>();
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
           if (m[j] > 0) {
-            x[2 * j] = cscale(ld(L.rd[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
-            x[2 * j + 1] = cscale(ld(L.rd[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]);
+            x[2 * j] = cscale(ld(at32(L.rd[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            x[2 * j + 1] = cscale(ld(at32(L.rd[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
           } else {
             x[2 * j] = czero<R>();
             x[2 * j + 1] = czero<R>();
@@ -353,15 +353,15 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           if (i == 2 * K + 1) {
             ok = true;
             scale = isq[m[K] + 1];
-            dst = L.f0nxt + (size_t)rup[K] * B + e;
+            dst = at32(L.f0nxt, (uint32_t)(rup[K] * B + e));
           } else if (i == 2 * K) {
             ok = (m[K] <= P.CD[K] - 3);
             scale = isq[m[K] + 2];
-            dst = L.wr[fam_f2(MD, K)] + rB + e;
+            dst = at32(L.wr[fam_f2(MD, K)], (uint32_t)(r * B + e));
           } else {
             ok = (m[j] <= P.CD[j] - 2);
             scale = isq[m[j] + 1];
-            dst = L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)] + rB + e;
+            dst = at32(L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)], (uint32_t)(r * B + e));
           }
           if (!ok) continue;
           const int row = (NQ + i) * NPOS;
