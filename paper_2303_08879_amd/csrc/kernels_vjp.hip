@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
     for (int d = MD - 1; d >= 0; --d)
       if (m[d] > 0) K0 = d;
     const size_t rB = (size_t)r * B;
-    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) g0a[e - e_own0] = ld(V.d0cur + rB + e);
+    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) g0a[e - e_own0] = ld(at32(V.d0cur, (uint32_t)(r * B + e)));
 
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
@@ -445,13 +445,13 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             kap[q] = ucoord(P, rem, q);
             rem -= kap[q] * P.ustride[q];
           }
-          h[2 * K + 1] = cscale(ld(V.gf0nxt + (size_t)rup[K] * B + e), isq[m[K] + 1]);
-          if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + rB + e), isq[m[K] + 2]);
+          h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)(rup[K] * B + e))), isq[m[K] + 1]);
+          if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(at32(V.gcur[fam_f2(MD, K)], (uint32_t)(r * B + e))), isq[m[K] + 2]);
 #pragma unroll
           for (int j = K + 1; j < MD; ++j) {
             if (m[j] <= P.CD[j] - 2) {
-              h[2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + rB + e), isq[m[j] + 1]);
-              h[2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + rB + e), isq[m[j] + 1]);
+              h[2 * j] = cscale(ld(at32(V.gcur[fam_1010(MD, K, j)], (uint32_t)(r * B + e))), isq[m[j] + 1]);
+              h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_1001(MD, K, j)], (uint32_t)(r * B + e))), isq[m[j] + 1]);
             }
           }
 #pragma unroll
@@ -473,14 +473,14 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             for (int q = 0; q < NQ; ++q)
               if (kap[q] > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kap[q]]));
             setx(NPOS, lfw[lf]);
-            setx(NQ + 2 * K, cscale(ld(V.fcur[0] + rB + e), sq[m[K] + 1]));
+            setx(NQ + 2 * K, cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]));
             if (m[K] > 0)
-              setx(NQ + 2 * K + 1, cscale(ld(V.fprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e), sq[m[K]]));
+              setx(NQ + 2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]));
 #pragma unroll
             for (int j = K + 1; j < MD; ++j) {
               if (m[j] > 0) {
-                setx(NQ + 2 * j, cscale(ld(V.fprev[fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
-                setx(NQ + 2 * j + 1, cscale(ld(V.fprev[fam_1010(MD, K, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
+                setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
               }
             }
 #pragma unroll
@@ -493,9 +493,9 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
               if (l == 2 * K) {
                 g0a[e - e_own0] = cadd(g0a[e - e_own0], cscale(u, sq[m[K] + 1]));
               } else if (l == 2 * K + 1) {
-                st(V.gprev[fam_f2(MD, K)] + (size_t)rdn[K] * B + e, cscale(u, sq[m[K]]));
+                st(at32(V.gprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e)), cscale(u, sq[m[K]]));
               } else {
-                st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + (size_t)rdn[j] * B + e,
+                st(at32(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e)),
                    cscale(u, sq[m[j]]));
               }
             }
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
         int rem = e;
         const int le = e - e_own0;
         cx<R> v = gbv[le];
-        if (has_diag_reader) v = cadd(v, ld(V.gcur[fam_f1k(K)] + rB + e));
+        if (has_diag_reader) v = cadd(v, ld(at32(V.gcur[fam_f1k(K)], (uint32_t)(r * B + e))));
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int kq = ucoord(P, rem, q);
@@ -564,11 +564,11 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
           for (int j = 0; j < MD; ++j) {
             if (j == 0 || m[j] <= P.CD[j] - 2) {
               const bool bridge = j <= K0 && m[j] <= P.CD[j] - 2;
-              const cx<R> gt = bridge ? gpk[(size_t)j * nrow1 + le] : ld(V.gcur[fam_f1k(j)] + rB + e);
+              const cx<R> gt = bridge ? gpk[(size_t)j * nrow1 + le] : ld(at32(V.gcur[fam_f1k(j)], (uint32_t)(r * B + e)));
               h[2 * j] = cscale(gt, isq[m[j] + 1]);
             }
             const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-            if (okb) h[2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + rB + e), isq[m[j] + 1]);
+            if (okb) h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_f1b(MD, j)], (uint32_t)(r * B + e))), isq[m[j] + 1]);
           }
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
@@ -586,8 +586,8 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
 #pragma unroll
             for (int j = 0; j < MD; ++j) {
               if (m[j] > 0) {
-                setx(NQ + 2 * j, cscale(ld(V.fprev[fam_f1b(MD, j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
-                setx(NQ + 2 * j + 1, cscale(ld(V.fprev[fam_f1k(j)] + (size_t)rdn[j] * B + e), sq[m[j]]));
+                setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
               }
             }
 #pragma unroll
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
               cx<R> u = czero<R>();
 #pragma unroll
               for (int i = 0; i < NPD; ++i) cfma_conj(u, sA[(NQ + i) * NPOS + NQ + l], h[i]);
-              st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + (size_t)rdn[j] * B + e, cscale(u, sq[m[j]]));
+              st(at32(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e)), cscale(u, sq[m[j]]));
             }
             cx<R> gb = czero<R>();
 #pragma unroll
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
         g0a[le] = v;
       }
     }
-    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) st(V.gcur[0] + rB + e, g0a[e - e_own0]);
+    for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) st(at32(V.gcur[0], (uint32_t)(r * B + e)), g0a[e - e_own0]);
     __syncthreads();
   }
   // fold the per-lane pair sums over the waves (fixed order) into this block's slot
