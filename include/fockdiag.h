@@ -74,8 +74,8 @@ enum { FD_B_AUTO = 0u, FD_B_ZERO = 1u, FD_B_GENERAL = 2u };
 /* Compiled limits: M <= 16 modes, at most 8 detected modes with cutoff >= 2,
  * at most 2 undetected modes with cutoff >= 2, every cutoff in [1, 64],
  * prod over detected cutoffs < 2^31 (<= 2^22 when a mode is undetected: the
- * plan keeps a 96-byte record per detected lattice point, and one level of
- * the detected lattice times the undetected block <= 2^28 amplitudes),
+ * plan keeps a 96-byte record per detected lattice point), one level of the
+ * detected lattice times the undetected block <= 2^28 amplitudes,
  * undetected block prod C_u^2 <= 4096
  * (the block of one node is staged in LDS; the reverse sweep also needs
  * (1 + 2|U|) blocks to fit in 160 KiB, else fock_diag_vjp returns

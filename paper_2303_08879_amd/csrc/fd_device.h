@@ -56,7 +56,7 @@ __device__ __forceinline__ cx<R> cadd(const cx<R>& a, const cx<R>& b) {
 // from the level's base: the memory instruction then takes the base from
 // scalar registers and one 32-bit offset register instead of a 64-bit
 // address per lane (fewer registers and address instructions).  The planner
-// keeps every level of a block plan below 2^28 amplitudes, so the offset
+// keeps every level of a plan below 2^28 amplitudes, so the offset
 // cannot wrap.
 template <typename T>
 __device__ __forceinline__ T* at32(T* base, uint32_t idx) {

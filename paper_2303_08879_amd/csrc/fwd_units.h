@@ -134,7 +134,7 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
   unrank<MD>(spn, pnw, P.CD, S, r, m, s);
   neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
 
-  const cx<R> g0 = ld(L.f0cur + r);
+  const cx<R> g0 = ld(at32(L.f0cur, (uint32_t)r));
   cx<R> yk[MD];
 #pragma unroll
   for (int K = 0; K < MD; ++K) yk[K] = czero<R>();
@@ -145,8 +145,8 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
     for (int j = 0; j < MD; ++j) {
       if (m[j] > 0) {
-        x[2 * j] = cscale(ld(L.rd[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]);   // d(m)-1_ket(j) = F1b(j)(m-1_j)
-        x[2 * j + 1] = cscale(ld(L.rd[fam_f1k(j)] + rdn[j]), sq[m[j]]);   // d(m)-1_bra(j) = F1k(j)(m-1_j)
+        x[2 * j] = cscale(ld(at32(L.rd[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]);   // d(m)-1_ket(j) = F1b(j)(m-1_j)
+        x[2 * j + 1] = cscale(ld(at32(L.rd[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]);   // d(m)-1_bra(j) = F1k(j)(m-1_j)
       } else {
         x[2 * j] = czero<R>();
         x[2 * j + 1] = czero<R>();
@@ -164,10 +164,10 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
         acc = cscale(acc, isq[m[j] + 1]);
         if (side == 0) {
           yk[j] = acc;
-          if (j == 0 || m[j] <= P.CD[j] - 2) st(L.wr[fam_f1k(j)] + r, acc);
+          if (j == 0 || m[j] <= P.CD[j] - 2) st(at32(L.wr[fam_f1k(j)], (uint32_t)r), acc);
         } else {
           const bool ok = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-          if (ok) st(L.wr[fam_f1b(MD, j)] + r, acc);
+          if (ok) st(at32(L.wr[fam_f1b(MD, j)], (uint32_t)r), acc);
         }
       }
     }
@@ -184,12 +184,12 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
     // pivot p = d(m) + 1_ket(K): reads p - 1_l for l >= ket(K)
     cx<R> x[NP];
     x[2 * K] = cscale(g0, sq[m[K] + 1]);                                    // p - 1_ket(K) = d(m)
-    x[2 * K + 1] = (m[K] > 0) ? cscale(ld(L.rd[fam_f2(MD, K)] + rdn[K]), sq[m[K]]) : czero<R>();
+    x[2 * K + 1] = (m[K] > 0) ? cscale(ld(at32(L.rd[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]) : czero<R>();
 #pragma unroll
     for (int j = K + 1; j < MD; ++j) {
       if (m[j] > 0) {
-        x[2 * j] = cscale(ld(L.rd[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]);
-        x[2 * j + 1] = cscale(ld(L.rd[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]);
+        x[2 * j] = cscale(ld(at32(L.rd[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
+        x[2 * j + 1] = cscale(ld(at32(L.rd[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
       } else {
         x[2 * j] = czero<R>();
         x[2 * j + 1] = czero<R>();
@@ -205,15 +205,15 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
       if (i == 2 * K + 1) {                 // d(m + 1_K): output amplitude
         ok = true;
         scale = isq[m[K] + 1];
-        dst = L.f0nxt + rup[K];
+        dst = at32(L.f0nxt, (uint32_t)rup[K]);
       } else if (i == 2 * K) {              // F2(K)(m)
         ok = (m[K] <= P.CD[K] - 3);
         scale = isq[m[K] + 2];
-        dst = L.wr[fam_f2(MD, K)] + r;
+        dst = at32(L.wr[fam_f2(MD, K)], (uint32_t)r);
       } else {                              // F1010(K,j)(m) / F1001(K,j)(m)
         ok = (m[j] <= P.CD[j] - 2);
         scale = isq[m[j] + 1];
-        dst = L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)] + r;
+        dst = at32(L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)], (uint32_t)r);
       }
       if (!ok) continue;
       cx<R> acc = czero<R>();

@@ -210,8 +210,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 #pragma unroll
       for (int d = MD - 1; d >= 0; --d)
         if (m[d] > 0) K0 = d;
-      g0acc = ld(V.d0cur + r);
-      G0 = ld(V.fcur[0] + r);
+      g0acc = ld(at32(V.d0cur, (uint32_t)r));
+      G0 = ld(at32(V.fcur[0], (uint32_t)r));
     }
     cx<R> ykg[MD];
 #pragma unroll
@@ -228,25 +228,25 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 #pragma unroll
       for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
       if (valid) {
-        h[2 * K + 1] = cscale(ld(V.gf0nxt + rup[K]), isq[m[K] + 1]);
-        if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(V.gcur[fam_f2(MD, K)] + r), isq[m[K] + 2]);
+        h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
+        if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(at32(V.gcur[fam_f2(MD, K)], (uint32_t)r)), isq[m[K] + 2]);
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
           if (m[j] <= P.CD[j] - 2) {
-            h[2 * j] = cscale(ld(V.gcur[fam_1010(MD, K, j)] + r), isq[m[j] + 1]);
-            h[2 * j + 1] = cscale(ld(V.gcur[fam_1001(MD, K, j)] + r), isq[m[j] + 1]);
+            h[2 * j] = cscale(ld(at32(V.gcur[fam_1010(MD, K, j)], (uint32_t)r)), isq[m[j] + 1]);
+            h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_1001(MD, K, j)], (uint32_t)r)), isq[m[j] + 1]);
           }
         }
         stx(2 * K, cscale(G0, sq[m[K] + 1]));
-        if (m[K] > 0) stx(2 * K + 1, cscale(ld(V.fprev[fam_f2(MD, K)] + rdn[K]), sq[m[K]]));
+        if (m[K] > 0) stx(2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]));
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
           if (m[j] > 0) {
-            stx(2 * j, cscale(ld(V.fprev[fam_1001(MD, K, j)] + rdn[j]), sq[m[j]]));
-            stx(2 * j + 1, cscale(ld(V.fprev[fam_1010(MD, K, j)] + rdn[j]), sq[m[j]]));
+            stx(2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
+            stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
           }
         }
-        if (ODD) stx(NP, ld(V.fcur[fam_f1k(K)] + r));
+        if (ODD) stx(NP, ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r)));
         // adjoint of the reads
 #pragma unroll
         for (int l = 2 * K; l < NP; ++l) {
@@ -257,9 +257,9 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
           if (l == 2 * K) {
             g0acc = cadd(g0acc, cscale(u, sq[m[K] + 1]));
           } else if (l == 2 * K + 1) {
-            if (m[K] > 0) st(V.gprev[fam_f2(MD, K)] + rdn[K], cscale(u, sq[m[K]]));
+            if (m[K] > 0) st(at32(V.gprev[fam_f2(MD, K)], (uint32_t)rdn[K]), cscale(u, sq[m[K]]));
           } else if (m[j] > 0) {
-            st(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)] + rdn[j], cscale(u, sq[m[j]]));
+            st(at32(V.gprev[(l & 1) ? fam_1010(MD, K, j) : fam_1001(MD, K, j)], (uint32_t)rdn[j]), cscale(u, sq[m[j]]));
           }
         }
         if (ODD) {
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 #pragma unroll
           for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
           const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
-          ykg[K] = has_diag_reader ? cadd(ld(V.gcur[fam_f1k(K)] + r), gp) : gp;
+          ykg[K] = has_diag_reader ? cadd(ld(at32(V.gcur[fam_f1k(K)], (uint32_t)r)), gp) : gp;
         }
       }
 #pragma unroll
@@ -290,14 +290,14 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
           for (int j = 0; j < MD; ++j) {
             if (j == 0 || m[j] <= P.CD[j] - 2) {
               const bool kpiv = (j <= K0) && (m[j] <= P.CD[j] - 2);
-              const cx<R> gt = kpiv ? ykg[j] : ld(V.gcur[fam_f1k(j)] + r);
+              const cx<R> gt = kpiv ? ykg[j] : ld(at32(V.gcur[fam_f1k(j)], (uint32_t)r));
               h[2 * j] = cscale(gt, isq[m[j] + 1]);
             }
             const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-            if (okb) h[2 * j + 1] = cscale(ld(V.gcur[fam_f1b(MD, j)] + r), isq[m[j] + 1]);
+            if (okb) h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_f1b(MD, j)], (uint32_t)r)), isq[m[j] + 1]);
             if (m[j] > 0) {
-              stx(2 * j, cscale(ld(V.fprev[fam_f1b(MD, j)] + rdn[j]), sq[m[j]]));
-              stx(2 * j + 1, cscale(ld(V.fprev[fam_f1k(j)] + rdn[j]), sq[m[j]]));
+              stx(2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]));
+              stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]));
             }
           }
           stx(NP, G0);
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             cx<R> u = czero<R>();
 #pragma unroll
             for (int i = 0; i < NP; ++i) cfma_conj(u, sA[i * NP + l], h[i]);
-            st(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)] + rdn[j], cscale(u, sq[m[j]]));
+            st(at32(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)], (uint32_t)rdn[j]), cscale(u, sq[m[j]]));
           }
           cx<R> gp = czero<R>();
 #pragma unroll
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         wave_sync();
       }
     }
-    if (live) st(V.gcur[0] + r, g0acc);
+    if (live) st(at32(V.gcur[0], (uint32_t)r), g0acc);
   }
   // fold the per-lane pair sums over the waves (fixed order) into this block's slot
   cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);

@@ -154,9 +154,9 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     P->group_nodes[g] = acc;
     P->maxN[g] = std::max<int64_t>(mx, 1);
   }
-  // the block kernels address a level's entries with 32-bit byte offsets
-  if (P->B > 1 && MD > 0 && P->maxN[0] * P->B > (int64_t(1) << 28)) {
-    *err = "with undetected modes a photon-number level may hold at most 2^28 amplitudes";
+  // the level kernels address a level's entries with 32-bit byte offsets
+  if (MD > 0 && P->maxN[0] * P->B > (int64_t(1) << 28)) {
+    *err = "a photon-number level (lattice points times undetected block) may hold at most 2^28 amplitudes";
     return FD_ERR_UNSUPPORTED;
   }
   // families
