@@ -156,6 +156,16 @@ struct Plan {
 };
 
 size_t elem_bytes(fd_dtype dt);
+// LDS of the undetected-block fill (vjp: its reverse), one wavefront: the
+// block (twice for the reverse: forward values and cotangents), A and b
+// between undetected positions, the square-root tables, the entry list by
+// weight and its offsets.
+inline size_t ufill_lds_bytes(const Plan& P, bool vjp) {
+  const size_t eb = elem_bytes(P.dt);
+  return (vjp ? 2 : 1) * (size_t)P.B * eb + (size_t)(kMaxUq * kMaxUq + kMaxUq) * eb + 2 * (kMaxCut + 4) * (eb / 2) +
+         (size_t)(P.B + P.wmax + 2) * sizeof(int);
+}
+
 fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
                      std::string* err);
 fd_status ensure_device(Plan* P, std::string* err);
@@ -230,6 +240,9 @@ hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, co
                        void* saved, hipStream_t st);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
 constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
+// LDS tile of the permutations between rho's C order and node order:
+// consecutive lattice points x consecutive undetected-block entries
+constexpr int kOutTN = 64, kOutTK = 16;
 hipError_t launch_prep(const Plan& P, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
                        hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,

@@ -69,39 +69,66 @@ __device__ __forceinline__ void prep_body(const cx<R>* __restrict__ A, const cx<
 // Entry kappa != 0 is pulled from its parent kappa - 1_q, q = first non-zero
 // coordinate, by Eq. recrel restricted to the undetected positions.  One
 // wavefront, the block in LDS, entries visited by weight (host-built list).
+// The weights form a chain of dependent steps, so everything a step reads
+// (entry list, A and b between undetected positions, square-root tables) is
+// staged in LDS first and a step never waits on global memory.
+// LDS: ufill_lds_bytes(plan, false).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int NQ>
 __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __restrict__ Ai,
                                            const cx<R>* __restrict__ bi, cx<R>* G, const int* __restrict__ elist,
                                            const int* __restrict__ woff, int wmax, cx<R>* g) {
-  const int nq = P.nq, npos = P.npos, B = P.B;
+  constexpr int nq = NQ;   // 2 per undetected mode
+  const int npos = P.npos, B = P.B;
   const int lane = threadIdx.x & 63;
+  cx<R>* sA = g + B;   // A between undetected positions, row stride NQ
+  cx<R>* sb = sA + NQ * NQ;
+  R* sq = reinterpret_cast<R*>(sb + NQ);
+  R* isq = sq + (kMaxCut + 4);
+  int* el = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+  int* wo = el + B;
+  for (int t = lane; t < B; t += 64) el[t] = elist[t];
+  for (int t = lane; t < wmax + 2; t += 64) wo[t] = woff[t];
+  for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = ld(Ai + (i / nq) * npos + i % nq);
+  if (lane < nq) sb[lane] = ld(bi + lane);
+  for (int v = lane; v < kMaxCut + 4; v += 64) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
   if (lane == 0) g[0] = ld(G);   // c, written by the prep kernel
   wave_sync();
   for (int w = 1; w <= wmax; ++w) {
-    for (int t = woff[w] + lane; t < woff[w + 1]; t += 64) {
-      const int e = elist[t];
-      int kap[kMaxUq];
+    const int t1 = wo[w + 1];
+    for (int t = wo[w] + lane; t < t1; t += 64) {
+      const int e = el[t];
+      int kap[NQ];
       int rem = e;
 #pragma unroll
-      for (int q = 0; q < kMaxUq; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         kap[q] = q < nq ? ucoord(P, rem, q) : 0;
         rem -= kap[q] * (q < nq ? P.ustride[q] : 0);
       }
-      int qf = nq;
+      // first non-zero coordinate, its stride and value (selected with
+      // constant indices: a lane-dependent index into the plan's arrays
+      // would fetch them from argument memory on every step)
+      int qf = nq, usf = 0, kqf = 0;
 #pragma unroll
-      for (int q = kMaxUq - 1; q >= 0; --q)
-        if (q < nq && kap[q] > 0) qf = q;
-      const int pe = e - P.ustride[qf];
+      for (int q = NQ - 1; q >= 0; --q)
+        if (q < nq && kap[q] > 0) {
+          qf = q;
+          usf = P.ustride[q];
+          kqf = kap[q];
+        }
+      const int pe = e - usf;
       cx<R> acc = czero<R>();
-      cfma(acc, ld(bi + qf), g[pe]);
+      cfma(acc, sb[qf], g[pe]);
 #pragma unroll
-      for (int q = 0; q < kMaxUq; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (q >= nq) continue;
         const int pq = kap[q] - (q == qf ? 1 : 0);
-        if (pq > 0) cfma(acc, ld(Ai + qf * npos + q), cscale(g[pe - P.ustride[q]], sqrt(R(pq))));
+        if (pq > 0) cfma(acc, sA[qf * NQ + q], cscale(g[pe - P.ustride[q]], sq[pq]));
       }
-      g[e] = cscale(acc, R(1) / sqrt(R(kap[qf])));
+      g[e] = cscale(acc, isq[kqf]);
     }
     wave_sync();
   }
@@ -410,7 +437,6 @@ __device__ __forceinline__ cx<R> out_perm_elem(const DevPlan& P, const int* spn,
 // kappa's kOutTN outputs written as one (the element-wise gather reads a
 // 64-byte sector per 16-byte element).  256 threads; returns 1 if a
 // non-finite value was stored.
-constexpr int kOutTN = 64, kOutTK = 16;
 template <typename R>
 __device__ __forceinline__ int out_perm_tile(const DevPlan& P, const int* spn, const int64_t* slv,
                                              const cx<R>* __restrict__ f0, cx<R>* __restrict__ rho, int64_t N,

@@ -32,9 +32,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_prep(const BatchCirc<R>* __r
     for (int i = threadIdx.x; i < nctl; i += blockDim.x) ctl[i] = 0u;
   if (C->P.B == 1) return;
   __syncthreads();
-  if (threadIdx.x < 64)
-    ufill_body<R>(C->P, Ai, Ai + npos * npos, f0, load_global(&C->elist), load_global(&C->woff), C->wmax,
-                  reinterpret_cast<cx<R>*>(smem_raw));
+  if (threadIdx.x < 64) {
+    if (C->P.nq == 2)
+      ufill_body<R, 2>(C->P, Ai, Ai + npos * npos, f0, load_global(&C->elist), load_global(&C->woff), C->wmax,
+                       reinterpret_cast<cx<R>*>(smem_raw));
+    else
+      ufill_body<R, 4>(C->P, Ai, Ai + npos * npos, f0, load_global(&C->elist), load_global(&C->woff), C->wmax,
+                       reinterpret_cast<cx<R>*>(smem_raw));
+  }
 }
 
 // F0 -> rho of every circuit; block b belongs to the circuit c with
@@ -186,7 +191,7 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
     out_slv = std::max<int64_t>(out_slv, (int64_t)(Pl.smax + 2) * 8);
     if (C.kind) {
       lds.sa_bytes = std::max(lds.sa_bytes, (int)align16((size_t)Pl.npos * (Pl.npos + 1) * eb));
-      ufill_lds = std::max(ufill_lds, (size_t)Pl.B * eb);
+      ufill_lds = std::max(ufill_lds, ufill_lds_bytes(Pl, false));
     }
     for (int s = 0; s < C.steps; ++s) work[i] += (double)Pl.ncnt[s] * Pl.B;
   }

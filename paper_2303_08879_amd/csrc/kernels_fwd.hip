@@ -16,13 +16,13 @@ __global__ void k_prep(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
 }
 
 // Step 1 of Algorithm 2: one wavefront, the undetected block in LDS.
-template <typename R>
+template <typename R, int NQ>
 __global__ __launch_bounds__(64) void k_ufill(DevPlan P, const cx<R>* __restrict__ Ai,
                                               const cx<R>* __restrict__ bi, cx<R>* G,
                                               const int* __restrict__ elist, const int* __restrict__ woff,
                                               int wmax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  ufill_body<R>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<cx<R>*>(smem_raw));
+  ufill_body<R, NQ>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<cx<R>*>(smem_raw));
 }
 
 // Algorithm 1 (every mode detected): one thread per lattice point of level S.
@@ -241,12 +241,12 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
     KTimer kt(Pl, KK_UFILL, st);
-    const size_t shm = (size_t)Pl.B * sizeof(cx<R>);
+    const size_t shm = ufill_lds_bytes(Pl, false);
+    auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : &k_ufill<R, 4>;
     if (shm > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ufill<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ufill<R>), dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff,
-                       Pl.wmax);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int S = 0; S <= Pl.smax && Pl.MD > 0; ++S) {
@@ -269,7 +269,8 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   }
   if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
   const int64_t total = Pl.out_elems;
-  const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
+  const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
+  const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
   const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) +
                      16 * (((size_t)(Pl.smax + 2) * 8 + 15) / 16) + (size_t)kOutTN * (kOutTK + 1) * sizeof(cx<R>);
   KTimer kt(Pl, KK_OUT_PERM, st);

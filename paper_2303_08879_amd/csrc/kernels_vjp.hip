@@ -55,6 +55,46 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
   for (int i = threadIdx.x; i <= P.smax; i += blockDim.x) slv[i] = P.MD > 0 ? P.lvl[i] : 0;
   __syncthreads();
   const int MD = P.MD, B = P.B, pnw = P.pnw;
+  if (B > 1) {
+    // tiles of kOutTN consecutive C-order lattice points n by kOutTK block
+    // entries kappa through LDS, the inverse of the output permutation: each
+    // kappa's run of n is read as one, each node's run of kappa written as one
+    cx<R>* tl = reinterpret_cast<cx<R>*>(reinterpret_cast<unsigned char*>(slv) + 16 * (((P.smax + 2) * 8 + 15) / 16));
+    constexpr int LD = kOutTK + 1;
+    const int64_t ntn = (N + kOutTN - 1) / kOutTN, tiles = ntn * ((B + kOutTK - 1) / kOutTK);
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+      const int64_t n0 = (tile % ntn) * kOutTN;
+      const int kap0 = (int)(tile / ntn) * kOutTK;
+      {
+        const int nl = threadIdx.x % kOutTN;
+        for (int k = threadIdx.x / kOutTN; k < kOutTK; k += kThreads / kOutTN)
+          if (n0 + nl < N && kap0 + k < B) tl[nl * LD + k] = ld(drho + (size_t)(kap0 + k) * N + n0 + nl);
+      }
+      __syncthreads();
+      const int kl = threadIdx.x % kOutTK;
+      for (int nl = threadIdx.x / kOutTK; nl < kOutTN; nl += kThreads / kOutTK) {
+        const int64_t n = n0 + nl;
+        if (n < N && kap0 + kl < B) {
+          int64_t rem = n;
+          int v[kMaxD];
+          int S = 0;
+          for (int d = MD - 1; d >= 0; --d) {
+            v[d] = (int)(rem % P.CD[d]);
+            rem /= P.CD[d];
+            S += v[d];
+          }
+          int rank = 0, sd = S;
+          for (int d = 0; d < MD; ++d) {
+            rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - v[d]);
+            sd -= v[d];
+          }
+          st(g0 + (size_t)(slv[S] + rank) * B + kap0 + kl, tl[nl * LD + kl]);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t kap = idx / N;
@@ -659,78 +699,107 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
 // cotangents in LDS: an entry's cotangent gathers from the targets that used
 // it as pivot (x + 1_q with first non-zero coordinate q) or as a read
 // (x + 1_q2 + 1_q with parent x + 1_q2, first non-zero coordinate q).
+// As in the forward fill, every operand of the weight steps is staged in LDS
+// first (incoming cotangents included), so the steps never wait on global
+// memory.  LDS: ufill_lds_bytes(plan, true).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int NQ>
 __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __restrict__ Ai,
                                                   const cx<R>* __restrict__ bi, const cx<R>* __restrict__ G,
                                                   const cx<R>* __restrict__ gin, const int* __restrict__ elist,
                                                   const int* __restrict__ woff, int wmax, double2* slot,
                                                   cx<R>* cbar) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nq = P.nq, npos = P.npos, B = P.B;
+  constexpr int nq = NQ;   // 2 per undetected mode
+  const int npos = P.npos, B = P.B;
   const int NR = npos + 1;
   const int lane = threadIdx.x;
   cx<R>* Gl = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* gf = Gl + B;
-  for (int e = lane; e < B; e += 64) Gl[e] = ld(G + e);
+  cx<R>* sA = gf + B;   // A between undetected positions, row stride NQ
+  cx<R>* sb = sA + NQ * NQ;
+  R* sq = reinterpret_cast<R*>(sb + NQ);
+  R* isq = sq + (kMaxCut + 4);
+  int* el = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+  int* wo = el + B;
+  for (int e = lane; e < B; e += 64) {
+    Gl[e] = ld(G + e);
+    gf[e] = ld(gin + e);
+    el[e] = elist[e];
+  }
+  for (int t = lane; t < wmax + 2; t += 64) wo[t] = woff[t];
+  for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = ld(Ai + (i / nq) * npos + i % nq);
+  if (lane < nq) sb[lane] = ld(bi + lane);
+  for (int v = lane; v < kMaxCut + 4; v += 64) {
+    sq[v] = sqrt(R(v));
+    isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
+  }
   wave_sync();
-  cx<double> ab[kMaxUq][kMaxUq + 1];
+  cx<double> ab[NQ][NQ + 1];
 #pragma unroll
-  for (int a = 0; a < kMaxUq; ++a)
+  for (int a = 0; a < NQ; ++a)
 #pragma unroll
-    for (int c = 0; c <= kMaxUq; ++c) ab[a][c] = cmake<double>(0.0, 0.0);
+    for (int c = 0; c <= NQ; ++c) ab[a][c] = cmake<double>(0.0, 0.0);
   for (int w = wmax; w >= 0; --w) {
-    for (int t = woff[w] + lane; t < woff[w + 1]; t += 64) {
-      const int e = elist[t];
-      int x[kMaxUq];
+    const int t1 = wo[w + 1];
+    for (int t = wo[w] + lane; t < t1; t += 64) {
+      const int e = el[t];
+      int x[NQ];
       int rem = e;
 #pragma unroll
-      for (int q = 0; q < kMaxUq; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         x[q] = q < nq ? ucoord(P, rem, q) : 0;
         rem -= x[q] * (q < nq ? P.ustride[q] : 0);
       }
-      int first0 = nq;
+      // first non-zero coordinate, its stride and value, selected with
+      // constant indices (a lane-dependent index into the plan's arrays
+      // would fetch them from argument memory on every step)
+      int first0 = nq, usf = 0, xf = 0;
 #pragma unroll
-      for (int q = kMaxUq - 1; q >= 0; --q)
-        if (q < nq && x[q] > 0) first0 = q;
-      cx<R> acc = ld(gin + e);
+      for (int q = NQ - 1; q >= 0; --q)
+        if (q < nq && x[q] > 0) {
+          first0 = q;
+          usf = P.ustride[q];
+          xf = x[q];
+        }
+      cx<R> acc = gf[e];
 #pragma unroll
-      for (int q = 0; q < kMaxUq; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (q >= nq || q > first0) continue;
         if (x[q] + 1 < P.udims[q]) {
-          const cx<R> ht = cscale(gf[e + P.ustride[q]], R(1) / sqrt(R(x[q] + 1)));
-          cfma_conj(acc, ld(bi + q), ht);
+          const cx<R> ht = cscale(gf[e + P.ustride[q]], isq[x[q] + 1]);
+          cfma_conj(acc, sb[q], ht);
         }
 #pragma unroll
-        for (int q2 = 0; q2 < kMaxUq; ++q2) {
+        for (int q2 = 0; q2 < NQ; ++q2) {
           if (q2 < q || q2 >= nq) continue;
           const int p2 = x[q2] + 1;                  // parent coordinate along q2
           const int pq = x[q] + (q2 == q ? 1 : 0);   // parent coordinate along q
           if (p2 >= P.udims[q2] || pq + 1 >= P.udims[q]) continue;
-          const cx<R> ht = cscale(gf[e + P.ustride[q2] + P.ustride[q]], R(1) / sqrt(R(pq + 1)));
+          const cx<R> ht = cscale(gf[e + P.ustride[q2] + P.ustride[q]], isq[pq + 1]);
           cx<R> u = czero<R>();
-          cfma_conj(u, ld(Ai + q * npos + q2), ht);
-          acc = cadd(acc, cscale(u, sqrt(R(p2))));
+          cfma_conj(u, sA[q * NQ + q2], ht);
+          acc = cadd(acc, cscale(u, sq[p2]));
         }
       }
       gf[e] = acc;
       if (e > 0) {
         // this entry as a target: parent x - 1_first0, direction first0
         const int qf = first0;
-        const int pe = e - P.ustride[qf];
-        const cx<R> h = cscale(acc, R(1) / sqrt(R(x[qf])));
+        const int pe = e - usf;
+        const cx<R> h = cscale(acc, isq[xf]);
         const cx<R> gp = Gl[pe];
 #pragma unroll
-        for (int a = 0; a < kMaxUq; ++a) {
+        for (int a = 0; a < NQ; ++a) {
           if (a != qf) continue;
-          ab[a][kMaxUq].x += (double)gp.x * h.x + (double)gp.y * h.y;
-          ab[a][kMaxUq].y += (double)gp.x * h.y - (double)gp.y * h.x;
+          ab[a][NQ].x += (double)gp.x * h.x + (double)gp.y * h.y;
+          ab[a][NQ].y += (double)gp.x * h.y - (double)gp.y * h.x;
 #pragma unroll
-          for (int q2 = 0; q2 < kMaxUq; ++q2) {
+          for (int q2 = 0; q2 < NQ; ++q2) {
             if (q2 >= nq) continue;
             const int pq2 = x[q2] - (q2 == qf ? 1 : 0);
             if (pq2 <= 0) continue;
-            const cx<R> g2 = cscale(Gl[pe - P.ustride[q2]], sqrt(R(pq2)));
+            const cx<R> g2 = cscale(Gl[pe - P.ustride[q2]], sq[pq2]);
             ab[a][q2].x += (double)g2.x * h.x + (double)g2.y * h.y;
             ab[a][q2].y += (double)g2.x * h.y - (double)g2.y * h.x;
           }
@@ -741,10 +810,10 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
   }
   // butterfly sums over the wavefront (fixed order), lane 0 adds to the slot
 #pragma unroll
-  for (int a = 0; a < kMaxUq; ++a) {
+  for (int a = 0; a < NQ; ++a) {
 #pragma unroll
-    for (int c = 0; c <= kMaxUq; ++c) {
-      if (a >= nq || (c >= nq && c != kMaxUq)) continue;   // uniform
+    for (int c = 0; c <= NQ; ++c) {
+      if (a >= nq || (c >= nq && c != NQ)) continue;   // uniform
       double vx = ab[a][c].x, vy = ab[a][c].y;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
@@ -752,7 +821,7 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
         vy += __shfl_xor(vy, off, 64);
       }
       if (lane == 0) {
-        const int p = a * NR + (c == kMaxUq ? npos : c);
+        const int p = a * NR + (c == NQ ? npos : c);
         double2 v = slot[p];
         slot[p] = make_double2(v.x + vx, v.y + vy);
       }
@@ -765,7 +834,7 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
 // caller's block order (zero for dropped modes), write dc.
 struct FinalArgs {
   int blk2pos[2 * kMaxModes];
-  int M2, npos, nslots;
+  int M2, npos;
 };
 
 template <typename R>
@@ -787,17 +856,28 @@ __global__ __launch_bounds__(kThreads) void k_vjp_final(const double2* __restric
     if (p >= 0) c1 = p * NR + a.npos;
   }
   double sx = 0.0, sy = 0.0;
-  if (c1 >= 0)
-    for (int s = threadIdx.x; s < a.nslots; s += blockDim.x) {
-      const double2 v = partial[(size_t)s * P + c1];
-      sx += v.x;
-      sy += v.y;
+  // slots threadIdx.x, + kThreads, ... in order; a fixed trip count lets the
+  // loads of all of them go out before the first add
+  static_assert(kPartialSlots % kThreads == 0, "slot count");
+  constexpr int KS = kPartialSlots / kThreads;
+  if (c1 >= 0) {
+    double2 v[KS], w[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const size_t s = threadIdx.x + (size_t)k * kThreads;
+      v[k] = partial[s * P + c1];
+      w[k] = c2 >= 0 ? partial[s * P + c2] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      sx += v[k].x;
+      sy += v[k].y;
       if (c2 >= 0) {
-        const double2 w = partial[(size_t)s * P + c2];
-        sx += w.x;
-        sy += w.y;
+        sx += w[k].x;
+        sy += w[k].y;
       }
     }
+  }
   red[threadIdx.x] = make_double2(sx, sy);
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
@@ -885,8 +965,11 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   cx<R>* g0 = reinterpret_cast<cx<R>*>(ws + V.g0);
   {
     const int64_t total = Pl.out_elems;
-    const int64_t grid = std::min<int64_t>((total + kThreads - 1) / kThreads, 65536);
-    const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) + (size_t)(Pl.smax + 2) * 8;
+    const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
+    const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
+    const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) +
+                       16 * (((size_t)(Pl.smax + 2) * 8 + 15) / 16) +
+                       (Pl.B > 1 ? (size_t)kOutTN * (kOutTK + 1) * sizeof(cx<R>) : 0);
     KTimer kt(Pl, KK_PERM_IN, st);
     hipLaunchKernelGGL((k_perm_in<R>), dim3(grid), dim3(kThreads), shm, st, P,
                        reinterpret_cast<const cx<R>*>(drho), g0, (int64_t)Pl.nodes_total, total);
@@ -993,12 +1076,13 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   if (Pl.B > 1) {
     const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + Ls.f0);
     KTimer kt(Pl, KK_UFILL_VJP, st);
-    const size_t shm = 2 * (size_t)Pl.B * sizeof(cx<R>);
+    const size_t shm = ufill_lds_bytes(Pl, true);
+    auto* kfn = Pl.nq == 2 ? &k_ufill_vjp<R, 2> : &k_ufill_vjp<R, 4>;
     if (shm > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ufill_vjp<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL((k_ufill_vjp<R>), dim3(1), dim3(64), shm, st, P, Ai, bi, G0blk, gseed, Pl.d_elist,
-                       Pl.d_woff, Pl.wmax, partial + (size_t)(kPartialSlots - 1) * PP, cb);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, G0blk, gseed, Pl.d_elist, Pl.d_woff, Pl.wmax,
+                       partial + (size_t)(kPartialSlots - 1) * PP, cb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cbar_src = cb;
   }
@@ -1008,7 +1092,6 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   for (int p = 0; p < Pl.npos; ++p) fa.blk2pos[Pl.pos2blk[p]] = p;
   fa.M2 = 2 * Pl.M;
   fa.npos = Pl.npos;
-  fa.nslots = kPartialSlots;
   const int nout = fa.M2 * fa.M2 + fa.M2 + 1;
   KTimer kt(Pl, KK_VJP_FINAL, st);
   hipLaunchKernelGGL((k_vjp_final<R>), dim3(nout), dim3(kThreads), 0, st, partial, fa, cbar_src,
