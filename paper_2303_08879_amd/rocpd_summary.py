@@ -3,6 +3,9 @@
     python rocpd_summary.py <results.db>              per-kernel table (kernel trace)
     python rocpd_summary.py --pmc <counter_collection.csv> [name-filter ...]
                                                       mean counter value per dispatch
+    python rocpd_summary.py --timeline <results.db> <marker> <k> <n>
+                                                      n dispatches in launch order from the
+                                                      k-th dispatch whose name contains marker
 """
 import csv
 import sqlite3
@@ -44,8 +47,25 @@ def pmc_summary(path, filters=()):
     return "\n".join(out)
 
 
+def timeline(db, marker, k, n):
+    """Dispatches in start order: kernel, workgroups, start offset and duration
+    (us) -- one pass of a sweep, to read per-launch latency against size."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, duration, grid_x / workgroup_x from kernels order by start").fetchall()
+    hits = [i for i, r in enumerate(rows) if marker in r[0]]
+    i0 = hits[k]
+    t0 = rows[i0][1]
+    out = ["| # | kernel | workgroups | start us | duration us |", "|---|---|---|---|---|"]
+    for j, (name, start, dur, wg) in enumerate(rows[i0:i0 + n]):
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| {j} | `{short}` | {wg} | {(start - t0) / 1000:.1f} | {dur / 1000:.1f} |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "--pmc":
         print(pmc_summary(sys.argv[2], sys.argv[3:]))
+    elif sys.argv[1] == "--timeline":
+        print(timeline(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])))
     else:
         print(summary(sys.argv[1]))
