@@ -255,6 +255,52 @@ const char* fd_last_error(void);
  * FD_ERR_HIP if a batched sweep gave up waiting at a step barrier. */
 fd_status fd_device_status(fd_plan p, hipStream_t stream);
 
+/* ---- Pure states: the state vector ------------------------------------
+ * The Fock amplitudes psi[n] = <n|psi>, 0 <= n_j < C_j, of a pure Gaussian
+ * state given by its Bargmann triple (A: M x M complex symmetric, b: M, c):
+ * the generating-function recurrence of Sec. 2.1 with D = M indices (one per
+ * mode), psi[n] = (b_i psi[n - 1_i] + sum_l sqrt(n_l - [l = i]) A_il
+ * psi[n - 1_i - 1_l]) / sqrt(n_i) with i the first mode where n_i > 0, swept
+ * level by level in the total photon number |n| (the pure-state case of
+ * Sec. 2.2 and the conditional pure states of Sec. 3.2: a state vector's
+ * conditional amplitudes are slices of psi).  With b = 0 every amplitude of
+ * odd |n| vanishes (Sec. 2.4) and only even levels are computed.
+ * Limits: at most 8 modes with cutoff >= 2 (modes with cutoff 1 carry no
+ * photons and are dropped), every cutoff in [1, 64], prod C_j < 2^31, one
+ * level <= 2^28 amplitudes. */
+typedef struct fd_state_plan_s* fd_state_plan;
+
+/* flags: FD_B_ZERO (b == 0 promised: odd levels are not computed, a non-zero
+ * b is reported through fd_state_device_status), FD_B_GENERAL, or FD_B_AUTO
+ * (each call reads the M entries of b on the host and takes the b = 0 sweep
+ * when they are all exactly zero).  No device memory is touched here. */
+fd_status fd_state_plan_create(int M, const int* cutoffs, fd_dtype dt, uint32_t flags, fd_state_plan* out);
+fd_status fd_state_plan_destroy(fd_state_plan p);
+/* Workspace bytes for fock_state_fwd (the amplitudes in level order plus A
+ * and b of the kept modes); 256-byte aligned device memory. */
+fd_status fd_state_plan_workspace(fd_state_plan p, size_t* bytes);
+
+/* fock_state_fwd -- psi of the triple, stream-ordered on `stream`.
+ *   A          device, M x M, row-major, complex of the plan's dtype
+ *   b          device, M entries;  c  device, 1 entry
+ *   psi        device output, prod_j C_j entries in C order over modes
+ *              0..M-1 (the last mode fastest); written completely
+ *   workspace  device, >= fd_state_plan_workspace bytes, 256-byte aligned;
+ *              may be reused once the call has completed on the stream
+ * Errors: FD_ERR_INVALID_ARG (NULL or misaligned pointer, plan made on
+ * another device), FD_ERR_WORKSPACE, FD_ERR_HIP; non-finite inputs or
+ * outputs and a non-zero b under FD_B_ZERO are reported by
+ * fd_state_device_status. */
+fd_status fock_state_fwd(fd_state_plan p, const void* A, const void* b, const void* c, void* psi,
+                         void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* As fd_device_status, for a state plan. */
+fd_status fd_state_device_status(fd_state_plan p, hipStream_t stream);
+/* As fd_plan_timing / fd_plan_kernel_times; kinds FD_K_PREP (A, b, c
+ * staging), FD_K_FWD_LEVEL (one launch per computed level), FD_K_OUT_PERM. */
+fd_status fd_state_plan_timing(fd_state_plan p, uint32_t kind_mask);
+fd_status fd_state_plan_kernel_times(fd_state_plan p, int kind, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

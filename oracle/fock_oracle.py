@@ -51,6 +51,7 @@ __all__ = [
     "from_interleaved",
     "taylor_box",
     "full_density_matrix",
+    "state_vector",
     "select_outputs",
     "fock_diag",
     "fock_diag_pattern",
@@ -150,6 +151,14 @@ def taylor_box(A, b, c, dims):
                 acc = acc + A[d, l] * (roots[l - d - 1] * _shift_down(cur, ax))
             sub[k + 1] = acc / math.sqrt(k + 1)
     return G
+
+
+def state_vector(A, b, c, cutoffs):
+    """Tier A for a pure state: psi[n] = <n|psi> for 0 <= n < cutoffs, the
+    Taylor box of the state's generating function with one index per mode
+    (D = M, Sec. 2.1; the pure-state case of Sec. 2.2).  A is M x M, b has M
+    entries."""
+    return taylor_box(A, b, c, cutoffs)
 
 
 def full_density_matrix(A, b, c, cutoffs):

@@ -13,6 +13,12 @@ struct fd_plan_s {
   fd::Plan P;
 };
 
+// A state-vector plan: the tables of the all-detected plan over the same
+// modes (the lattice of n, its levels and the output permutation).
+struct fd_state_plan_s {
+  fd_plan inner = nullptr;
+};
+
 namespace {
 thread_local std::string g_err;
 
@@ -25,8 +31,10 @@ fd_status ok() {
   return FD_OK;
 }
 
-// Decide the b = 0 schedule (Sec. 2.4) for this call.
-fd_status decide_b_zero(const fd::Plan& P, const void* b, hipStream_t s, bool* b_zero) {
+// Decide the b = 0 schedule (Sec. 2.4) for this call; b has nb entries
+// (2M for a density matrix, M for a state vector).
+fd_status decide_b_zero(const fd::Plan& P, const void* b, hipStream_t s, bool* b_zero, int nb = -1) {
+  if (nb < 0) nb = 2 * P.M;
   if (P.flags == FD_B_ZERO) {
     *b_zero = true;
     return FD_OK;
@@ -36,17 +44,17 @@ fd_status decide_b_zero(const fd::Plan& P, const void* b, hipStream_t s, bool* b
     return FD_OK;
   }
   const size_t eb = fd::elem_bytes(P.dt);
-  std::vector<unsigned char> h((size_t)2 * P.M * eb);
+  std::vector<unsigned char> h((size_t)nb * eb);
   if (hipMemcpyAsync(h.data(), b, h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(FD_ERR_HIP, "reading b for the b = 0 test failed");
   bool z = true;
   if (P.dt == FD_C64) {
     const float* v = reinterpret_cast<const float*>(h.data());
-    for (size_t i = 0; i < (size_t)4 * P.M; ++i) z = z && v[i] == 0.0f;
+    for (size_t i = 0; i < (size_t)2 * nb; ++i) z = z && v[i] == 0.0f;
   } else {
     const double* v = reinterpret_cast<const double*>(h.data());
-    for (size_t i = 0; i < (size_t)4 * P.M; ++i) z = z && v[i] == 0.0;
+    for (size_t i = 0; i < (size_t)2 * nb; ++i) z = z && v[i] == 0.0;
   }
   *b_zero = z;
   return FD_OK;
@@ -404,6 +412,67 @@ fd_status fd_plan_kernel_times(fd_plan p, int kind, int64_t* launches, double* t
 }
 
 const char* fd_last_error(void) { return g_err.c_str(); }
+
+fd_status fd_state_plan_create(int M, const int* cutoffs, fd_dtype dt, uint32_t flags, fd_state_plan* out) {
+  if (!out) return fail(FD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (M < 1 || M > 16) return fail(FD_ERR_INVALID_ARG, "M must be in [1, 16]");
+  fd_state_plan sp = new (std::nothrow) fd_state_plan_s;
+  if (!sp) return fail(FD_ERR_OOM, "host allocation failed");
+  const uint32_t all = M >= 32 ? 0xffffffffu : ((1u << M) - 1u);
+  fd_status s = fd_plan_create(M, cutoffs, all, dt, flags, &sp->inner);
+  if (s != FD_OK) {
+    delete sp;
+    return s;
+  }
+  *out = sp;
+  return ok();
+}
+
+fd_status fd_state_plan_destroy(fd_state_plan sp) {
+  if (!sp) return ok();
+  fd_status s = fd_plan_destroy(sp->inner);
+  delete sp;
+  return s;
+}
+
+fd_status fd_state_plan_workspace(fd_state_plan sp, size_t* bytes) {
+  if (!sp || !bytes) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  *bytes = fd::state_ws_bytes(sp->inner->P);
+  return ok();
+}
+
+fd_status fock_state_fwd(fd_state_plan sp, const void* A, const void* b, const void* c, void* psi, void* workspace,
+                         size_t ws_bytes, hipStream_t stream) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = sp->inner->P;
+  fd_status s = check_ptrs(P, {A, b, c, psi, workspace});
+  if (s != FD_OK) return s;
+  if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < fd::state_ws_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  bool b_zero = false;
+  if ((s = decide_b_zero(P, b, stream, &b_zero, P.M)) != FD_OK) return s;
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  if (fd::run_state_fwd(P, b_zero, A, b, c, psi, workspace, stream) != hipSuccess)
+    return fail(FD_ERR_HIP, "kernel launch failed");
+  return ok();
+}
+
+fd_status fd_state_device_status(fd_state_plan sp, hipStream_t stream) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  return fd_device_status(sp->inner, stream);
+}
+
+fd_status fd_state_plan_timing(fd_state_plan sp, uint32_t kind_mask) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  return fd_plan_timing(sp->inner, kind_mask);
+}
+
+fd_status fd_state_plan_kernel_times(fd_state_plan sp, int kind, int64_t* launches, double* total_ms) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  return fd_plan_kernel_times(sp->inner, kind, launches, total_ms);
+}
 
 fd_status fd_device_status(fd_plan p, hipStream_t stream) {
   if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");

@@ -126,6 +126,25 @@ __device__ __forceinline__ int ucoord(const DevPlan& P, int rem, int q) { return
 // PN[d][x] for x in [-1, smax+1]; table row width pnw.
 __device__ __forceinline__ int pnv(const int* spn, int pnw, int d, int x) { return spn[d * pnw + x + 1]; }
 
+// Node-order position (level offset + rank) of the detected lattice point
+// whose C-order index is x (last detected mode fastest), 0 <= x < prod CD <
+// 2^31.  Digits come last mode first, each from one double multiply: (x +
+// 1/2) / C lies at least 1 / (2 C) >= 2^-7 from an integer and the rounded
+// product is off by under 2^-21, so truncation gives floor(x / C) exactly;
+// the suffix sums the rank needs accumulate in the same pass.
+__device__ __forceinline__ int64_t node_of_cindex(const DevPlan& P, const int* spn, const int64_t* slv, int x) {
+  const int pnw = P.pnw;
+  int rem = x, suf = 0, rank = 0;
+  for (int d = P.MD - 1; d >= 0; --d) {
+    const int q = (int)((rem + 0.5) * P.cinv[d]);
+    const int nd = rem - q * P.CD[d];
+    rem = q;
+    suf += nd;
+    rank += pnv(spn, pnw, d + 1, suf) - pnv(spn, pnw, d + 1, suf - nd);
+  }
+  return slv[suf] + rank;
+}
+
 // Lattice point of rank r at level S (lexicographic, first mode slowest).
 // s[d] = S - sum_{i<d} m_i.  The count of points of sub-box d+1 whose sum
 // lies in (s - v, s] is PN[d+1][s] - PN[d+1][s-v]; m_d is the largest v with

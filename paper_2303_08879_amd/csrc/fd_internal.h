@@ -73,6 +73,7 @@ struct DevPlan {
   int udims[kMaxUq];         // U block dims [C_u.., C_u..]
   int ustride[kMaxUq];
   double uinv[kMaxUq];       // 1 / ustride (exact coordinate split, see ucoord)
+  double cinv[kMaxD];        // 1 / CD (exact digit split of C-order indices, see node_of_cindex)
   const int* pn;             // [(MD+1) x pnw]: PN[d][s+1] = #points of sub-box d with sum <= s
   const int64_t* lvl;        // [(MD) x (smax+2)]: node offset of level S for group g (store-all)
   const int* node;           // Algorithm 2 plans: node records in level-major order (else null)
@@ -245,6 +246,12 @@ constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its 
 constexpr int kOutTN = 64, kOutTK = 16;
 hipError_t launch_prep(const Plan& P, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
                        hipStream_t st);
+// F0 in node order (level-major, prod_D C_j x B entries) -> rho in C order.
+hipError_t launch_out_perm(const Plan& P, const void* f0, void* rho, hipStream_t st);
+// State vectors (kernels_state.hip): workspace bytes and the forward sweep.
+size_t state_ws_bytes(const Plan& P);
+hipError_t run_state_fwd(const Plan& P, bool b_zero, const void* A, const void* b, const void* c, void* psi, void* ws,
+                         hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,
                    const void* drho, void* dA, void* db, void* dc, void* ws, hipStream_t st);
 

@@ -407,28 +407,15 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 }
 
 // ---------------------------------------------------------------------------
-// F0 (level-major nodes of B entries) -> rho, C order [kappa][n_D]: the value
-// of output element idx (spn = PN table, slv = level node offsets of F0).
+// F0 -> rho for plans without undetected modes (one entry per node): the
+// value of output element idx, C order over the detected modes (spn = PN
+// table, slv = level node offsets of F0).
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ cx<R> out_perm_elem(const DevPlan& P, const int* spn, const int64_t* slv,
                                                const cx<R>* __restrict__ f0, int64_t N, int64_t idx) {
-  const int MD = P.MD, B = P.B, pnw = P.pnw;
-  const int64_t kap = idx / N;
-  int64_t rem = idx - kap * N;
-  int n[kMaxD];
-  int S = 0;
-  for (int d = MD - 1; d >= 0; --d) {
-    n[d] = (int)(rem % P.CD[d]);
-    rem /= P.CD[d];
-    S += n[d];
-  }
-  int rank = 0, sd = S;
-  for (int d = 0; d < MD; ++d) {
-    rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - n[d]);
-    sd -= n[d];
-  }
-  return ld(f0 + (size_t)(slv[S] + rank) * B + kap);
+  (void)N;
+  return ld(f0 + node_of_cindex(P, spn, slv, (int)idx));
 }
 
 // F0 -> rho for plans with undetected modes, one tile of kOutTN consecutive

@@ -241,7 +241,9 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
   }
   if (qe != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       per_cu < 1) {
-    *err = "occupancy query for the batched sweep failed";
+    *err = "occupancy query for the batched sweep failed (" + std::string(hipGetErrorString(qe)) +
+           ", workgroups per CU " + std::to_string(per_cu) + ", LDS bytes " + std::to_string(S->shm_sweep) +
+           ", wavefronts per workgroup " + std::to_string(lds.waves) + ")";
     return FD_ERR_HIP;
   }
   int coop = 0;

@@ -218,6 +218,20 @@ hipError_t launch_prep(const Plan& Pl, const void* A, const void* b, const void*
   return hipGetLastError();
 }
 
+// F0 in node order -> rho (C order), with the non-finite check.
+template <typename R>
+static hipError_t launch_out_perm_t(const Plan& Pl, const DevPlan& P, const cx<R>* f0, void* rho, hipStream_t st) {
+  const int64_t total = Pl.out_elems;
+  const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
+  const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
+  const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) +
+                     16 * (((size_t)(Pl.smax + 2) * 8 + 15) / 16) + (size_t)kOutTN * (kOutTK + 1) * sizeof(cx<R>);
+  KTimer kt(Pl, KK_OUT_PERM, st);
+  hipLaunchKernelGGL((k_out_perm<R>), dim3(grid), dim3(kThreads), shm, st, P, f0, reinterpret_cast<cx<R>*>(rho),
+                     (int64_t)Pl.nodes_total, total, Pl.d_status);
+  return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho,
                                 char* ws, char* saved, hipStream_t st) {
@@ -268,15 +282,13 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
     if (e != hipSuccess) return e;
   }
   if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
-  const int64_t total = Pl.out_elems;
-  const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
-  const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
-  const size_t shm = 16 * ((((size_t)(Pl.MD + 1) * (Pl.smax + 3)) * 4 + 15) / 16) +
-                     16 * (((size_t)(Pl.smax + 2) * 8 + 15) / 16) + (size_t)kOutTN * (kOutTK + 1) * sizeof(cx<R>);
-  KTimer kt(Pl, KK_OUT_PERM, st);
-  hipLaunchKernelGGL((k_out_perm<R>), dim3(grid), dim3(kThreads), shm, st, P, f0, reinterpret_cast<cx<R>*>(rho),
-                     (int64_t)Pl.nodes_total, total, Pl.d_status);
-  return hipGetLastError();
+  return launch_out_perm_t<R>(Pl, P, f0, rho, st);
+}
+
+hipError_t launch_out_perm(const Plan& Pl, const void* f0, void* rho, hipStream_t st) {
+  const DevPlan P = make_devplan(Pl, false);
+  if (Pl.dt == FD_C64) return launch_out_perm_t<float>(Pl, P, static_cast<const cx<float>*>(f0), rho, st);
+  return launch_out_perm_t<double>(Pl, P, static_cast<const cx<double>*>(f0), rho, st);
 }
 
 hipError_t run_forward(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,

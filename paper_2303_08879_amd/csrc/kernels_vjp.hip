@@ -95,24 +95,10 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
     }
     return;
   }
+  // one entry per node (no undetected modes): C-order index -> node order
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t kap = idx / N;
-    int64_t rem = idx - kap * N;
-    int n[kMaxD];
-    int S = 0;
-    for (int d = MD - 1; d >= 0; --d) {
-      n[d] = (int)(rem % P.CD[d]);
-      rem /= P.CD[d];
-      S += n[d];
-    }
-    int rank = 0, sd = S;
-    for (int d = 0; d < MD; ++d) {
-      rank += pnv(spn, pnw, d + 1, sd) - pnv(spn, pnw, d + 1, sd - n[d]);
-      sd -= n[d];
-    }
-    st(g0 + (size_t)(slv[S] + rank) * B + kap, ld(drho + idx));
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    st(g0 + node_of_cindex(P, spn, slv, (int)idx), ld(drho + idx));
 }
 
 constexpr int kWRec = 16;

@@ -242,6 +242,7 @@ DevPlan make_devplan(const Plan& P, bool odd) {
     d.ustride[q] = P.ustride[q];
     d.uinv[q] = 1.0 / P.ustride[q];
   }
+  for (int j = 0; j < P.MD; ++j) d.cinv[j] = 1.0 / P.CD[j];
   d.pn = P.d_pn;
   d.lvl = P.d_lvl;
   d.node = P.d_node;

@@ -25,7 +25,8 @@ EXPORTS = [
     "fd_plan_create", "fd_plan_destroy", "fd_plan_workspace", "fd_plan_query", "fock_diag_fwd",
     "fock_diag_vjp", "detection_probs", "fock_diag_fwd_batch", "fd_last_error", "fd_device_status",
     "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs", "fd_batch_set_tuning", "fd_batch_get_tuning",
-    "fock_diag_vjp_batch",
+    "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
+    "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -77,6 +78,13 @@ def lib():
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     L.fd_batch_set_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.fd_batch_get_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+    L.fd_state_plan_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, u32, ctypes.POINTER(vp)]
+    L.fd_state_plan_destroy.argtypes = [vp]
+    L.fd_state_plan_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.fock_state_fwd.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fd_state_device_status.argtypes = [vp, vp]
+    L.fd_state_plan_timing.argtypes = [vp, u32]
+    L.fd_state_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         if name != "fd_last_error":
             getattr(L, name).restype = i32
@@ -141,6 +149,56 @@ class Plan:
         v = ctypes.c_int64()
         _check(lib().fd_plan_query(self.handle, int(what), ctypes.byref(v)))
         return v.value
+
+
+class StatePlan:
+    """fd_state_plan_create / fd_state_plan_destroy: the state vector psi of a
+    pure state over ``cutoffs`` (shape = cutoffs, C order)."""
+
+    def __init__(self, cutoffs, dtype=torch.complex128, b_mode="auto"):
+        self.cutoffs = [int(c) for c in cutoffs]
+        self.M = len(self.cutoffs)
+        self.dtype = dtype
+        dt = FD_C128 if dtype == torch.complex128 else FD_C64
+        flags = {"auto": FD_B_AUTO, "zero": FD_B_ZERO, "general": FD_B_GENERAL}[b_mode]
+        arr = (ctypes.c_int * self.M)(*self.cutoffs)
+        h = ctypes.c_void_p()
+        _check(lib().fd_state_plan_create(self.M, arr, dt, flags, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.fd_state_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def out_shape(self):
+        return tuple(self.cutoffs)
+
+    def workspace(self):
+        n = ctypes.c_size_t()
+        _check(lib().fd_state_plan_workspace(self.handle, ctypes.byref(n)))
+        return n.value
+
+
+def fock_state_fwd(plan, A, b, c, psi, workspace, stream=None):
+    _check(lib().fock_state_fwd(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(psi), _ptr(workspace),
+                                _nbytes(workspace), _stream(stream)))
+
+
+def fd_state_device_status(plan, stream=None):
+    _check(lib().fd_state_device_status(plan.handle, _stream(stream)))
+
+
+def fd_state_plan_timing(plan, kind_mask):
+    _check(lib().fd_state_plan_timing(plan.handle, int(kind_mask)))
+
+
+def fd_state_plan_kernel_times(plan, kind):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().fd_state_plan_kernel_times(plan.handle, int(kind), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def fock_diag_fwd(plan, A, b, c, rho, workspace, saved=None, stream=None):

@@ -63,6 +63,29 @@ def fock_diag_batch(triples, shapes, dtype=torch.complex128, b_mode="auto", devi
     return rho
 
 
+_state_plans = {}
+
+
+def get_state_plan(cutoffs, dtype=torch.complex128, b_mode="auto"):
+    key = (tuple(int(c) for c in cutoffs), dtype, b_mode)
+    p = _state_plans.get(key)
+    if p is None:
+        p = F.StatePlan(cutoffs, dtype, b_mode)
+        _state_plans[key] = p
+    return p
+
+
+def state_vector(A, b, c, cutoffs, dtype=torch.complex128, b_mode="auto", device="cuda"):
+    """psi[n] = <n|psi>, 0 <= n < cutoffs, of the pure state with triple
+    (A: M x M, b: M, c) -- fock_state_fwd."""
+    plan = get_state_plan(cutoffs, dtype, b_mode)
+    A, b, c = _as_inputs(A, b, c, dtype, device)
+    ws = _workspace(plan.workspace(), device)
+    psi = torch.empty(plan.out_shape, dtype=dtype, device=device)
+    F.fock_state_fwd(plan, A, b, c, psi, ws)
+    return psi
+
+
 class FockDiagFunction(torch.autograd.Function):
     """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
     intermediate amplitudes (PyTorch's complex-gradient convention: the

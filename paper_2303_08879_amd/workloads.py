@@ -41,6 +41,8 @@ __all__ = [
     "config4",
     "config5",
     "config5b",
+    "pure_state",
+    "state8",
     "random_cotangent",
 ]
 
@@ -220,6 +222,31 @@ def config5b(seed: int = 55, n: int = 64, c_u: int = 30, c_d: int = 8) -> list:
         circ.params["n_star"] = (1, 1, 1, 1, 1)
         out.append(circ)
     return out
+
+
+def pure_state(seed: int, M: int, cutoffs, r_lo=0.3, r_hi=0.7, alpha_var=0.0) -> Circuit:
+    """A lossless circuit (squeezing r~U(r_lo, r_hi), Haar interferometer,
+    eta = 1, optional displacement) as a *state-vector* triple: the ket block
+    of its density triple, A_psi = A[:M, :M], b_psi = b[:M], and c_psi =
+    sqrt(c) (c of a density matrix is |c_psi|^2; the global phase is free).
+    For a pure state the ket-bra block of A vanishes (Sec. 2.2, rank-one
+    states), which is checked here.  ``detected_mask`` is all modes."""
+    rng = np.random.default_rng(seed)
+    circ = _circuit(rng, M, r_lo, r_hi, lambda g, MM: np.ones(MM), cutoffs, (1 << M) - 1, alpha_var=alpha_var)
+    A, b, c = circ.A, circ.b, circ.c
+    assert np.abs(A[:M, M:]).max() < 1e-10, "lossless circuit did not give a pure state"
+    circ.params["rho_triple"] = (A, b, c)
+    circ.A = np.ascontiguousarray(A[:M, :M])
+    circ.b = np.ascontiguousarray(b[:M])
+    circ.c = complex(np.sqrt(complex(c)))
+    return circ
+
+
+def state8(seed: int = 8, c: int = 8, alpha_var: float = 0.0) -> Circuit:
+    """Pure-state workload: M=8 squeezed modes (r~U(0.3,0.7)) through a Haar
+    interferometer, no loss, b=0 (Gaussian boson sampling input), cutoff 8 in
+    every mode: psi has 8^8 = 16.8M amplitudes."""
+    return pure_state(seed, 8, [c] * 8, alpha_var=alpha_var)
 
 
 def random_cotangent(shape, seed: int) -> np.ndarray:

@@ -146,3 +146,44 @@ def test_exact_reciprocal_coordinate_split():
     for d in range(1, 4097):
         q = ((rem + 0.5) * (1.0 / d)).astype(np.int64)
         assert np.array_equal(q, np.arange(4096) // d), d
+
+
+def test_state_plan_host_checks():
+    L = F.lib()
+    h = ctypes.c_void_p()
+    cut = (ctypes.c_int * 3)(4, 1, 5)
+    assert L.fd_state_plan_create(0, cut, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    assert L.fd_state_plan_create(3, cut, 0, 9, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    assert L.fd_state_plan_create(3, cut, 5, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    bad = (ctypes.c_int * 2)(65, 4)
+    assert L.fd_state_plan_create(2, bad, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    nine = (ctypes.c_int * 9)(*([2] * 9))
+    assert L.fd_state_plan_create(9, nine, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    p = F.StatePlan([4, 1, 5], b_mode="general")
+    assert p.out_shape == (4, 1, 5)
+    # amplitudes in level order (20 x 16 B, 256-aligned) + A and b of the 2 kept modes
+    assert p.workspace() == 512 + 256
+    assert L.fock_state_fwd(None, None, None, None, None, None, 0, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_state_fwd(p.handle, None, 16, 16, 16, 256, 1 << 20, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_state_fwd(p.handle, 16, 16, 16, 16, 256 + 16, 1 << 20, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_state_fwd(p.handle, 16, 16, 16, 16, 256, 512, None) == F.FD_ERR_WORKSPACE
+    assert L.fd_state_plan_destroy(None) == F.FD_OK
+
+
+def test_exact_reciprocal_digit_split_of_cindex():
+    # The permutations between C order and node order split a C-order index
+    # x < 2^31 into digits with trunc((x + 0.5) * (1 / C)), C <= 64, in double
+    # precision (same arithmetic as the device).  Checked against integer
+    # division at every residue near the top of the range, around powers of
+    # two, and on random indices.
+    import numpy as np
+    rng = np.random.default_rng(0)
+    top = (1 << 31) - 1
+    xs = [np.arange(top - 4096, top + 1, dtype=np.int64)]
+    for k in range(1, 31):
+        xs.append(np.arange(max(0, (1 << k) - 130), (1 << k) + 130, dtype=np.int64))
+    xs.append(rng.integers(0, top, size=200000, dtype=np.int64))
+    x = np.concatenate(xs)
+    for C in range(2, 65):
+        q = ((x + 0.5) * (1.0 / C)).astype(np.int64)
+        assert np.array_equal(q, x // C), C

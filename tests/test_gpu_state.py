@@ -1,0 +1,116 @@
+"""GPU parity of the pure-state path (fock_state_fwd, the state vector psi of a
+pure Gaussian state) against the FP64 oracle, through the C ABI.  Bar (c128):
+normwise relative error <= 1e-10 (both sides sum the same Taylor coefficients
+in double precision by the same pivot route); c64: <= 1e-5.  Under b = 0 the
+odd-|n| amplitudes must be exactly zero."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2303_08879_amd import fockdiag as F
+from paper_2303_08879_amd import ops
+from paper_2303_08879_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def rand_state(rng, M, b_zero, scale=0.3):
+    X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    X = scale * (X + X.T)
+    b = np.zeros(M, complex) if b_zero else 0.4 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    return X, b, 0.7 - 0.2j
+
+
+def gpu_psi(A, b, c, cut, dtype=torch.complex128, b_mode="auto"):
+    print(f"[gpu] state cut={cut} dtype={dtype} b_mode={b_mode}", flush=True)
+    psi = ops.state_vector(A, b, c, cut, dtype=dtype, b_mode=b_mode)
+    torch.cuda.synchronize()
+    return psi.cpu().numpy()
+
+
+def odd_mask(shape):
+    return (np.indices(shape).sum(axis=0) % 2) == 1
+
+
+CASES = [([9], False), ([9], True), ([5, 4], False), ([5, 4], True), ([4, 1, 3], False), ([4, 1, 3], True),
+         ([3, 3, 3, 3], True), ([2, 4, 3, 2], False), ([3] * 6, False), ([2] * 8, True), ([3] * 8, False),
+         ([3] * 8, True), ([1, 1], False), ([7, 2, 5], False), ([6, 6, 6], True)]
+
+
+@pytest.mark.parametrize("cut,b_zero", CASES)
+@pytest.mark.parametrize("b_mode", ["auto", "explicit"])
+def test_state_vector_parity(cut, b_zero, b_mode):
+    rng = np.random.default_rng(sum(cut) * 31 + len(cut) + int(b_zero))
+    A, b, c = rand_state(rng, len(cut), b_zero)
+    mode = b_mode if b_mode == "auto" else ("zero" if b_zero else "general")
+    psi = gpu_psi(A, b, c, cut, b_mode=mode)
+    ref = O.state_vector(A, b, c, cut)
+    assert psi.shape == tuple(cut)
+    assert O.rel_err(psi, ref) <= TOL
+    if b_zero:
+        assert np.all(psi[odd_mask(psi.shape)] == 0)
+
+
+def test_state_vector_c64():
+    rng = np.random.default_rng(5)
+    cut = [5, 4, 6]
+    A, b, c = rand_state(rng, 3, False)
+    psi = gpu_psi(A, b, c, cut, dtype=torch.complex64)
+    assert O.rel_err(psi.astype(np.complex128), O.state_vector(A, b, c, cut)) <= 1e-5
+
+
+def test_physical_displaced_state_full():
+    ci = W.pure_state(12, 6, [8] * 6, alpha_var=0.2)
+    psi = gpu_psi(ci.A, ci.b, ci.c, ci.cutoffs)
+    assert O.rel_err(psi, O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs)) <= TOL
+    assert np.sum(np.abs(psi) ** 2) <= 1 + 1e-12
+
+
+def test_state8_full_size_corner():
+    # the measured workload (8 modes, cutoff 8, b = 0): every amplitude with
+    # n_j < 3 depends only on amplitudes inside that corner, so the oracle's
+    # corner box is the reference for psi[:3, ..., :3]
+    ci = W.state8()
+    psi = gpu_psi(ci.A, ci.b, ci.c, ci.cutoffs, b_mode="zero")
+    corner = psi[(slice(0, 3),) * 8]
+    assert O.rel_err(corner, O.state_vector(ci.A, ci.b, ci.c, [3] * 8)) <= TOL
+    assert np.all(psi[odd_mask(psi.shape)] == 0)
+    assert 0.5 < np.sum(np.abs(psi) ** 2) <= 1 + 1e-12
+
+
+def test_workspace_reuse_and_repeated_calls():
+    rng = np.random.default_rng(21)
+    cut = [4, 5, 3]
+    plan = F.StatePlan(cut, torch.complex128, "general")
+    ws = torch.empty(plan.workspace(), dtype=torch.uint8, device="cuda")
+    psi = torch.empty(cut, dtype=torch.complex128, device="cuda")
+    for k in range(3):
+        A, b, c = rand_state(rng, 3, False)
+        At = torch.tensor(A, device="cuda")
+        bt = torch.tensor(b, device="cuda")
+        ct = torch.tensor([c], dtype=torch.complex128, device="cuda")
+        F.fock_state_fwd(plan, At, bt, ct, psi, ws)
+        torch.cuda.synchronize()
+        assert O.rel_err(psi.cpu().numpy(), O.state_vector(A, b, c, cut)) <= TOL, k
+    F.fd_state_device_status(plan)
+
+
+def test_status_reports_nonzero_b_and_nonfinite():
+    cut = [3, 3]
+    A = torch.zeros((2, 2), dtype=torch.complex128, device="cuda")
+    c = torch.ones(1, dtype=torch.complex128, device="cuda")
+    plan = F.StatePlan(cut, torch.complex128, "zero")
+    ws = torch.empty(plan.workspace(), dtype=torch.uint8, device="cuda")
+    psi = torch.empty(cut, dtype=torch.complex128, device="cuda")
+    b = torch.tensor([0.0, 0.5], dtype=torch.complex128, device="cuda")
+    F.fock_state_fwd(plan, A, b, c, psi, ws)
+    with pytest.raises(F.FockDiagError) as e:
+        F.fd_state_device_status(plan)
+    assert e.value.status == F.FD_ERR_INVALID_ARG
+    F.fock_state_fwd(plan, A, torch.zeros(2, dtype=torch.complex128, device="cuda"),
+                     torch.tensor([float("nan")], dtype=torch.complex128, device="cuda"), psi, ws)
+    with pytest.raises(F.FockDiagError) as e:
+        F.fd_state_device_status(plan)
+    assert e.value.status == F.FD_ERR_NONFINITE

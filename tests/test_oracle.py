@@ -277,3 +277,57 @@ def test_vjp_finite_differences():
 def test_rel_err():
     assert O.rel_err([1, 2], [1, 2]) == 0.0
     assert abs(O.rel_err([1, 2.0 + 1e-3], [1, 2]) - 1e-3 / math.sqrt(5)) < 1e-15
+
+
+# ---------------------------------------------------------------- state vectors (pure states)
+def test_state_vector_coherent_closed_form():
+    # A = 0, b = alpha: F(z) = c exp(alpha . z), psi[n] = c prod alpha_j^n_j / sqrt(n_j!)
+    alpha = np.array([0.4 - 0.3j, 0.7j, -0.5])
+    c = math.exp(-0.5 * np.sum(np.abs(alpha) ** 2))
+    psi = O.state_vector(np.zeros((3, 3)), alpha, c, [6, 5, 4])
+    for n in np.ndindex(*psi.shape):
+        ref = c * np.prod([alpha[j] ** n[j] / math.sqrt(math.factorial(n[j])) for j in range(3)])
+        assert abs(psi[n] - ref) < 1e-15, n
+
+
+def test_state_vector_squeezed_closed_form():
+    # one mode, A = [[a]], b = 0: F = c exp(a z^2 / 2), so psi[2k] = c (a/2)^k sqrt((2k)!) / k!, psi[odd] = 0
+    r, phi = 0.8, 0.6
+    a = -np.exp(1j * phi) * math.tanh(r)
+    c = 1 / math.sqrt(math.cosh(r))
+    psi = O.state_vector(np.array([[a]]), np.zeros(1), c, [40])
+    for n in range(40):
+        ref = 0.0 if n % 2 else c * (a / 2) ** (n // 2) * math.sqrt(math.factorial(n)) / math.factorial(n // 2)
+        assert abs(psi[n] - ref) < 1e-14, n
+    assert abs(np.sum(np.abs(psi) ** 2) - 1) < 1e-4   # tail beyond n = 39 is ~tanh(r)^40
+
+
+@pytest.mark.parametrize("bzero", [False, True])
+def test_state_vector_matches_loop_hafnians(bzero):
+    rng = np.random.default_rng(17 + int(bzero))
+    M = 4
+    X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    X = 0.3 * (X + X.T)
+    bb = np.zeros(M, complex) if bzero else 0.5 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    psi = O.state_vector(X, bb, 0.6 + 0.1j, [3, 4, 2, 3])
+    for n in np.ndindex(*psi.shape):
+        ref = O.amplitude_bruteforce(X, bb, 0.6 + 0.1j, n)
+        assert abs(psi[n] - ref) <= 1e-13 * max(1.0, abs(ref)), n
+        if bzero and sum(n) % 2:
+            assert psi[n] == 0
+
+
+def test_pure_state_generator_is_the_ket_block():
+    # the density matrix of the lossless circuit equals psi psi^dag of the
+    # state-vector triple the generator returns
+    ci = W.pure_state(1, 2, [6, 5], alpha_var=0.2)
+    psi = O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs)
+    A, b, c = ci.params["rho_triple"]
+    R = O.full_density_matrix(A, b, c, ci.cutoffs)
+    np.testing.assert_allclose(R, np.einsum("ab,cd->acbd", psi, np.conj(psi)), atol=1e-15)
+
+
+def test_physical_state_vector_is_normalised():
+    ci = W.pure_state(3, 2, [40, 40], r_lo=0.2, r_hi=0.3)
+    psi = O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs)
+    assert abs(np.sum(np.abs(psi) ** 2) - 1) < 1e-9
