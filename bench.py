@@ -171,6 +171,74 @@ def gradient_leg(n=64):
                 output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec)
 
 
+def level_counts(cutoffs):
+    """Points n of the box 0 <= n_j < C_j with |n| = S, for every S."""
+    import numpy as np
+    cnt = np.ones(1, dtype=np.int64)
+    for C in cutoffs:
+        cnt = np.convolve(cnt, np.ones(int(C), dtype=np.int64))
+    return cnt
+
+
+def state_leg(steps=20):
+    """The pure-state workload (8 squeezed modes through a Haar interferometer,
+    no loss, b = 0, cutoff 8: the 8^8 amplitudes of psi), complex128.  Under
+    b = 0 one launch per even level S computes level S from level S - 2 and
+    clears level S - 1; algorithmic bytes of that launch: 16 per amplitude
+    written (levels S and S - 1) plus 16 per amplitude of level S - 2 read
+    once.  The output permutation to C order is timed apart."""
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+    ci = W.state8()
+    dt, dev = torch.complex128, "cuda"
+    plan = F.StatePlan(ci.cutoffs, dt, "zero")
+    A = torch.tensor(ci.A, dtype=dt, device=dev)
+    b = torch.tensor(ci.b, dtype=dt, device=dev)
+    c = torch.tensor([ci.c], dtype=dt, device=dev)
+    ws = torch.empty(plan.workspace(), dtype=torch.uint8, device=dev)
+    psi = torch.empty(plan.out_shape, dtype=dt, device=dev)
+
+    def call():
+        F.fock_state_fwd(plan, A, b, c, psi, ws)
+
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    F.fd_state_plan_timing(plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_OUT_PERM))
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    nl, ms_l = F.fd_state_plan_kernel_times(plan, F.FD_K_FWD_LEVEL)
+    _, ms_p = F.fd_state_plan_kernel_times(plan, F.FD_K_OUT_PERM)
+    F.fd_state_plan_timing(plan, 0)
+    F.fd_state_device_status(plan)
+    N = level_counts(ci.cutoffs)
+    smax = len(N) - 1
+    alg = sum(16 * (N[S] + N[S - 1] + N[S - 2]) for S in range(2, smax + 1, 2))
+    if smax % 2:
+        alg += 16 * N[smax]   # the last odd level, cleared alone
+    launches = nl // steps
+    amps = int(N.sum())
+    gbs = alg * steps / (ms_l * 1e-3) / 1e9
+    return dict(workload="state8: pure state, M=8 squeezed modes r~U(0.3,0.7), Haar interferometer, no loss, b=0, "
+                         "cutoff 8 (8^8 amplitudes of psi), complex128",
+                amplitudes=amps, calls=steps, ms_per_call=1e3 * sec / steps,
+                value=amps * steps / sec, unit="state-vector amplitudes/s",
+                level_ms_per_call=ms_l / steps, out_perm_ms_per_call=ms_p / steps,
+                roofline={"bound": "hbm", "kernel": "k_state_level (even levels)", "achieved": round(gbs, 2),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+                          "launches": launches, "avg_launch_us": round(1e3 * ms_l / nl, 3),
+                          "algorithmic_bytes_per_launch": int(alg // max(launches, 1)),
+                          "traffic": measured_traffic("k_state_level")},
+                norm2=float((psi.abs() ** 2).sum()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +248,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-corner", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
+    ap.add_argument("--no-state", action="store_true", help="skip the pure-state (state vector) leg")
     ap.add_argument("--gradient-leg", action="store_true",
                     help="also time the 64-circuit gradient workload (forward + VJP per circuit)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -312,6 +381,8 @@ def main():
     }
     if not args.no_batched:
         line["batched"] = batched_leg()
+    if not args.no_state:
+        line["state_vector"] = state_leg()
     if args.gradient_leg:
         line["gradient_batch"] = gradient_leg()
     if not args.no_cpu_baseline:
