@@ -255,6 +255,42 @@ const char* fd_last_error(void);
  * FD_ERR_HIP if a batched sweep gave up waiting at a step barrier. */
 fd_status fd_device_status(fd_plan p, hipStream_t stream);
 
+/* ---- Total photon cutoff and probability-sum stopping -----------------
+ * fd_plan_create_total -- a plan with every mode detected whose lattice is
+ * cut by the total photon number: the points n with n_j < C_j and |n| <=
+ * total_cutoff (the level sets of Algorithm 1 become simplices; Sec. 3.1:
+ * the sweep stops at level total_cutoff).  fock_diag_fwd / detection_probs
+ * on such a plan return p(n) in level order: level S = 0, 1, ... at
+ * fd_plan_level_offsets[S], inside a level the points in lexicographic order
+ * with the first mode slowest; FD_Q_OUT_ELEMS entries.  Per-mode cutoffs
+ * still apply (pass total_cutoff + 1 for none).  Limits as fd_plan_create
+ * except that the box product may exceed 2^31 (the points below the cutoff
+ * may not).  fock_diag_vjp and the batched calls return FD_ERR_UNSUPPORTED
+ * for these plans. */
+fd_status fd_plan_create_total(int M, const int* cutoffs, int total_cutoff, fd_dtype dt, uint32_t flags,
+                               fd_plan* out);
+
+/* Host copy of the level offsets of a plan with every mode detected: offsets
+ * has FD_Q_LEVELS + 1 entries (n must be at least that); level S holds the
+ * points offsets[S] .. offsets[S+1]-1 of the level-ordered output of a
+ * total-cutoff plan (and of the internal node order of any all-detected
+ * plan). */
+fd_status fd_plan_level_offsets(fd_plan p, int64_t* offsets, int n);
+
+/* detection_probs_until -- detection_probs with probability-sum stopping
+ * (the cumulative probability of the computed levels measures how much of
+ * the state lies below the cutoff): levels are swept in blocks of 4; after
+ * each block the masses sum_{|n| = S} p(n) are read back (this call
+ * synchronises `stream` once per block) and the sweep ends at the first
+ * level S* with sum_{S <= S*} mass(S) >= 1 - eps.  probs holds p(n) for
+ * |n| <= S* and zero above; *levels_done = S* + 1 (FD_Q_LEVELS if the sum
+ * stays below 1 - eps), *mass = the sum over the returned levels (host
+ * pointers).  eps in [0, 1); plan with every mode detected and at least one
+ * cutoff >= 2; workspace as for fock_diag_fwd without saved. */
+fd_status detection_probs_until(fd_plan p, const void* A, const void* b, const void* c, void* probs, double eps,
+                                int* levels_done, double* mass, void* workspace, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* ---- Pure states: the state vector ------------------------------------
  * The Fock amplitudes psi[n] = <n|psi>, 0 <= n_j < C_j, of a pure Gaussian
  * state given by its Bargmann triple (A: M x M complex symmetric, b: M, c):

@@ -56,6 +56,9 @@ __all__ = [
     "fock_diag",
     "fock_diag_pattern",
     "detection_probs",
+    "level_points",
+    "probs_total",
+    "stop_level",
     "loop_hafnian",
     "amplitude_bruteforce",
     "adjoint_closed_form",
@@ -212,6 +215,56 @@ def fock_diag_pattern(A, b, c, cutoffs, detected_mask: int, pattern):
     out = fock_diag(A, b, c, cut, detected_mask)
     idx = (Ellipsis,) + tuple(int(n) for n in pattern)
     return out[idx]
+
+
+def level_points(cutoffs, total):
+    """The lattice points n (0 <= n_j < C_j) with |n| <= total, level by
+    level (S = |n| = 0, 1, ...), each level in lexicographic order with the
+    first mode slowest; returns (points, level offsets)."""
+    cut = [int(C) for C in cutoffs]
+    smax = min(int(total), sum(C - 1 for C in cut))
+
+    def compositions(S, d):
+        if d == len(cut) - 1:
+            if S < cut[d]:
+                yield (S,)
+            return
+        for v in range(min(cut[d] - 1, S) + 1):
+            for rest in compositions(S - v, d + 1):
+                yield (v,) + rest
+
+    pts, offs = [], [0]
+    for S in range(smax + 1):
+        pts.extend(compositions(S, 0))
+        offs.append(len(pts))
+    return pts, offs
+
+
+def probs_total(A, b, c, cutoffs, total):
+    """p(n) for 0 <= n_j < C_j with a total photon cutoff |n| <= total
+    (Sec. 3.1 with the sweep ending at level total), in the order of
+    ``level_points``.  No entry depends on the cutoffs (each level only reads
+    lower ones): read off the box with per-mode cutoffs min(C_j, total + 1)
+    when that is small, else pattern by pattern (Tier B)."""
+    mask = (1 << len(cutoffs)) - 1
+    pts, offs = level_points(cutoffs, total)
+    dims = [min(int(C), int(total) + 1) for C in cutoffs]
+    if math.prod(d * d for d in dims) <= 4_000_000:   # the whole box is cheap: read it off
+        box = detection_probs(A, b, c, dims)
+        return np.array([box[n] for n in pts], dtype=np.complex128), offs
+    vals = [complex(fock_diag_pattern(A, b, c, cutoffs, mask, n)) for n in pts]
+    return np.array(vals, dtype=np.complex128), offs
+
+
+def stop_level(level_mass, eps):
+    """Probability-sum stopping: the first level S* with sum_{S <= S*} mass(S)
+    >= 1 - eps (None if the sum stays below)."""
+    acc = 0.0
+    for S, m in enumerate(level_mass):
+        acc += float(np.real(m))
+        if acc >= 1.0 - eps:
+            return S
+    return None
 
 
 # --------------------------------------------------------------------------

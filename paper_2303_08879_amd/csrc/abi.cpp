@@ -164,6 +164,7 @@ fd_status fd_plan_destroy(fd_plan p) {
     (void)hipFree(P.d_elist);
     (void)hipFree(P.d_woff);
     (void)hipFree(P.d_node);
+    (void)hipFree(P.d_mass);
     (void)hipSetDevice(cur);
   }
   drop_graphs(P);
@@ -250,6 +251,62 @@ fd_status fock_diag_fwd(fd_plan p, const void* A, const void* b, const void* c, 
   return ok();
 }
 
+fd_status fd_plan_create_total(int M, const int* cutoffs, int total_cutoff, fd_dtype dt, uint32_t flags,
+                               fd_plan* out) {
+  if (!out) return fail(FD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (total_cutoff < 0) return fail(FD_ERR_INVALID_ARG, "total_cutoff must be >= 0");
+  fd_plan p = new (std::nothrow) fd_plan_s;
+  if (!p) return fail(FD_ERR_OOM, "host allocation failed");
+  std::string err;
+  const uint32_t all = M >= 32 ? 0xffffffffu : ((1u << M) - 1u);
+  fd_status s = fd::build_plan(M, cutoffs, all, dt, flags, &p->P, &err, total_cutoff);
+  if (s != FD_OK) {
+    delete p;
+    return fail(s, err);
+  }
+  *out = p;
+  return ok();
+}
+
+fd_status fd_plan_level_offsets(fd_plan p, int64_t* offsets, int n) {
+  if (!p || !offsets) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  const fd::Plan& P = p->P;
+  if (P.mask != (P.M >= 32 ? 0xffffffffu : ((1u << P.M) - 1u)))
+    return fail(FD_ERR_INVALID_ARG, "level offsets are defined for plans with every mode detected");
+  if (n < P.smax + 2) return fail(FD_ERR_INVALID_ARG, "offsets needs FD_Q_LEVELS + 1 entries");
+  for (int S = 0; S <= P.smax + 1; ++S) offsets[S] = P.MD > 0 ? P.lvl[S] : (S == 0 ? 0 : 1);
+  return ok();
+}
+
+fd_status detection_probs_until(fd_plan p, const void* A, const void* b, const void* c, void* probs, double eps,
+                                int* levels_done, double* mass, void* workspace, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  if (P.mask != (P.M >= 32 ? 0xffffffffu : ((1u << P.M) - 1u)))
+    return fail(FD_ERR_INVALID_ARG, "detection_probs_until needs a plan with every mode detected");
+  if (P.MD == 0) return fail(FD_ERR_INVALID_ARG, "no mode with cutoff >= 2");
+  if (!levels_done || !mass) return fail(FD_ERR_INVALID_ARG, "levels_done and mass must be host pointers");
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(FD_ERR_INVALID_ARG, "eps must be in [0, 1)");
+  fd_status s = check_ptrs(P, {A, b, c, probs, workspace});
+  if (s != FD_OK) return s;
+  if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  bool b_zero = false;
+  if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;
+  const bool odd = P.odd_for(b_zero);
+  if (ws_bytes < fd::fwd_layout(P, odd, false, 0).total) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  fd::StopRule rule;
+  rule.eps = eps;
+  hipError_t e = fd::run_forward(P, odd, A, b, c, probs, workspace, nullptr, stream, &rule);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  *levels_done = rule.levels_done;
+  *mass = rule.mass;
+  return ok();
+}
+
 fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c, void* probs, void* workspace,
                           size_t ws_bytes, hipStream_t stream) {
   if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
@@ -264,6 +321,7 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
                         size_t ws_bytes, hipStream_t stream) {
   if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
   fd::Plan& P = p->P;
+  if (P.level_cap >= 0) return fail(FD_ERR_UNSUPPORTED, "no reverse sweep for plans with a total photon cutoff");
   fd_status s = check_ptrs(P, {A, b, c, drho, dA, db, dc, workspace});
   if (s != FD_OK) return s;
   if (!aligned(workspace, 256) || (saved && !aligned(saved, 256)))
@@ -316,6 +374,8 @@ fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
     if (!plans[i]) return fail(FD_ERR_INVALID_ARG, "a plan of the batch is NULL");
     P[i] = &plans[i]->P;
     if (P[i]->dt != P[0]->dt) return fail(FD_ERR_INVALID_ARG, "every plan of a batch must have the same dtype");
+    if (P[i]->level_cap >= 0)
+      return fail(FD_ERR_UNSUPPORTED, "plans with a total photon cutoff are not batched; use fock_diag_fwd");
     fd_status s = check_ptrs(*P[i], {A[i], b[i], c[i], rho[i], workspace[i]});
     if (s != FD_OK) return s;
     if (!aligned(workspace[i], 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");

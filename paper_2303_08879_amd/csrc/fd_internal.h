@@ -132,7 +132,8 @@ struct Plan {
   std::vector<int64_t> group_nodes;  // per group: prod_{i>=g} CD_i
   std::vector<int64_t> maxN;         // per group: max level size
   std::vector<int> fam_group;        // per family
-  int64_t nodes_total = 1;           // prod CD
+  int64_t nodes_total = 1;           // prod CD (capped plans: lattice points with |n| <= smax)
+  int level_cap = -1;                // total photon cutoff of the detected lattice (-1: the box)
   int64_t out_elems = 1;
   // structure counts (App. B)
   int64_t pivots = 0, stored[6] = {0, 0, 0, 0, 0, 0}, targets = 0, terms = 0;
@@ -141,6 +142,7 @@ struct Plan {
   int* d_pn = nullptr;
   int64_t* d_lvl = nullptr;
   int* d_node = nullptr;             // node records (Algorithm 2 plans)
+  double* d_mass = nullptr;          // per-level probability masses (stopping rule)
   int* d_status = nullptr;
   // undetected-block fill order (step 1 of Algorithm 2): entries sorted by weight
   std::vector<int> elist, woff;
@@ -167,8 +169,11 @@ inline size_t ufill_lds_bytes(const Plan& P, bool vjp) {
          (size_t)(P.B + P.wmax + 2) * sizeof(int);
 }
 
+// level_cap >= 0: every mode with cutoff >= 2 detected, only lattice points
+// with |n| <= level_cap (the levels of a total photon cutoff), F0 returned in
+// level order.
 fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
-                     std::string* err);
+                     std::string* err, int level_cap = -1);
 fd_status ensure_device(Plan* P, std::string* err);
 DevPlan make_devplan(const Plan& P, bool odd);
 
@@ -237,8 +242,18 @@ struct KTimer {
 };
 
 // kernels (kernels_fwd.hip / kernels_vjp.hip)
+// Probability-sum stopping of a sweep over an all-detected plan: after every
+// kStopBlock levels the masses sum_{|n| = S} p(n) of the new levels are read
+// back (the stream is synchronised) and the sweep ends at the first level S*
+// with sum_{S <= S*} mass >= 1 - eps; F0 above S* is cleared.
+constexpr int kStopBlock = 4;
+struct StopRule {
+  double eps = 0.0;
+  int levels_done = 0;   // out: S* + 1 (smax + 1 if the sum never reaches 1 - eps)
+  double mass = 0.0;     // out: sum of the returned levels' masses
+};
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
-                       void* saved, hipStream_t st);
+                       void* saved, hipStream_t st, StopRule* stop = nullptr);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
 constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
 // LDS tile of the permutations between rho's C order and node order:

@@ -230,7 +230,7 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
       R scale;
       cx<R>* dst;
       if (i == 2 * K + 1) {                 // d(m + 1_K): output amplitude
-        ok = true;
+        ok = L.f0nxt != nullptr;            // none above the last level (a total photon cutoff)
         scale = isq[m[K] + 1];
         dst = at32(L.f0nxt, (uint32_t)rup[K]);
       } else if (i == 2 * K) {              // F2(K)(m)

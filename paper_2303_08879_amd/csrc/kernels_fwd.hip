@@ -218,9 +218,54 @@ hipError_t launch_prep(const Plan& Pl, const void* A, const void* b, const void*
   return hipGetLastError();
 }
 
+// Plans with a total photon cutoff return F0 in level order: a copy with the
+// non-finite check.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_copy_levels(const cx<R>* __restrict__ f0, cx<R>* __restrict__ rho,
+                                                          int64_t n, int* status) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const cx<R> v = ld(f0 + i);
+    if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+    st(rho + i, v);
+  }
+  if (bad) atomicOr(status, 1);
+}
+
+// mass[S] = sum of Re F0 over level S (the detection probabilities of level
+// S), S = S0 + blockIdx.x; strided per-thread sums, then a fixed-order tree.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_level_mass(const cx<R>* __restrict__ f0, const int64_t* __restrict__ lvl,
+                                                         int S0, double* mass) {
+  __shared__ double red[kThreads];
+  const int S = S0 + blockIdx.x;
+  double acc = 0.0;
+  for (int64_t i = lvl[S] + threadIdx.x; i < lvl[S + 1]; i += blockDim.x) acc += (double)ld(f0 + i).x;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mass[S] = red[0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_clear(cx<R>* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    st(p + i, czero<R>());
+}
+
 // F0 in node order -> rho (C order), with the non-finite check.
 template <typename R>
 static hipError_t launch_out_perm_t(const Plan& Pl, const DevPlan& P, const cx<R>* f0, void* rho, hipStream_t st) {
+  if (Pl.level_cap >= 0) {
+    const int64_t n = Pl.nodes_total;
+    KTimer kt(Pl, KK_OUT_PERM, st);
+    hipLaunchKernelGGL((k_copy_levels<R>), dim3((unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 65536)),
+                       dim3(kThreads), 0, st, f0, reinterpret_cast<cx<R>*>(rho), n, Pl.d_status);
+    return hipGetLastError();
+  }
   const int64_t total = Pl.out_elems;
   const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
   const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
@@ -234,7 +279,7 @@ static hipError_t launch_out_perm_t(const Plan& Pl, const DevPlan& P, const cx<R
 
 template <typename R>
 static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho,
-                                char* ws, char* saved, hipStream_t st) {
+                                char* ws, char* saved, hipStream_t st, StopRule* stop) {
   const bool store_all = saved != nullptr;
   // prep lives in the workspace; intermediates in `saved` (store-all) or the workspace (ring)
   FwdLayout Lw = fwd_layout(Pl, odd, false, 0);
@@ -248,6 +293,10 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   DevPlan P = make_devplan(Pl, odd);
   (void)ci;
   hipError_t e;
+  if (stop) {
+    stop->levels_done = Pl.smax + 1;
+    stop->mass = 0.0;
+  }
   {
     KTimer kt(Pl, KK_PREP, st);
     e = launch_prep(Pl, A, b, c, Ai, f0, st);
@@ -280,6 +329,32 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
       e = launch_fwd_level_t<R>(Pl, P, odd, S, L, Ai, bi, st);
     }
     if (e != hipSuccess) return e;
+    if (stop && ((S + 1) % kStopBlock == 0 || S == Pl.smax)) {
+      // levels S0..S are final (F0 of a level is written by the launch below it)
+      const int S0 = S - S % kStopBlock;
+      hipLaunchKernelGGL((k_level_mass<R>), dim3(S - S0 + 1), dim3(kThreads), 0, st, f0, Pl.d_lvl, S0, Pl.d_mass);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      double hm[kStopBlock];
+      if ((e = hipMemcpyAsync(hm, Pl.d_mass + S0, (size_t)(S - S0 + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                              st)) != hipSuccess ||
+          (e = hipStreamSynchronize(st)) != hipSuccess)
+        return e;
+      int hit = -1;
+      for (int k = 0; k <= S - S0 && hit < 0; ++k) {
+        stop->mass += hm[k];
+        if (stop->mass >= 1.0 - stop->eps) hit = S0 + k;
+      }
+      if (hit >= 0) {
+        stop->levels_done = hit + 1;
+        const int64_t from = Pl.lvl[hit + 1], to = Pl.lvl[Pl.smax + 1];   // F0 above level hit
+        if (to > from) {
+          hipLaunchKernelGGL((k_clear<R>), dim3((unsigned)std::min<int64_t>((to - from + kThreads - 1) / kThreads, 65536)),
+                             dim3(kThreads), 0, st, f0 + from, to - from);
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        break;
+      }
+    }
   }
   if (!rho) return hipSuccess;   // recompute for the reverse sweep: no output needed
   return launch_out_perm_t<R>(Pl, P, f0, rho, st);
@@ -292,10 +367,10 @@ hipError_t launch_out_perm(const Plan& Pl, const void* f0, void* rho, hipStream_
 }
 
 hipError_t run_forward(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
-                       void* saved, hipStream_t st) {
+                       void* saved, hipStream_t st, StopRule* stop) {
   if (Pl.dt == FD_C64)
-    return run_forward_t<float>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st);
-  return run_forward_t<double>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st);
+    return run_forward_t<float>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st, stop);
+  return run_forward_t<double>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st, stop);
 }
 
 }  // namespace fd

@@ -14,8 +14,26 @@ size_t elem_bytes(fd_dtype dt) { return dt == FD_C64 ? 8 : 16; }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Lattice points n with 0 <= n_d <= ub[d] (no point if some ub[d] < 0) and
+// |n| <= smax: a convolution over the modes.
+static int64_t count_box_levels(const std::vector<int>& ub, int smax) {
+  for (int u : ub)
+    if (u < 0) return 0;
+  std::vector<int64_t> cnt(smax + 1, 0), nxt(smax + 1, 0);
+  cnt[0] = 1;
+  for (int u : ub) {
+    std::fill(nxt.begin(), nxt.end(), 0);
+    for (int s = 0; s <= smax; ++s)
+      for (int v = 0; v <= u && v <= s; ++v) nxt[s] += cnt[s - v];
+    cnt.swap(nxt);
+  }
+  int64_t t = 0;
+  for (int64_t x : cnt) t += x;
+  return t;
+}
+
 fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
-                     std::string* err) {
+                     std::string* err, int level_cap) {
   static std::atomic<uint64_t> next_uid{1};
   P->uid = next_uid.fetch_add(1);
   if (M < 1 || M > kMaxModes) {
@@ -98,15 +116,22 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
   }
   // output size
   int64_t out = 1;
-  for (int j = 0; j < M; ++j) out *= ((mask >> j) & 1u) ? cutoffs[j] : (int64_t)cutoffs[j] * cutoffs[j];
-  P->out_elems = out;
+  if (level_cap < 0)
+    for (int j = 0; j < M; ++j) out *= ((mask >> j) & 1u) ? cutoffs[j] : (int64_t)cutoffs[j] * cutoffs[j];
+  P->out_elems = out;   // capped plans: set once the levels are counted
+  if (level_cap >= 0 && P->MU > 0) {
+    *err = "a total photon cutoff needs every mode with cutoff >= 2 detected";
+    return FD_ERR_INVALID_ARG;
+  }
+  P->level_cap = level_cap;
   int64_t nt = 1;
   for (int c : P->CD) {
     nt *= c;
-    if (nt >= (int64_t(1) << 31)) {
+    if (level_cap < 0 && nt >= (int64_t(1) << 31)) {
       *err = "product of detected cutoffs must be < 2^31";
       return FD_ERR_UNSUPPORTED;
     }
+    nt = std::min<int64_t>(nt, int64_t(1) << 40);
   }
   P->nodes_total = nt;
   if (P->B > 1 && nt > (int64_t(1) << 22)) {
@@ -116,6 +141,7 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
   const int MD = P->MD;
   int smax = 0;
   for (int c : P->CD) smax += c - 1;
+  if (level_cap >= 0) smax = std::min(smax, level_cap);
   P->smax = smax;
   const int pnw = smax + 3;
   // ncnt[d][s] = #(n_d..n_{MD-1}) in the box with sum s
@@ -153,6 +179,16 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     }
     P->group_nodes[g] = acc;
     P->maxN[g] = std::max<int64_t>(mx, 1);
+  }
+  if (level_cap >= 0) {
+    // the lattice points of levels 0..smax, returned in level order
+    nt = MD > 0 ? P->lvl[smax + 1] : 1;
+    if (nt >= (int64_t(1) << 31)) {
+      *err = "at most 2^31 - 1 lattice points below the total photon cutoff";
+      return FD_ERR_UNSUPPORTED;
+    }
+    P->nodes_total = nt;
+    P->out_elems = nt;
   }
   // the level kernels address a level's entries with 32-bit byte offsets
   if (MD > 0 && P->maxN[0] * P->B > (int64_t(1) << 28)) {
@@ -197,6 +233,41 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     }
     P->pivots = (C[0] - 1) * prod_except(0, -1, 0);
     for (int K = 0; K < MD; ++K) P->pivots += (C[K] - 1) * prod_except(K, -1, K);
+    if (level_cap >= 0) {
+      // the same families and pivots, counted on the levels 0..smax
+      auto ubox = [&]() { std::vector<int> u(MD); for (int d = 0; d < MD; ++d) u[d] = C[d] - 1; return u; };
+      for (int i = 0; i < 6; ++i) P->stored[i] = 0;
+      P->stored[F_F0] = nt;
+      std::vector<int> u = ubox();
+      u[0] = C[0] - 2;
+      P->stored[F_F1K] += count_box_levels(u, smax);
+      P->pivots = count_box_levels(u, smax);
+      u[0] = C[0] - 3;
+      P->stored[F_F1B] += count_box_levels(u, smax);
+      for (int j = 1; j < MD; ++j) {
+        u = ubox();
+        u[0] = C[0] - 2;
+        u[j] = C[j] - 2;
+        P->stored[F_F1K] += count_box_levels(u, smax);
+        P->stored[F_F1B] += count_box_levels(u, smax);
+      }
+      for (int K = 0; K < MD; ++K) {
+        u = ubox();
+        for (int d = 0; d < K; ++d) u[d] = 0;
+        u[K] = C[K] - 2;
+        P->pivots += count_box_levels(u, smax);
+        u[K] = C[K] - 3;
+        P->stored[F_F2] += count_box_levels(u, smax);
+        for (int j = K + 1; j < MD; ++j) {
+          u[K] = C[K] - 2;
+          std::vector<int> w = u;
+          w[j] = C[j] - 2;
+          const int64_t v = count_box_levels(w, smax);
+          P->stored[F_1010] += v;
+          P->stored[F_1001] += v;
+        }
+      }
+    }
   } else {
     P->stored[F_F0] = 1;
   }
@@ -388,6 +459,11 @@ fd_status ensure_device(Plan* P, std::string* err) {
     *err = "upload of plan tables failed";
     return FD_ERR_HIP;
   }
+  if (P->MD > 0 && P->B == 1 &&
+      hipMalloc((void**)&P->d_mass, (size_t)(P->smax + 1) * sizeof(double)) != hipSuccess) {
+    *err = "hipMalloc of the level masses failed";
+    return FD_ERR_OOM;
+  }
   if (P->B > 1 && P->MD > 0) {
     std::vector<int> nt;
     if (!build_node_table(*P, &nt, err)) return FD_ERR_HIP;
@@ -428,6 +504,7 @@ void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms) {
   }
   const std::vector<int>& C = P.CD;
   std::vector<int> m(MD, 0);
+  int msum = 0;   // |m|: the walk skips points above level smax (capped plans)
   for (int64_t it = 0; it < P.nodes_total; ++it) {
     int nz = 0;
     for (int j = 0; j < MD; ++j) nz += m[j] > 0;
@@ -453,7 +530,10 @@ void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms) {
       W += (double)t * ((double)reads * P.B + (odd ? unb + bterm : 0.0));
     }
     for (int j = MD - 1; j >= 0; --j) {
-      if (++m[j] < C[j]) break;
+      ++m[j];
+      ++msum;
+      if (m[j] < C[j] && msum <= P.smax) break;
+      msum -= m[j];
       m[j] = 0;
     }
   }

@@ -27,6 +27,7 @@ EXPORTS = [
     "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs", "fd_batch_set_tuning", "fd_batch_get_tuning",
     "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
+    "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -78,6 +79,10 @@ def lib():
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     L.fd_batch_set_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.fd_batch_get_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+    L.fd_plan_create_total.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, i32, u32, ctypes.POINTER(vp)]
+    L.fd_plan_level_offsets.argtypes = [vp, i64p, i32]
+    L.detection_probs_until.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.fd_state_plan_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, u32, ctypes.POINTER(vp)]
     L.fd_state_plan_destroy.argtypes = [vp]
     L.fd_state_plan_workspace.argtypes = [vp, ctypes.POINTER(sz)]
@@ -115,16 +120,23 @@ class Plan:
     """fd_plan_create / fd_plan_destroy.  ``dtype`` is torch.complex128 or
     torch.complex64; ``b_mode`` one of 'auto', 'zero', 'general'."""
 
-    def __init__(self, cutoffs, detected_mask, dtype=torch.complex128, b_mode="auto"):
+    def __init__(self, cutoffs, detected_mask, dtype=torch.complex128, b_mode="auto", total_cutoff=None):
+        """total_cutoff: a total photon cutoff (fd_plan_create_total; every mode
+        detected, output p(n) in level order)."""
         self.cutoffs = [int(c) for c in cutoffs]
         self.M = len(self.cutoffs)
         self.detected_mask = int(detected_mask)
         self.dtype = dtype
+        self.total_cutoff = total_cutoff
         dt = FD_C128 if dtype == torch.complex128 else FD_C64
         flags = {"auto": FD_B_AUTO, "zero": FD_B_ZERO, "general": FD_B_GENERAL}[b_mode]
         arr = (ctypes.c_int * self.M)(*self.cutoffs)
         h = ctypes.c_void_p()
-        _check(lib().fd_plan_create(self.M, arr, self.detected_mask, dt, flags, ctypes.byref(h)))
+        if total_cutoff is None:
+            _check(lib().fd_plan_create(self.M, arr, self.detected_mask, dt, flags, ctypes.byref(h)))
+        else:
+            _check(lib().fd_plan_create_total(self.M, arr, int(total_cutoff), dt, flags, ctypes.byref(h)))
+            self.detected_mask = (1 << self.M) - 1
         self.handle = h
 
     def __del__(self):
@@ -133,8 +145,17 @@ class Plan:
             _lib.fd_plan_destroy(h)
             self.handle = None
 
+    def level_offsets(self):
+        """fd_plan_level_offsets (plans with every mode detected)."""
+        n = self.query(FD_Q_LEVELS) + 1
+        arr = (ctypes.c_int64 * n)()
+        _check(lib().fd_plan_level_offsets(self.handle, arr, n))
+        return list(arr)
+
     @property
     def out_shape(self):
+        if self.total_cutoff is not None:
+            return (self.query(FD_Q_OUT_ELEMS),)
         U = [j for j in range(self.M) if not (self.detected_mask >> j) & 1]
         D = [j for j in range(self.M) if (self.detected_mask >> j) & 1]
         return tuple([self.cutoffs[j] for j in U] * 2 + [self.cutoffs[j] for j in D])
@@ -209,6 +230,15 @@ def fock_diag_fwd(plan, A, b, c, rho, workspace, saved=None, stream=None):
 def detection_probs(plan, A, b, c, probs, workspace, stream=None):
     _check(lib().detection_probs(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(probs), _ptr(workspace),
                                  _nbytes(workspace), _stream(stream)))
+
+
+def detection_probs_until(plan, A, b, c, probs, eps, workspace, stream=None):
+    """Returns (levels_done, mass)."""
+    n, m = ctypes.c_int(), ctypes.c_double()
+    _check(lib().detection_probs_until(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(probs), float(eps),
+                                       ctypes.byref(n), ctypes.byref(m), _ptr(workspace), _nbytes(workspace),
+                                       _stream(stream)))
+    return n.value, m.value
 
 
 def fock_diag_vjp(plan, A, b, c, saved, drho, dA, db, dc, workspace, stream=None):

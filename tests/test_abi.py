@@ -2,6 +2,7 @@
 symbol the header declares, validates arguments, and its planner reproduces
 the structure counts of App. B."""
 import ctypes
+import math
 import os
 import re
 
@@ -187,3 +188,41 @@ def test_exact_reciprocal_digit_split_of_cindex():
     for C in range(2, 65):
         q = ((x + 0.5) * (1.0 / C)).astype(np.int64)
         assert np.array_equal(q, x // C), C
+
+
+def test_total_cutoff_plan_counts_and_offsets():
+    import itertools
+    L = F.lib()
+    h = ctypes.c_void_p()
+    cut = (ctypes.c_int * 2)(4, 4)
+    assert L.fd_plan_create_total(2, cut, -1, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
+    # a cap at or above the box's top level changes nothing: the counts are App. B's
+    for C in ([4, 3, 5], [6, 6], [3, 3, 3, 3]):
+        box = F.Plan(C, (1 << len(C)) - 1)
+        cap = F.Plan(C, 0, total_cutoff=sum(c - 1 for c in C) + 2)
+        for q in (F.FD_Q_OUT_ELEMS, F.FD_Q_LEVELS, F.FD_Q_PIVOTS, F.FD_Q_NODES_F0, F.FD_Q_NODES_F1,
+                  F.FD_Q_NODES_F2, F.FD_Q_NODES_F1010, F.FD_Q_NODES_F1001):
+            assert cap.query(q) == box.query(q), (C, q)
+    # below it: the points with |n| <= N, level offsets as counted by brute force
+    C, N = [5, 1, 4, 6], 6
+    p = F.Plan(C, 0, total_cutoff=N)
+    pts = [n for n in itertools.product(*[range(c) for c in C]) if sum(n) <= N]
+    assert p.query(F.FD_Q_OUT_ELEMS) == len(pts) and p.out_shape == (len(pts),)
+    assert p.query(F.FD_Q_LEVELS) == N + 1
+    offs = p.level_offsets()
+    assert offs == [sum(1 for n in pts if sum(n) < S) for S in range(N + 2)]
+    # F2(K) nodes: n_<K = 0, n_K <= C_K - 3, |n| <= N (kept modes 5, 4, 6)
+    K = [5, 4, 6]
+    f2 = sum(1 for K0 in range(3) for n in itertools.product(*[range(c) for c in K])
+             if sum(n) <= N and all(n[d] == 0 for d in range(K0)) and n[K0] <= K[K0] - 3)
+    assert p.query(F.FD_Q_NODES_F2) == f2
+    # a box product beyond 2^31 is fine below a total cutoff
+    big = F.Plan([64] * 8, 0, total_cutoff=10)
+    assert big.query(F.FD_Q_OUT_ELEMS) == math.comb(18, 8)
+    # no reverse sweep, no batches for these plans (host-side refusals)
+    assert L.fock_diag_vjp(p.handle, 16, 16, 16, None, 0, 16, 16, 16, 16, 256, 1 << 20, None) == \
+        F.FD_ERR_UNSUPPORTED
+    assert L.detection_probs_until(p.handle, 16, 16, 16, 16, 1.5, ctypes.byref(ctypes.c_int()),
+                                   ctypes.byref(ctypes.c_double()), 256, 1 << 20, None) == F.FD_ERR_INVALID_ARG
+    assert L.detection_probs_until(p.handle, 16, 16, 16, 16, 1e-3, None, None, 256, 1 << 20, None) == \
+        F.FD_ERR_INVALID_ARG

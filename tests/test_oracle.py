@@ -331,3 +331,44 @@ def test_physical_state_vector_is_normalised():
     ci = W.pure_state(3, 2, [40, 40], r_lo=0.2, r_hi=0.3)
     psi = O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs)
     assert abs(np.sum(np.abs(psi) ** 2) - 1) < 1e-9
+
+
+# ---------------------------------------------------------------- total photon cutoff and stopping
+def test_probs_total_poisson_product_and_order():
+    # a product of coherent states: p(n) = prod_j exp(-|a_j|^2) |a_j|^(2 n_j) / n_j!
+    alpha = np.array([0.5, 0.3 + 0.4j, 0.7j])
+    A, b, c = triple([0.0, 0.0, 0.0], np.eye(3), 1.0, alpha)
+    p, offs = O.probs_total(A, b, c, [5, 4, 6], 6)
+    pts, offs2 = O.level_points([5, 4, 6], 6)
+    assert offs == offs2 and offs[-1] == len(pts) == len(p)
+    for S in range(len(offs) - 1):
+        lvl = pts[offs[S]:offs[S + 1]]
+        assert all(sum(n) == S for n in lvl) and lvl == sorted(lvl)
+    for n, v in zip(pts, p):
+        ref = np.prod([math.exp(-abs(a) ** 2) * abs(a) ** (2 * k) / math.factorial(k) for a, k in zip(alpha, n)])
+        assert abs(v - ref) < 1e-15, n
+
+
+def test_stop_level_thermal_closed_form():
+    # one thermal mode, mean photon number nbar: p(n) = (1 - q) q^n, q = nbar / (1 + nbar);
+    # the mass of levels 0..S is 1 - q^(S+1), so S* = ceil(log(eps) / log(q)) - 1
+    nbar = 1.7
+    q = nbar / (1 + nbar)
+    sig = np.diag([nbar + 0.5, nbar + 0.5])   # thermal covariance, vacuum = 1/2
+    A, b, c = W.bargmann_triple(sig, np.zeros(2))
+    p, offs = O.probs_total(A, b, c, [60], 59)
+    np.testing.assert_allclose(np.real(p), (1 - q) * q ** np.arange(60), rtol=1e-12, atol=1e-16)
+    for eps in (1e-2, 1e-4, 1e-7):
+        expect = math.ceil(math.log(eps) / math.log(q)) - 1
+        assert O.stop_level(np.real(p), eps) == expect
+    assert O.stop_level(np.real(p)[:3], 1e-9) is None
+
+
+def test_probs_total_box_and_pattern_routes_agree():
+    rng = np.random.default_rng(31)
+    U = W.haar_unitary(rng, 3)
+    A, b, c = triple([0.5, 0.3, 0.6], U, 0.85, [0.2, 0.1j, -0.1])
+    p_box, offs = O.probs_total(A, b, c, [6, 5, 7], 7)            # small: via the box
+    pts, _ = O.level_points([6, 5, 7], 7)
+    p_pat = np.array([complex(O.fock_diag_pattern(A, b, c, [6, 5, 7], 0b111, n)) for n in pts])
+    np.testing.assert_allclose(p_box, p_pat, rtol=1e-13, atol=1e-17)
