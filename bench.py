@@ -239,6 +239,46 @@ def state_leg(steps=20):
                 norm2=float((psi.abs() ** 2).sum()))
 
 
+def total_leg(steps=20, N=16, eps=0.05):
+    """Total photon cutoff: the 8-mode lossy state of config 5 (r~U(0.5,1.0),
+    eta~U(0.8,0.95), b = 0) with per-mode cutoff 40 and |n| <= N, p(n) of the
+    C(N+8, 8) points in level order (complex128); then the same sweep with
+    probability-sum stopping at 1 - eps (the stream is synchronised once per 4
+    levels)."""
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+    ci = W.config5()
+    dt, dev = torch.complex128, "cuda"
+    plan = F.Plan([40] * 8, 0, dt, "zero", total_cutoff=N)
+    A = torch.tensor(ci.A, dtype=dt, device=dev)
+    b = torch.tensor(ci.b, dtype=dt, device=dev)
+    c = torch.tensor([ci.c], dtype=dt, device=dev)
+    ws = torch.empty(plan.workspace(False)[0], dtype=torch.uint8, device=dev)
+    out = torch.empty(plan.out_shape, dtype=dt, device=dev)
+    for _ in range(3):
+        F.detection_probs(plan, A, b, c, out, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.detection_probs(plan, A, b, c, out, ws)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    full_mass = float(out.real.sum())
+    levels, mass = F.detection_probs_until(plan, A, b, c, out, eps, ws)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        levels, mass = F.detection_probs_until(plan, A, b, c, out, eps, ws)
+    sec_stop = time.perf_counter() - t1
+    F.fd_device_status(plan)
+    pts = plan.query(F.FD_Q_OUT_ELEMS)
+    return dict(workload=f"config5 state (8 modes, b=0), per-mode cutoff 40, total photon cutoff {N}: "
+                         f"p(n) for the {pts} points with |n| <= {N}, complex128",
+                points=pts, ms_per_call=1e3 * sec / steps, value=pts * steps / sec, unit="probabilities/s",
+                mass_below_cutoff=full_mass,
+                stopping={"eps": eps, "levels_done": levels, "mass": mass, "ms_per_call": 1e3 * sec_stop / steps})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +289,7 @@ def main():
     ap.add_argument("--cpu-corner", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
     ap.add_argument("--no-state", action="store_true", help="skip the pure-state (state vector) leg")
+    ap.add_argument("--no-total", action="store_true", help="skip the total-photon-cutoff leg")
     ap.add_argument("--gradient-leg", action="store_true",
                     help="also time the 64-circuit gradient workload (forward + VJP per circuit)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -383,6 +424,8 @@ def main():
         line["batched"] = batched_leg()
     if not args.no_state:
         line["state_vector"] = state_leg()
+    if not args.no_total:
+        line["total_cutoff"] = total_leg()
     if args.gradient_leg:
         line["gradient_batch"] = gradient_leg()
     if not args.no_cpu_baseline:

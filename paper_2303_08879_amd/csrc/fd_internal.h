@@ -247,6 +247,7 @@ struct KTimer {
 // back (the stream is synchronised) and the sweep ends at the first level S*
 // with sum_{S <= S*} mass >= 1 - eps; F0 above S* is cleared.
 constexpr int kStopBlock = 4;
+constexpr int kMassParts = 32;   // workgroups per level of the mass sum (partials added on the host in order)
 struct StopRule {
   double eps = 0.0;
   int levels_done = 0;   // out: S* + 1 (smax + 1 if the sum never reaches 1 - eps)

@@ -232,22 +232,28 @@ __global__ __launch_bounds__(kThreads) void k_copy_levels(const cx<R>* __restric
   if (bad) atomicOr(status, 1);
 }
 
-// mass[S] = sum of Re F0 over level S (the detection probabilities of level
-// S), S = S0 + blockIdx.x; strided per-thread sums, then a fixed-order tree.
+// Partial masses of level S = S0 + blockIdx.y (the sum of Re F0, i.e. of the
+// detection probabilities of the level): part blockIdx.x of kMassParts
+// contiguous chunks, strided per-thread sums, then a fixed-order tree;
+// mass[S * kMassParts + part].
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_level_mass(const cx<R>* __restrict__ f0, const int64_t* __restrict__ lvl,
                                                          int S0, double* mass) {
   __shared__ double red[kThreads];
-  const int S = S0 + blockIdx.x;
+  const int S = S0 + blockIdx.y;
+  const int64_t n = lvl[S + 1] - lvl[S];
+  const int64_t chunk = (n + kMassParts - 1) / kMassParts;
+  const int64_t i0 = lvl[S] + (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(lvl[S + 1], i0 + chunk);
   double acc = 0.0;
-  for (int64_t i = lvl[S] + threadIdx.x; i < lvl[S + 1]; i += blockDim.x) acc += (double)ld(f0 + i).x;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc += (double)ld(f0 + i).x;
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) mass[S] = red[0];
+  if (threadIdx.x == 0) mass[(size_t)S * kMassParts + blockIdx.x] = red[0];
 }
 
 template <typename R>
@@ -332,16 +338,19 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
     if (stop && ((S + 1) % kStopBlock == 0 || S == Pl.smax)) {
       // levels S0..S are final (F0 of a level is written by the launch below it)
       const int S0 = S - S % kStopBlock;
-      hipLaunchKernelGGL((k_level_mass<R>), dim3(S - S0 + 1), dim3(kThreads), 0, st, f0, Pl.d_lvl, S0, Pl.d_mass);
+      hipLaunchKernelGGL((k_level_mass<R>), dim3(kMassParts, S - S0 + 1), dim3(kThreads), 0, st, f0, Pl.d_lvl, S0,
+                         Pl.d_mass);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      double hm[kStopBlock];
-      if ((e = hipMemcpyAsync(hm, Pl.d_mass + S0, (size_t)(S - S0 + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                              st)) != hipSuccess ||
+      double hm[kStopBlock * kMassParts];
+      if ((e = hipMemcpyAsync(hm, Pl.d_mass + (size_t)S0 * kMassParts, (size_t)(S - S0 + 1) * kMassParts * sizeof(double),
+                              hipMemcpyDeviceToHost, st)) != hipSuccess ||
           (e = hipStreamSynchronize(st)) != hipSuccess)
         return e;
       int hit = -1;
       for (int k = 0; k <= S - S0 && hit < 0; ++k) {
-        stop->mass += hm[k];
+        double m = 0.0;
+        for (int q = 0; q < kMassParts; ++q) m += hm[k * kMassParts + q];
+        stop->mass += m;
         if (stop->mass >= 1.0 - stop->eps) hit = S0 + k;
       }
       if (hit >= 0) {

@@ -460,7 +460,7 @@ fd_status ensure_device(Plan* P, std::string* err) {
     return FD_ERR_HIP;
   }
   if (P->MD > 0 && P->B == 1 &&
-      hipMalloc((void**)&P->d_mass, (size_t)(P->smax + 1) * sizeof(double)) != hipSuccess) {
+      hipMalloc((void**)&P->d_mass, (size_t)(P->smax + 1) * kMassParts * sizeof(double)) != hipSuccess) {
     *err = "hipMalloc of the level masses failed";
     return FD_ERR_OOM;
   }
