@@ -257,9 +257,10 @@ fd_status fd_device_status(fd_plan p, hipStream_t stream);
 
 /* ---- Total photon cutoff and probability-sum stopping -----------------
  * fd_plan_create_total -- a plan with every mode detected whose lattice is
- * cut by the total photon number: the points n with n_j < C_j and |n| <=
- * total_cutoff (the level sets of Algorithm 1 become simplices; Sec. 3.1:
- * the sweep stops at level total_cutoff).  fock_diag_fwd / detection_probs
+ * cut by the total photon number (the global cutoff condition of Sec. 2.3,
+ * Eq. global_boundary_conditions, with N_max = total_cutoff + 1): the points
+ * n with n_j < C_j and |n| <= total_cutoff, i.e. the levels of Algorithm 1
+ * up to total_cutoff, whose level sets are simplices.  fock_diag_fwd / detection_probs
  * on such a plan return p(n) in level order: level S = 0, 1, ... at
  * fd_plan_level_offsets[S], inside a level the points in lexicographic order
  * with the first mode slowest; FD_Q_OUT_ELEMS entries.  Per-mode cutoffs
@@ -278,8 +279,9 @@ fd_status fd_plan_create_total(int M, const int* cutoffs, int total_cutoff, fd_d
 fd_status fd_plan_level_offsets(fd_plan p, int64_t* offsets, int n);
 
 /* detection_probs_until -- detection_probs with probability-sum stopping
- * (the cumulative probability of the computed levels measures how much of
- * the state lies below the cutoff): levels are swept in blocks of 4; after
+ * (the second cutoff condition of Sec. 2.3: stop once the probabilities of
+ * the outcomes computed so far sum close enough to one): levels are swept in
+ * blocks of 4; after
  * each block the masses sum_{|n| = S} p(n) are read back (this call
  * synchronises `stream` once per block) and the sweep ends at the first
  * level S* with sum_{S <= S*} mass(S) >= 1 - eps.  probs holds p(n) for

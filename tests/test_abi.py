@@ -226,3 +226,14 @@ def test_total_cutoff_plan_counts_and_offsets():
                                    ctypes.byref(ctypes.c_double()), 256, 1 << 20, None) == F.FD_ERR_INVALID_ARG
     assert L.detection_probs_until(p.handle, 16, 16, 16, 16, 1e-3, None, None, 256, 1 << 20, None) == \
         F.FD_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("M,Nmax", [(3, 6), (4, 5), (2, 9)])
+def test_total_cutoff_pivot_count_app_b1(M, Nmax):
+    # App. B.1, global cutoff w < 2 N_max (|n| <= N_max - 1): per level N the
+    # diagonal pivots C(N+M-1, N) plus the K-pivots sum_K C(N+M-K, N) =
+    # C(N+M, N+1); per-mode cutoffs large enough not to bind
+    p = F.Plan([64] * M, 0, total_cutoff=Nmax - 1)
+    expect = sum(math.comb(N + M - 1, N) + math.comb(N + M, N + 1) for N in range(Nmax))
+    assert p.query(F.FD_Q_PIVOTS) == expect
+    assert p.query(F.FD_Q_OUT_ELEMS) == math.comb(Nmax - 1 + M, M)
