@@ -332,10 +332,30 @@ fd_status fd_state_plan_workspace(fd_state_plan p, size_t* bytes);
 fd_status fock_state_fwd(fd_state_plan p, const void* A, const void* b, const void* c, void* psi,
                          void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* fock_state_vjp -- reverse mode of fock_state_fwd: with g = dL/dpsi^* the
+ * cotangent of psi (Sec. 2.5, Eqs. dL_dB and dL_dA: the returned values are
+ * sum_k g_k conj(d psi_k / d x)), writes dA (M x M, symmetric: A enters as
+ * its symmetric part (A + A^T)/2), db (M) and dc (1).  The local gradients
+ * are the closed-form solutions of the tangent recurrences of Sec. 2.5:
+ * d psi_k/d b_i = sqrt(k_i) psi_{k-1_i}, d psi_k/d A_il = 1/2 sqrt(k_i (k_l -
+ * [i = l])) psi_{k-1_i-1_l}, d psi_k/d c = psi_k / c, so the cotangents are
+ * dot products of g with shifted copies of psi over the box (entries of modes
+ * with cutoff 1 are zero).  Deterministic (fixed reduction order).
+ *   psi        device, the output of fock_state_fwd for the same (A, b, c)
+ *   dpsi       device, g in psi's layout
+ *   c          device, the c of the forward call (dc = sum g conj(psi) / conj(c))
+ *   workspace  device, >= fd_state_plan_vjp_workspace bytes, 256-byte aligned
+ * Errors as fock_state_fwd. */
+fd_status fd_state_plan_vjp_workspace(fd_state_plan p, size_t* bytes);
+fd_status fock_state_vjp(fd_state_plan p, const void* c, const void* psi, const void* dpsi, void* dA, void* db,
+                         void* dc, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 /* As fd_device_status, for a state plan. */
 fd_status fd_state_device_status(fd_state_plan p, hipStream_t stream);
 /* As fd_plan_timing / fd_plan_kernel_times; kinds FD_K_PREP (A, b, c
- * staging), FD_K_FWD_LEVEL (one launch per computed level), FD_K_OUT_PERM. */
+ * staging), FD_K_FWD_LEVEL (one launch per computed level), FD_K_OUT_PERM,
+ * FD_K_VJP_LEVEL (the cotangent dot products of fock_state_vjp, all their
+ * launches as one record) and FD_K_VJP_FINAL. */
 fd_status fd_state_plan_timing(fd_state_plan p, uint32_t kind_mask);
 fd_status fd_state_plan_kernel_times(fd_state_plan p, int kind, int64_t* launches, double* total_ms);
 

@@ -519,6 +519,27 @@ fd_status fock_state_fwd(fd_state_plan sp, const void* A, const void* b, const v
   return ok();
 }
 
+fd_status fd_state_plan_vjp_workspace(fd_state_plan sp, size_t* bytes) {
+  if (!sp || !bytes) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  *bytes = fd::state_vjp_ws_bytes(sp->inner->P);
+  return ok();
+}
+
+fd_status fock_state_vjp(fd_state_plan sp, const void* c, const void* psi, const void* dpsi, void* dA, void* db,
+                         void* dc, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = sp->inner->P;
+  fd_status s = check_ptrs(P, {c, psi, dpsi, dA, db, dc, workspace});
+  if (s != FD_OK) return s;
+  if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < fd::state_vjp_ws_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  if (fd::run_state_vjp(P, c, psi, dpsi, dA, db, dc, workspace, stream) != hipSuccess)
+    return fail(FD_ERR_HIP, "kernel launch failed");
+  return ok();
+}
+
 fd_status fd_state_device_status(fd_state_plan sp, hipStream_t stream) {
   if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
   return fd_device_status(sp->inner, stream);

@@ -268,6 +268,9 @@ hipError_t launch_out_perm(const Plan& P, const void* f0, void* rho, hipStream_t
 size_t state_ws_bytes(const Plan& P);
 hipError_t run_state_fwd(const Plan& P, bool b_zero, const void* A, const void* b, const void* c, void* psi, void* ws,
                          hipStream_t st);
+size_t state_vjp_ws_bytes(const Plan& P);
+hipError_t run_state_vjp(const Plan& P, const void* c, const void* psi, const void* g, void* dA, void* db, void* dc,
+                         void* ws, hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,
                    const void* drho, void* dA, void* db, void* dc, void* ws, hipStream_t st);
 

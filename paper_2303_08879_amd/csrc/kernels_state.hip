@@ -17,6 +17,7 @@
 // the target less one up to mode i).
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "fd_device.h"
 
@@ -27,9 +28,10 @@ struct StateModes {
   int mode[kMaxD];      // kept mode k -> caller's mode index
 };
 
-// A and b of the kept modes into the workspace (MD x MD, then MD), psi at
-// the vacuum = c; non-finite inputs set status bit 0, a non-zero b under the
-// b = 0 promise status bit 1.
+// A (symmetrised, (A + A^T)/2, as for density matrices) and b of the kept
+// modes into the workspace (MD x MD, then MD), psi at the vacuum = c;
+// non-finite inputs set status bit 0, a non-zero b under the b = 0 promise
+// status bit 1.
 template <typename R>
 __global__ __launch_bounds__(64) void k_state_prep(int M, StateModes sm, const cx<R>* __restrict__ A,
                                                    const cx<R>* __restrict__ b, const cx<R>* __restrict__ c,
@@ -39,8 +41,9 @@ __global__ __launch_bounds__(64) void k_state_prep(int M, StateModes sm, const c
   int bad = 0;
   for (int i = threadIdx.x; i < MD * MD; i += blockDim.x) {
     const cx<R> v = ld(A + (size_t)sm.mode[i / MD] * M + sm.mode[i % MD]);
+    const cx<R> w = ld(A + (size_t)sm.mode[i % MD] * M + sm.mode[i / MD]);
     if (!isfinite(v.x) || !isfinite(v.y)) bad |= 1;
-    st(Ak + i, v);
+    st(Ak + i, cmake<R>(R(0.5) * (v.x + w.x), R(0.5) * (v.y + w.y)));
   }
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
     const cx<R> v = ld(b + i);
@@ -120,6 +123,219 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
     }
     st(cur + r, cscale(acc, isq[ni]));
   }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode.  The local gradients of Sec. 2.5 (the solutions of its
+// tangent recurrences for b and A) have closed forms in the amplitudes:
+//   d psi_k / d b_i   = sqrt(k_i) psi_{k - 1_i},
+//   d psi_k / d A_il  = 1/2 sqrt(k_i (k_l - [i = l])) psi_{k - 1_i - 1_l},
+//   d psi_k / d c     = psi_k / c,
+// and every shifted amplitude lies inside the box, so the cotangents
+//   bbar_i = sum_k g_k conj(d psi_k / d b_i)   (g = dL/dpsi^*, Eqs. dL_dB, dL_dA)
+// are weighted dot products of g with shifted copies of psi.  One launch
+// accumulates up to kVjpGroup of them; each thread sums its indices in
+// order, the workgroup folds its threads in a fixed tree into its slot, and
+// the final kernel adds the slots in order (bitwise reproducible).
+// ---------------------------------------------------------------------------
+constexpr int kVjpGroup = 8;
+constexpr int kVjpSlots = 1024;
+
+struct StateVjpTerms {
+  int n;                    // terms in this launch (<= kVjpGroup)
+  int col[kVjpGroup];       // output column of each term
+  int kind[kVjpGroup];      // 0: bbar_i, 1: Abar_il (i < l), 2: Abar_ii, 3: sum g conj(psi)
+  int i[kVjpGroup], l[kVjpGroup];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_state_vjp_terms(DevPlan P, const cx<R>* __restrict__ psi,
+                                                              const cx<R>* __restrict__ g, int total, StateVjpTerms T,
+                                                              int ncol, double2* __restrict__ slots) {
+  __shared__ double2 red[kThreads];
+  const int MD = P.MD;
+  int stride[kMaxD];
+  {
+    int s = 1;
+    for (int d = MD - 1; d >= 0; --d) {
+      stride[d] = s;
+      s *= P.CD[d];
+    }
+  }
+  double ax[kVjpGroup], ay[kVjpGroup];
+#pragma unroll
+  for (int t = 0; t < kVjpGroup; ++t) ax[t] = ay[t] = 0.0;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+    // digits of x (last mode fastest), exact double-reciprocal split
+    int k[kMaxD];
+    int rem = x;
+    for (int d = MD - 1; d >= 0; --d) {
+      const int q = (int)((rem + 0.5) * P.cinv[d]);
+      k[d] = rem - q * P.CD[d];
+      rem = q;
+    }
+    const cx<R> gv = ld(g + x);
+#pragma unroll
+    for (int t = 0; t < kVjpGroup; ++t) {
+      if (t >= T.n) break;
+      const int kind = T.kind[t], i = T.i[t], l = T.l[t];
+      double w = 0.0;
+      int y = x;
+      if (kind == 0) {
+        if (k[i] < 1) continue;
+        w = sqrt((double)k[i]);
+        y = x - stride[i];
+      } else if (kind == 1) {
+        if (k[i] < 1 || k[l] < 1) continue;
+        w = 0.5 * sqrt((double)k[i] * (double)k[l]);
+        y = x - stride[i] - stride[l];
+      } else if (kind == 2) {
+        if (k[i] < 2) continue;
+        w = 0.5 * sqrt((double)k[i] * (double)(k[i] - 1));
+        y = x - 2 * stride[i];
+      } else {
+        w = 1.0;
+      }
+      const cx<R> pv = ld(psi + y);
+      // g * conj(w psi_y)
+      const double px = w * (double)pv.x, py = w * (double)pv.y;
+      ax[t] += (double)gv.x * px + (double)gv.y * py;
+      ay[t] += (double)gv.y * px - (double)gv.x * py;
+    }
+  }
+  for (int t = 0; t < T.n; ++t) {
+    red[threadIdx.x] = make_double2(ax[t], ay[t]);
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        red[threadIdx.x].x += red[threadIdx.x + w].x;
+        red[threadIdx.x].y += red[threadIdx.x + w].y;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) slots[(size_t)blockIdx.x * ncol + T.col[t]] = red[0];
+    __syncthreads();
+  }
+}
+
+// One workgroup per caller entry of dA (M x M), db (M), dc: the slots of its
+// column added in order (zero for modes with cutoff 1), Abar mirrored.
+struct StateVjpMap {
+  int M, MD, ncol, nslots;
+  int mode[kMaxD];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_state_vjp_final(StateVjpMap m, const double2* __restrict__ slots,
+                                                              const cx<R>* __restrict__ c, cx<R>* dA, cx<R>* db,
+                                                              cx<R>* dc) {
+  __shared__ double2 red[kThreads];
+  const int e = blockIdx.x, M = m.M, MD = m.MD;
+  int col = -1;
+  if (e < M * M) {
+    int ki = -1, kl = -1;
+    for (int d = 0; d < MD; ++d) {
+      if (m.mode[d] == e / M) ki = d;
+      if (m.mode[d] == e % M) kl = d;
+    }
+    if (ki >= 0 && kl >= 0) {
+      const int a = min(ki, kl), bb = max(ki, kl);
+      col = MD + a * MD - a * (a - 1) / 2 + (bb - a);   // columns: bbar (MD), then the upper triangle row by row
+    }
+  } else if (e < M * M + M) {
+    for (int d = 0; d < MD; ++d)
+      if (m.mode[d] == e - M * M) col = d;
+  } else {
+    col = m.ncol - 1;
+  }
+  double sx = 0.0, sy = 0.0;
+  if (col >= 0)
+    for (int s = threadIdx.x; s < m.nslots; s += blockDim.x) {
+      sx += slots[(size_t)s * m.ncol + col].x;
+      sy += slots[(size_t)s * m.ncol + col].y;
+    }
+  red[threadIdx.x] = make_double2(sx, sy);
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double2 t = red[0];
+  if (e < M * M) {
+    st(dA + e, cmake<R>((R)t.x, (R)t.y));
+  } else if (e < M * M + M) {
+    st(db + (e - M * M), cmake<R>((R)t.x, (R)t.y));
+  } else {
+    // cbar = sum g conj(psi / c) = (sum g conj(psi)) / conj(c)
+    const cx<R> cv = ld(c);
+    const double cr = (double)cv.x, ci = (double)cv.y, n2 = cr * cr + ci * ci;
+    st(dc, cmake<R>((R)((t.x * cr - t.y * ci) / n2), (R)((t.y * cr + t.x * ci) / n2)));
+  }
+}
+
+size_t state_vjp_ws_bytes(const Plan& Pl) {
+  const int ncol = Pl.MD + Pl.MD * (Pl.MD + 1) / 2 + 1;
+  return (size_t)kVjpSlots * ncol * sizeof(double2);
+}
+
+template <typename R>
+static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi, const void* g, void* dA, void* db,
+                                  void* dc, void* ws, hipStream_t st) {
+  const int MD = Pl.MD, ncol = MD + MD * (MD + 1) / 2 + 1;
+  const int total = (int)Pl.nodes_total;
+  const DevPlan P = make_devplan(Pl, true);
+  double2* slots = static_cast<double2*>(ws);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + kThreads - 1) / kThreads, kVjpSlots));
+  // the terms: bbar_i (col i), Abar_il for i <= l (col MD + upper-triangle index), sum g conj(psi) (last col)
+  std::vector<StateVjpTerms> launches;
+  StateVjpTerms cur;
+  std::memset(&cur, 0, sizeof(cur));
+  auto add = [&](int col, int kind, int i, int l) {
+    cur.col[cur.n] = col;
+    cur.kind[cur.n] = kind;
+    cur.i[cur.n] = i;
+    cur.l[cur.n] = l;
+    if (++cur.n == kVjpGroup) {
+      launches.push_back(cur);
+      std::memset(&cur, 0, sizeof(cur));
+    }
+  };
+  for (int i = 0; i < MD; ++i) add(i, 0, i, i);
+  for (int a = 0; a < MD; ++a)
+    for (int bb = a; bb < MD; ++bb) add(MD + a * MD - a * (a - 1) / 2 + (bb - a), a == bb ? 2 : 1, a, bb);
+  add(ncol - 1, 3, 0, 0);
+  if (cur.n) launches.push_back(cur);
+  {
+    KTimer kt(Pl, KK_VJP_LEVEL, st);
+    for (const StateVjpTerms& T : launches) {
+      hipLaunchKernelGGL((k_state_vjp_terms<R>), dim3(grid), dim3(kThreads), 0, st, P,
+                         static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(g), total, T, ncol, slots);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  StateVjpMap m;
+  std::memset(&m, 0, sizeof(m));
+  m.M = Pl.M;
+  m.MD = MD;
+  m.ncol = ncol;
+  m.nslots = grid;
+  for (int d = 0; d < MD; ++d) m.mode[d] = Pl.dmodes[d];
+  KTimer kt(Pl, KK_VJP_FINAL, st);
+  hipLaunchKernelGGL((k_state_vjp_final<R>), dim3(Pl.M * Pl.M + Pl.M + 1), dim3(kThreads), 0, st, m, slots,
+                     static_cast<const cx<R>*>(c), static_cast<cx<R>*>(dA), static_cast<cx<R>*>(db),
+                     static_cast<cx<R>*>(dc));
+  return hipGetLastError();
+}
+
+hipError_t run_state_vjp(const Plan& Pl, const void* c, const void* psi, const void* g, void* dA, void* db, void* dc,
+                         void* ws, hipStream_t st) {
+  if (Pl.dt == FD_C64) return run_state_vjp_t<float>(Pl, c, psi, g, dA, db, dc, ws, st);
+  return run_state_vjp_t<double>(Pl, c, psi, g, dA, db, dc, ws, st);
 }
 
 size_t state_ws_bytes(const Plan& Pl) {

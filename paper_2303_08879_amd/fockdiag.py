@@ -27,7 +27,8 @@ EXPORTS = [
     "fd_plan_timing", "fd_plan_kernel_times", "fd_plan_use_graphs", "fd_batch_set_tuning", "fd_batch_get_tuning",
     "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
-    "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until",
+    "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
+    "fock_state_vjp",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -85,6 +86,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     L.fd_state_plan_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, u32, ctypes.POINTER(vp)]
     L.fd_state_plan_destroy.argtypes = [vp]
+    L.fd_state_plan_vjp_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.fock_state_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fd_state_plan_workspace.argtypes = [vp, ctypes.POINTER(sz)]
     L.fock_state_fwd.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.fd_state_device_status.argtypes = [vp, vp]
@@ -202,10 +205,20 @@ class StatePlan:
         _check(lib().fd_state_plan_workspace(self.handle, ctypes.byref(n)))
         return n.value
 
+    def vjp_workspace(self):
+        n = ctypes.c_size_t()
+        _check(lib().fd_state_plan_vjp_workspace(self.handle, ctypes.byref(n)))
+        return n.value
+
 
 def fock_state_fwd(plan, A, b, c, psi, workspace, stream=None):
     _check(lib().fock_state_fwd(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(psi), _ptr(workspace),
                                 _nbytes(workspace), _stream(stream)))
+
+
+def fock_state_vjp(plan, c, psi, dpsi, dA, db, dc, workspace, stream=None):
+    _check(lib().fock_state_vjp(plan.handle, _ptr(c), _ptr(psi), _ptr(dpsi), _ptr(dA), _ptr(db), _ptr(dc),
+                                _ptr(workspace), _nbytes(workspace), _stream(stream)))
 
 
 def fd_state_device_status(plan, stream=None):

@@ -124,3 +124,40 @@ class FockDiagFunction(torch.autograd.Function):
 def fock_diag_ad(A, b, c, cutoffs, detected_mask, b_mode="auto"):
     """Differentiable rho[k_U, l_U, n_D] w.r.t. (A, b, c)."""
     return FockDiagFunction.apply(A, b, c, tuple(cutoffs), int(detected_mask), b_mode)
+
+
+class StateVectorFunction(torch.autograd.Function):
+    """psi = state_vector(A, b, c); backward = fock_state_vjp (the cotangents
+    sum_k g_k conj(d psi_k / d x), PyTorch's convention for holomorphic maps;
+    A enters as its symmetric part)."""
+
+    @staticmethod
+    def forward(ctx, A, b, c, cutoffs, b_mode):
+        dtype = A.dtype
+        plan = get_state_plan(cutoffs, dtype, b_mode)
+        A_, b_, c_ = A.contiguous(), b.contiguous(), c.reshape(1).contiguous()
+        ws = _workspace(plan.workspace(), A.device)
+        psi = torch.empty(plan.out_shape, dtype=dtype, device=A.device)
+        F.fock_state_fwd(plan, A_, b_, c_, psi, ws)
+        ctx.plan = plan
+        ctx.c_shape = c.shape
+        ctx.save_for_backward(c_, psi)
+        return psi
+
+    @staticmethod
+    def backward(ctx, grad_psi):
+        c, psi = ctx.saved_tensors
+        plan = ctx.plan
+        ws = _workspace(plan.vjp_workspace(), psi.device)
+        M = len(plan.cutoffs)
+        dA = torch.empty((M, M), dtype=psi.dtype, device=psi.device)
+        db = torch.empty(M, dtype=psi.dtype, device=psi.device)
+        dc = torch.empty(1, dtype=psi.dtype, device=psi.device)
+        F.fock_state_vjp(plan, c, psi, grad_psi.contiguous(), dA, db, dc, ws)
+        return dA, db, dc.reshape(ctx.c_shape), None, None
+
+
+def state_vector_ad(A, b, c, cutoffs, b_mode="auto"):
+    """state_vector with autograd support (A, b, c device tensors)."""
+    return StateVectorFunction.apply(A, b, c, tuple(int(x) for x in cutoffs), b_mode)
+

@@ -114,3 +114,76 @@ def test_status_reports_nonzero_b_and_nonfinite():
     with pytest.raises(F.FockDiagError) as e:
         F.fd_state_device_status(plan)
     assert e.value.status == F.FD_ERR_NONFINITE
+
+
+VJP_CASES = [([6], False), ([5, 4], False), ([5, 4], True), ([4, 1, 3], False), ([3, 3, 3, 3], True),
+             ([2, 4, 3, 2], False), ([3] * 8, False), ([7, 2, 5], False)]
+
+
+def gpu_state_vjp(A, b, c, cut, g, dtype=torch.complex128):
+    print(f"[gpu] state vjp cut={cut} dtype={dtype}", flush=True)
+    plan = F.StatePlan(cut, dtype, "general")
+    dev = "cuda"
+    At, bt = torch.tensor(A, dtype=dtype, device=dev), torch.tensor(b, dtype=dtype, device=dev)
+    ct = torch.tensor([c], dtype=dtype, device=dev)
+    ws = torch.empty(plan.workspace(), dtype=torch.uint8, device=dev)
+    psi = torch.empty(cut, dtype=dtype, device=dev)
+    F.fock_state_fwd(plan, At, bt, ct, psi, ws)
+    vws = torch.empty(plan.vjp_workspace(), dtype=torch.uint8, device=dev)
+    gt = torch.tensor(g, dtype=dtype, device=dev)
+    M = len(cut)
+    dA = torch.empty((M, M), dtype=dtype, device=dev)
+    db = torch.empty(M, dtype=dtype, device=dev)
+    dc = torch.empty(1, dtype=dtype, device=dev)
+    F.fock_state_vjp(plan, ct, psi, gt, dA, db, dc, vws)
+    torch.cuda.synchronize()
+    return dA.cpu().numpy(), db.cpu().numpy(), complex(dc.cpu().numpy()[0])
+
+
+def grad_err(got, ref):
+    (gA, gb, gc), (rA, rb, rc) = got, ref
+    x = np.concatenate([gA.ravel(), gb.ravel(), [gc]]).astype(np.complex128)
+    y = np.concatenate([np.asarray(rA).ravel(), np.asarray(rb).ravel(), [rc]])
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("cut,b_zero", VJP_CASES)
+def test_state_vjp_parity(cut, b_zero):
+    rng = np.random.default_rng(sum(cut) * 7 + len(cut) + int(b_zero))
+    A, b, c = rand_state(rng, len(cut), b_zero)
+    g = rng.standard_normal(cut) + 1j * rng.standard_normal(cut)
+    got = gpu_state_vjp(A, b, c, cut, g)
+    ref = O.adjoint_closed_form(A, b, c, O.state_vector(A, b, c, cut), g)
+    assert grad_err(got, ref) <= TOL
+    assert np.allclose(got[0], got[0].T, rtol=0, atol=0)   # symmetric by construction
+    got2 = gpu_state_vjp(A, b, c, cut, g)
+    assert all(np.array_equal(np.asarray(u), np.asarray(v)) for u, v in zip(got, got2))   # deterministic
+
+
+def test_state_vjp_nonsymmetric_A_and_c64():
+    rng = np.random.default_rng(77)
+    cut = [4, 5, 3]
+    X = 0.3 * (rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))   # not symmetric
+    b = 0.3 * (rng.standard_normal(3) + 1j * rng.standard_normal(3))
+    c = 0.9 + 0.2j
+    As = 0.5 * (X + X.T)
+    g = rng.standard_normal(cut) + 1j * rng.standard_normal(cut)
+    ref = O.adjoint_closed_form(As, b, c, O.state_vector(As, b, c, cut), g)
+    assert grad_err(gpu_state_vjp(X, b, c, cut, g), ref) <= TOL
+    assert grad_err(gpu_state_vjp(X, b, c, cut, g, torch.complex64), ref) <= 1e-5
+
+
+def test_state_vector_autograd():
+    ci = W.pure_state(9, 3, [6, 5, 4], alpha_var=0.3)
+    dev = "cuda"
+    A = torch.tensor(ci.A, device=dev, requires_grad=True)
+    b = torch.tensor(ci.b, device=dev, requires_grad=True)
+    c = torch.tensor([ci.c], dtype=torch.complex128, device=dev, requires_grad=True)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(ci.cutoffs) + 1j * rng.standard_normal(ci.cutoffs)
+    psi = ops.state_vector_ad(A, b, c, ci.cutoffs)
+    (psi * torch.tensor(w, device=dev).conj()).real.sum().backward()
+    torch.cuda.synchronize()
+    ref = O.adjoint_closed_form(ci.A, ci.b, ci.c, O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs), w)
+    got = (A.grad.cpu().numpy(), b.grad.cpu().numpy(), complex(c.grad.cpu().numpy()[0]))
+    assert grad_err(got, ref) <= TOL

@@ -372,3 +372,28 @@ def test_probs_total_box_and_pattern_routes_agree():
     pts, _ = O.level_points([6, 5, 7], 7)
     p_pat = np.array([complex(O.fock_diag_pattern(A, b, c, [6, 5, 7], 0b111, n)) for n in pts])
     np.testing.assert_allclose(p_box, p_pat, rtol=1e-13, atol=1e-17)
+
+
+def test_state_vector_vjp_finite_differences():
+    # the closed-form adjoint with D = M (one index per mode) against central
+    # differences of the state vector along random symmetric directions
+    rng = np.random.default_rng(41)
+    M, cut = 3, [4, 3, 5]
+    X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    A = 0.25 * (X + X.T)
+    b = 0.3 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    c = 0.8 - 0.1j
+    psi = O.state_vector(A, b, c, cut)
+    g = rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape)
+    dA, db, dc = O.adjoint_closed_form(A, b, c, psi, g)
+    h = 1e-6
+    for _ in range(6):
+        EA = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+        EA = 0.5 * (EA + EA.T)
+        Eb = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+        Ec = complex(rng.standard_normal(), rng.standard_normal())
+        fp = O.state_vector(A + h * EA, b + h * Eb, c + h * Ec, cut)
+        fm = O.state_vector(A - h * EA, b - h * Eb, c - h * Ec, cut)
+        fd = np.real(np.sum(np.conj(g) * (fp - fm))) / (2 * h)
+        pred = np.real(np.sum(np.conj(dA) * EA) + np.sum(np.conj(db) * Eb) + np.conj(dc) * Ec)
+        assert abs(fd - pred) < 1e-7 * max(1.0, abs(pred))
