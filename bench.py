@@ -218,8 +218,23 @@ def state_leg(steps=20):
     _, ms_p = F.fd_state_plan_kernel_times(plan, F.FD_K_OUT_PERM)
     F.fd_state_plan_timing(plan, 0)
     F.fd_state_device_status(plan)
+    # reverse mode with a seeded cotangent: dA, db, dc (45 dot products over the box)
+    g = torch.tensor(W.random_cotangent(plan.out_shape, seed=5), dtype=dt, device=dev)
+    vws = torch.empty(plan.vjp_workspace(), dtype=torch.uint8, device=dev)
+    dA = torch.empty((8, 8), dtype=dt, device=dev)
+    db = torch.empty(8, dtype=dt, device=dev)
+    dc = torch.empty(1, dtype=dt, device=dev)
+    F.fock_state_vjp(plan, c, psi, g, dA, db, dc, vws)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        F.fock_state_vjp(plan, c, psi, g, dA, db, dc, vws)
+    torch.cuda.synchronize()
+    sec_v = time.perf_counter() - t2
     N = level_counts(ci.cutoffs)
     smax = len(N) - 1
+    terms = 8 + 8 * 9 // 2 + 1          # bbar, the upper triangle of Abar, cbar
+    passes = -(-terms // 16)
     alg = sum(16 * (N[S] + N[S - 1] + N[S - 2]) for S in range(2, smax + 1, 2))
     if smax % 2:
         alg += 16 * N[smax]   # the last odd level, cleared alone
@@ -236,7 +251,12 @@ def state_leg(steps=20):
                           "launches": launches, "avg_launch_us": round(1e3 * ms_l / nl, 3),
                           "algorithmic_bytes_per_launch": int(alg // max(launches, 1)),
                           "traffic": measured_traffic("k_state_level")},
-                norm2=float((psi.abs() ** 2).sum()))
+                norm2=float((psi.abs() ** 2).sum()),
+                vjp={"ms_per_call": 1e3 * sec_v / steps, "launches": passes + 1,
+                     "note": f"{passes} launches of up to 16 of the {terms} cotangent dot products (each reads "
+                             "the cotangent and shifted amplitudes once: 32 B per amplitude) and the ordered "
+                             "slot reduction",
+                     "algorithmic_GBs": round(passes * 32 * amps * steps / sec_v / 1e9, 1)})
 
 
 def total_leg(steps=20, N=16, eps=0.05):

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
 // order, the workgroup folds its threads in a fixed tree into its slot, and
 // the final kernel adds the slots in order (bitwise reproducible).
 // ---------------------------------------------------------------------------
-constexpr int kVjpGroup = 8;
+constexpr int kVjpGroup = 16;
 constexpr int kVjpSlots = 1024;
 
 struct StateVjpTerms {
