@@ -350,12 +350,25 @@ fd_status fd_state_plan_vjp_workspace(fd_state_plan p, size_t* bytes);
 fd_status fock_state_vjp(fd_state_plan p, const void* c, const void* psi, const void* dpsi, void* dA, void* db,
                          void* dc, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* fock_state_jvp -- forward mode of fock_state_fwd: the tangent dpsi of psi
+ * along a direction (dA: M x M, db: M, dc: 1) of the triple, from the same
+ * closed forms (the tangent recurrences of Sec. 2.5 solved: dpsi_k = dc/c
+ * psi_k + sum_i db_i sqrt(k_i) psi_{k-1_i} + sum_{i,l} dA_il 1/2
+ * sqrt(k_i (k_l - [i = l])) psi_{k-1_i-1_l}; A enters as its symmetric part,
+ * so only the symmetric part of dA matters).  One pass over the box, no
+ * workspace; psi and c as for fock_state_vjp, dpsi in psi's layout.  With
+ * fock_state_vjp it satisfies <g, J t> = <J^H g, t>.  Errors as
+ * fock_state_fwd. */
+fd_status fock_state_jvp(fd_state_plan p, const void* c, const void* psi, const void* dA, const void* db,
+                         const void* dc, void* dpsi, hipStream_t stream);
+
 /* As fd_device_status, for a state plan. */
 fd_status fd_state_device_status(fd_state_plan p, hipStream_t stream);
 /* As fd_plan_timing / fd_plan_kernel_times; kinds FD_K_PREP (A, b, c
  * staging), FD_K_FWD_LEVEL (one launch per computed level), FD_K_OUT_PERM,
  * FD_K_VJP_LEVEL (the cotangent dot products of fock_state_vjp, all their
- * launches as one record) and FD_K_VJP_FINAL. */
+ * launches as one record), FD_K_VJP_FINAL, and FD_K_FWD_LEVEL for the one
+ * launch of fock_state_jvp. */
 fd_status fd_state_plan_timing(fd_state_plan p, uint32_t kind_mask);
 fd_status fd_state_plan_kernel_times(fd_state_plan p, int kind, int64_t* launches, double* total_ms);
 

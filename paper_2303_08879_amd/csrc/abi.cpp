@@ -540,6 +540,19 @@ fd_status fock_state_vjp(fd_state_plan sp, const void* c, const void* psi, const
   return ok();
 }
 
+fd_status fock_state_jvp(fd_state_plan sp, const void* c, const void* psi, const void* dA, const void* db,
+                         const void* dc, void* dpsi, hipStream_t stream) {
+  if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = sp->inner->P;
+  fd_status s = check_ptrs(P, {c, psi, dA, db, dc, dpsi});
+  if (s != FD_OK) return s;
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  if (fd::run_state_jvp(P, c, psi, dA, db, dc, dpsi, stream) != hipSuccess)
+    return fail(FD_ERR_HIP, "kernel launch failed");
+  return ok();
+}
+
 fd_status fd_state_device_status(fd_state_plan sp, hipStream_t stream) {
   if (!sp) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
   return fd_device_status(sp->inner, stream);

@@ -269,6 +269,8 @@ size_t state_ws_bytes(const Plan& P);
 hipError_t run_state_fwd(const Plan& P, bool b_zero, const void* A, const void* b, const void* c, void* psi, void* ws,
                          hipStream_t st);
 size_t state_vjp_ws_bytes(const Plan& P);
+hipError_t run_state_jvp(const Plan& P, const void* c, const void* psi, const void* dA, const void* db, const void* dc,
+                         void* dpsi, hipStream_t st);
 hipError_t run_state_vjp(const Plan& P, const void* c, const void* psi, const void* g, void* dA, void* db, void* dc,
                          void* ws, hipStream_t st);
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,

@@ -277,6 +277,98 @@ __global__ __launch_bounds__(kThreads) void k_state_vjp_final(StateVjpMap m, con
   }
 }
 
+// Forward mode: the tangent of psi along (dA, db, dc), from the same closed
+// forms, one thread per amplitude:
+//   dpsi_k = (dc / c) psi_k + sum_i db_i sqrt(k_i) psi_{k-1_i}
+//          + sum_{i <= l} S_il w_il(k) psi_{k-1_i-1_l},
+// S_il = dA_il + dA_li (i < l), dA_ii (i = l), w_il = 1/2 sqrt(k_i k_l) or
+// 1/2 sqrt(k_i (k_i - 1)): the directional derivative for the symmetric part
+// of dA, as A enters through (A + A^T)/2.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_state_jvp(DevPlan P, StateModes sm, int M, const cx<R>* __restrict__ psi,
+                                                        const cx<R>* __restrict__ c, const cx<R>* __restrict__ tA,
+                                                        const cx<R>* __restrict__ tb, const cx<R>* __restrict__ tc,
+                                                        int total, cx<R>* __restrict__ dpsi) {
+  __shared__ double2 sS[kMaxD * kMaxD];
+  __shared__ double2 sB[kMaxD];
+  const int MD = P.MD;
+  for (int e = threadIdx.x; e < MD * MD; e += blockDim.x) {
+    const int i = e / MD, l = e % MD;
+    const cx<R> a = ld(tA + (size_t)sm.mode[i] * M + sm.mode[l]);
+    const cx<R> t = ld(tA + (size_t)sm.mode[l] * M + sm.mode[i]);
+    sS[e] = i == l ? make_double2(a.x, a.y) : make_double2((double)a.x + t.x, (double)a.y + t.y);
+  }
+  for (int i = threadIdx.x; i < MD; i += blockDim.x) {
+    const cx<R> v = ld(tb + sm.mode[i]);
+    sB[i] = make_double2(v.x, v.y);
+  }
+  __syncthreads();
+  // dc / c
+  const cx<R> cv = ld(c), dv = ld(tc);
+  const double n2 = (double)cv.x * cv.x + (double)cv.y * cv.y;
+  const double rx = ((double)dv.x * cv.x + (double)dv.y * cv.y) / n2, ry = ((double)dv.y * cv.x - (double)dv.x * cv.y) / n2;
+  int stride[kMaxD];
+  {
+    int s = 1;
+    for (int d = MD - 1; d >= 0; --d) {
+      stride[d] = s;
+      s *= P.CD[d];
+    }
+  }
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+    int k[kMaxD];
+    int rem = x;
+    for (int d = MD - 1; d >= 0; --d) {
+      const int q = (int)((rem + 0.5) * P.cinv[d]);
+      k[d] = rem - q * P.CD[d];
+      rem = q;
+    }
+    const cx<R> p0 = ld(psi + x);
+    double ax = rx * p0.x - ry * p0.y, ay = rx * p0.y + ry * p0.x;
+    for (int i = 0; i < MD; ++i) {
+      if (k[i] < 1) continue;
+      const cx<R> p1 = ld(psi + x - stride[i]);
+      const double w = sqrt((double)k[i]);
+      const double2 t = sB[i];
+      ax += w * (t.x * p1.x - t.y * p1.y);
+      ay += w * (t.x * p1.y + t.y * p1.x);
+      for (int l = i; l < MD; ++l) {
+        const int kl = k[l] - (l == i ? 1 : 0);
+        if (kl < 1) continue;
+        const cx<R> p2 = ld(psi + x - stride[i] - stride[l]);
+        const double w2 = 0.5 * sqrt((double)k[i] * (double)kl);
+        const double2 S = sS[i * MD + l];
+        ax += w2 * (S.x * p2.x - S.y * p2.y);
+        ay += w2 * (S.x * p2.y + S.y * p2.x);
+      }
+    }
+    st(dpsi + x, cmake<R>((R)ax, (R)ay));
+  }
+}
+
+hipError_t run_state_jvp(const Plan& Pl, const void* c, const void* psi, const void* dA, const void* db, const void* dc,
+                         void* dpsi, hipStream_t st) {
+  StateModes sm;
+  std::memset(&sm, 0, sizeof(sm));
+  sm.MD = Pl.MD;
+  for (int k = 0; k < Pl.MD; ++k) sm.mode[k] = Pl.dmodes[k];
+  const DevPlan P = make_devplan(Pl, true);
+  const int total = (int)Pl.nodes_total;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kThreads - 1) / kThreads, 65536));
+  KTimer kt(Pl, KK_FWD_LEVEL, st);
+  if (Pl.dt == FD_C64)
+    hipLaunchKernelGGL((k_state_jvp<float>), dim3(grid), dim3(kThreads), 0, st, P, sm, Pl.M,
+                       static_cast<const cx<float>*>(psi), static_cast<const cx<float>*>(c),
+                       static_cast<const cx<float>*>(dA), static_cast<const cx<float>*>(db),
+                       static_cast<const cx<float>*>(dc), total, static_cast<cx<float>*>(dpsi));
+  else
+    hipLaunchKernelGGL((k_state_jvp<double>), dim3(grid), dim3(kThreads), 0, st, P, sm, Pl.M,
+                       static_cast<const cx<double>*>(psi), static_cast<const cx<double>*>(c),
+                       static_cast<const cx<double>*>(dA), static_cast<const cx<double>*>(db),
+                       static_cast<const cx<double>*>(dc), total, static_cast<cx<double>*>(dpsi));
+  return hipGetLastError();
+}
+
 size_t state_vjp_ws_bytes(const Plan& Pl) {
   const int ncol = Pl.MD + Pl.MD * (Pl.MD + 1) / 2 + 1;
   return (size_t)kVjpSlots * ncol * sizeof(double2);

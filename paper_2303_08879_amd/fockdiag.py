@@ -28,7 +28,7 @@ EXPORTS = [
     "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
     "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
-    "fock_state_vjp",
+    "fock_state_vjp", "fock_state_jvp",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -88,6 +88,7 @@ def lib():
     L.fd_state_plan_destroy.argtypes = [vp]
     L.fd_state_plan_vjp_workspace.argtypes = [vp, ctypes.POINTER(sz)]
     L.fock_state_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.fock_state_jvp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.fd_state_plan_workspace.argtypes = [vp, ctypes.POINTER(sz)]
     L.fock_state_fwd.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.fd_state_device_status.argtypes = [vp, vp]
@@ -219,6 +220,11 @@ def fock_state_fwd(plan, A, b, c, psi, workspace, stream=None):
 def fock_state_vjp(plan, c, psi, dpsi, dA, db, dc, workspace, stream=None):
     _check(lib().fock_state_vjp(plan.handle, _ptr(c), _ptr(psi), _ptr(dpsi), _ptr(dA), _ptr(db), _ptr(dc),
                                 _ptr(workspace), _nbytes(workspace), _stream(stream)))
+
+
+def fock_state_jvp(plan, c, psi, dA, db, dc, dpsi, stream=None):
+    _check(lib().fock_state_jvp(plan.handle, _ptr(c), _ptr(psi), _ptr(dA), _ptr(db), _ptr(dc), _ptr(dpsi),
+                                _stream(stream)))
 
 
 def fd_state_device_status(plan, stream=None):

@@ -187,3 +187,51 @@ def test_state_vector_autograd():
     ref = O.adjoint_closed_form(ci.A, ci.b, ci.c, O.state_vector(ci.A, ci.b, ci.c, ci.cutoffs), w)
     got = (A.grad.cpu().numpy(), b.grad.cpu().numpy(), complex(c.grad.cpu().numpy()[0]))
     assert grad_err(got, ref) <= TOL
+
+
+def gpu_state_jvp(A, b, c, cut, tA, tb, tc, dtype=torch.complex128):
+    print(f"[gpu] state jvp cut={cut} dtype={dtype}", flush=True)
+    plan = F.StatePlan(cut, dtype, "general")
+    dev = "cuda"
+    T = lambda x: torch.tensor(np.asarray(x), dtype=dtype, device=dev)
+    ct = T([c])
+    ws = torch.empty(plan.workspace(), dtype=torch.uint8, device=dev)
+    psi = torch.empty(cut, dtype=dtype, device=dev)
+    F.fock_state_fwd(plan, T(A), T(b), ct, psi, ws)
+    dpsi = torch.empty_like(psi)
+    F.fock_state_jvp(plan, ct, psi, T(tA), T(tb), T([tc]), dpsi)
+    torch.cuda.synchronize()
+    return dpsi.cpu().numpy()
+
+
+@pytest.mark.parametrize("cut", [[6], [5, 4], [4, 1, 3], [3, 3, 3, 3], [7, 2, 5], [3] * 6])
+def test_state_jvp_matches_tangent_recurrences(cut):
+    # reference: the paper's tangent recurrences (Sec. 2.5) walked by the
+    # oracle, along the symmetric part of the A direction
+    rng = np.random.default_rng(sum(cut) * 3 + len(cut))
+    M = len(cut)
+    A, b, c = rand_state(rng, M, False)
+    tA = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))   # any direction
+    tb = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    tc = complex(rng.standard_normal(), rng.standard_normal())
+    G, dB, dAr = O.tangent_recurrences(A, b, c, cut)
+    T = 0.5 * (tA + tA.T)
+    ref = tc / c * G + sum(tb[m] * dB[m] for m in range(M)) + sum(T[m, n] * dAr[m, n] for m in range(M)
+                                                                   for n in range(M))
+    got = gpu_state_jvp(A, b, c, cut, tA, tb, tc)
+    assert O.rel_err(got, ref) <= TOL
+
+
+def test_state_jvp_vjp_adjoint_identity():
+    rng = np.random.default_rng(99)
+    cut = [5, 6, 4]
+    A, b, c = rand_state(rng, 3, False)
+    tA = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    tb = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    tc = complex(rng.standard_normal(), rng.standard_normal())
+    g = rng.standard_normal(cut) + 1j * rng.standard_normal(cut)
+    jt = gpu_state_jvp(A, b, c, cut, tA, tb, tc)
+    dA, db, dc = gpu_state_vjp(A, b, c, cut, g)
+    lhs = np.sum(np.conj(g) * jt)
+    rhs = np.sum(tA * np.conj(dA)) + np.sum(tb * np.conj(db)) + tc * np.conj(dc)
+    assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(lhs))
