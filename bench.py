@@ -181,6 +181,7 @@ def level_counts(cutoffs):
 
 
 def state_leg(steps=20):
+    import numpy as np
     """The pure-state workload (8 squeezed modes through a Haar interferometer,
     no loss, b = 0, cutoff 8: the 8^8 amplitudes of psi), complex128.  Under
     b = 0 one launch per even level S computes level S from level S - 2 and
@@ -231,6 +232,19 @@ def state_leg(steps=20):
         F.fock_state_vjp(plan, c, psi, g, dA, db, dc, vws)
     torch.cuda.synchronize()
     sec_v = time.perf_counter() - t2
+    # forward mode along a seeded direction of the triple: one pass over the box
+    rng = np.random.default_rng(6)
+    tA = torch.tensor(rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)), dtype=dt, device=dev)
+    tb = torch.tensor(rng.standard_normal(8) + 1j * rng.standard_normal(8), dtype=dt, device=dev)
+    tc = torch.tensor([0.3 - 0.1j], dtype=dt, device=dev)
+    dpsi = torch.empty_like(psi)
+    F.fock_state_jvp(plan, c, psi, tA, tb, tc, dpsi)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(steps):
+        F.fock_state_jvp(plan, c, psi, tA, tb, tc, dpsi)
+    torch.cuda.synchronize()
+    sec_j = time.perf_counter() - t3
     N = level_counts(ci.cutoffs)
     smax = len(N) - 1
     terms = 8 + 8 * 9 // 2 + 1          # bbar, the upper triangle of Abar, cbar
@@ -256,7 +270,10 @@ def state_leg(steps=20):
                      "note": f"{passes} launches of up to 16 of the {terms} cotangent dot products (each reads "
                              "the cotangent and shifted amplitudes once: 32 B per amplitude) and the ordered "
                              "slot reduction",
-                     "algorithmic_GBs": round(passes * 32 * amps * steps / sec_v / 1e9, 1)})
+                     "algorithmic_GBs": round(passes * 32 * amps * steps / sec_v / 1e9, 1)},
+                jvp={"ms_per_call": 1e3 * sec_j / steps, "launches": 1,
+                     "note": "one pass: reads psi (and its shifted neighbours), writes the tangent: 32 B per amplitude",
+                     "algorithmic_GBs": round(32 * amps * steps / sec_j / 1e9, 1)})
 
 
 def total_leg(steps=20, N=16, eps=0.05):
