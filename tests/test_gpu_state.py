@@ -235,3 +235,15 @@ def test_state_jvp_vjp_adjoint_identity():
     lhs = np.sum(np.conj(g) * jt)
     rhs = np.sum(tA * np.conj(dA)) + np.sum(tb * np.conj(db)) + tc * np.conj(dc)
     assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(lhs))
+
+
+def test_state_jvp_c64():
+    rng = np.random.default_rng(15)
+    cut = [5, 4, 6]
+    A, b, c = rand_state(rng, 3, False)
+    tA = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    tb = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    tc = 0.2 + 0.1j
+    ref = gpu_state_jvp(A, b, c, cut, tA, tb, tc)
+    got = gpu_state_jvp(A, b, c, cut, tA, tb, tc, torch.complex64)
+    assert O.rel_err(got.astype(np.complex128), ref) <= 1e-5

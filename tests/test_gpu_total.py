@@ -116,3 +116,30 @@ def test_stopping_on_a_box_plan():
     S = np.add.outer(np.arange(10), np.arange(10))
     assert np.all(p[S >= levels] == 0)
     assert O.rel_err(p[S < levels], ref[S < levels]) <= TOL
+
+
+def test_total_cutoff_edges():
+    A, b, c = lossy(3, 3, alpha_var=0.1)
+    # N = 0: the vacuum only, p(0) = c
+    p, offs, _ = run_total(A, b, c, [5, 5, 5], 0)
+    assert offs == [0, 1] and len(p) == 1 and abs(p[0] - c) <= 1e-15 * abs(c)
+    # every mode with cutoff 1: one point whatever N
+    p, offs, _ = run_total(A, b, c, [1, 1, 1], 7)
+    assert len(p) == 1 and abs(p[0] - c) <= 1e-15 * abs(c)
+    # N above the box's top level: the whole box in level order
+    p, offs, _ = run_total(A, b, c, [3, 2, 3], 50)
+    ref, roffs = O.probs_total(A, b, c, [3, 2, 3], 50)
+    assert offs == roffs and O.rel_err(p, ref) <= TOL
+
+
+def test_total_cutoff_c64():
+    A, b, c = lossy(4, 4, alpha_var=0.1)
+    cut, N = [6, 6, 6, 6], 7
+    plan = F.Plan(cut, 0, torch.complex64, "general", total_cutoff=N)
+    T = lambda x: torch.tensor(np.asarray(x), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(plan.workspace(False)[0], dtype=torch.uint8, device="cuda")
+    out = torch.empty(plan.out_shape, dtype=torch.complex64, device="cuda")
+    F.detection_probs(plan, T(A), T(b), T([c]), out, ws)
+    torch.cuda.synchronize()
+    ref, _ = O.probs_total(A, b, c, cut, N)
+    assert O.rel_err(out.cpu().numpy().astype(np.complex128), ref) <= 1e-5
