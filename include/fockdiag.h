@@ -266,8 +266,9 @@ fd_status fd_device_status(fd_plan p, hipStream_t stream);
  * with the first mode slowest; FD_Q_OUT_ELEMS entries.  Per-mode cutoffs
  * still apply (pass total_cutoff + 1 for none).  Limits as fd_plan_create
  * except that the box product may exceed 2^31 (the points below the cutoff
- * may not).  fock_diag_vjp and the batched calls return FD_ERR_UNSUPPORTED
- * for these plans. */
+ * may not).  fock_diag_vjp takes the cotangent in the same level order (after
+ * fock_diag_fwd with `saved`); the batched forward returns
+ * FD_ERR_UNSUPPORTED for these plans. */
 fd_status fd_plan_create_total(int M, const int* cutoffs, int total_cutoff, fd_dtype dt, uint32_t flags,
                                fd_plan* out);
 

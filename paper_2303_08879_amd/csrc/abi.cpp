@@ -321,7 +321,7 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
                         size_t ws_bytes, hipStream_t stream) {
   if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
   fd::Plan& P = p->P;
-  if (P.level_cap >= 0) return fail(FD_ERR_UNSUPPORTED, "no reverse sweep for plans with a total photon cutoff");
+  if (P.level_cap >= 0 && P.B > 1) return fail(FD_ERR_UNSUPPORTED, "a total photon cutoff needs every mode detected");
   fd_status s = check_ptrs(P, {A, b, c, drho, dA, db, dc, workspace});
   if (s != FD_OK) return s;
   if (!aligned(workspace, 256) || (saved && !aligned(saved, 256)))

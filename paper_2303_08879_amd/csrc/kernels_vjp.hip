@@ -38,6 +38,12 @@ struct VjpPtrs {
   int64_t priv_stride;          // entries per slot
 };
 
+template <typename R>
+__global__ void k_zero_cx(cx<R>* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    st(p + i, czero<R>());
+}
+
 __global__ void k_zero_d2(double2* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = make_double2(0.0, 0.0);
@@ -254,7 +260,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 #pragma unroll
       for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
       if (valid) {
-        h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
+        // (no level above the last one under a total photon cutoff)
+        if (V.gf0nxt) h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
         if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(at32(V.gcur[fam_f2(MD, K)], (uint32_t)r)), isq[m[K] + 2]);
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
@@ -949,7 +956,13 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   }
   DevPlan P = make_devplan(Pl, odd);
   cx<R>* g0 = reinterpret_cast<cx<R>*>(ws + V.g0);
-  {
+  if (Pl.level_cap >= 0) {
+    // a total photon cutoff: the cotangent already comes in level (node) order
+    KTimer kt(Pl, KK_PERM_IN, st);
+    if ((e = hipMemcpyAsync(g0, drho, (size_t)Pl.nodes_total * sizeof(cx<R>), hipMemcpyDeviceToDevice, st)) !=
+        hipSuccess)
+      return e;
+  } else {
     const int64_t total = Pl.out_elems;
     const int64_t tiles = ((Pl.nodes_total + kOutTN - 1) / kOutTN) * ((Pl.B + kOutTK - 1) / kOutTK);
     const int64_t grid = std::min<int64_t>(Pl.B > 1 ? tiles : (total + kThreads - 1) / kThreads, 65536);
@@ -962,6 +975,18 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int MD = Pl.MD;
+  if (Pl.level_cap >= 0 && MD > 0) {
+    // under a total photon cutoff the families of the last level feed no
+    // target: their cotangents (read by that level's pivots) start at zero
+    for (int f = 1; f < Pl.nfam; ++f) {
+      if (V.gfam[f] == 0) continue;
+      const int g = Pl.fam_group[f];
+      const int64_t n = Pl.maxN[g] * Pl.B;
+      hipLaunchKernelGGL((k_zero_cx<R>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                         gptr<R>(Pl, ws, V.gfam[f], g, Pl.smax), n);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   const size_t tab = 2 * (kMaxCut + 4) * sizeof(R) + (size_t)(MD + 1) * (Pl.smax + 3) * sizeof(int);
   for (int S = Pl.smax; S >= 0 && MD > 0; --S) {
     VjpPtrs<R> Vp;
@@ -974,7 +999,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       Vp.gprev[f] = gptr<R>(Pl, ws, V.gfam[f], g, S - 1);
       Vp.gcur[f] = gptr<R>(Pl, ws, V.gfam[f], g, S);
     }
-    Vp.gf0nxt = gptr<R>(Pl, ws, V.gfam[0], 0, S + 1);
+    Vp.gf0nxt = (Pl.level_cap >= 0 && S == Pl.smax) ? nullptr : gptr<R>(Pl, ws, V.gfam[0], 0, S + 1);
     Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
                                               (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
     Vp.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;

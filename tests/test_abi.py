@@ -219,9 +219,7 @@ def test_total_cutoff_plan_counts_and_offsets():
     # a box product beyond 2^31 is fine below a total cutoff
     big = F.Plan([64] * 8, 0, total_cutoff=10)
     assert big.query(F.FD_Q_OUT_ELEMS) == math.comb(18, 8)
-    # no reverse sweep, no batches for these plans (host-side refusals)
-    assert L.fock_diag_vjp(p.handle, 16, 16, 16, None, 0, 16, 16, 16, 16, 256, 1 << 20, None) == \
-        F.FD_ERR_UNSUPPORTED
+    # host-side argument checks of the stopping call
     assert L.detection_probs_until(p.handle, 16, 16, 16, 16, 1.5, ctypes.byref(ctypes.c_int()),
                                    ctypes.byref(ctypes.c_double()), 256, 1 << 20, None) == F.FD_ERR_INVALID_ARG
     assert L.detection_probs_until(p.handle, 16, 16, 16, 16, 1e-3, None, None, 256, 1 << 20, None) == \

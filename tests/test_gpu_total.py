@@ -143,3 +143,35 @@ def test_total_cutoff_c64():
     torch.cuda.synchronize()
     ref, _ = O.probs_total(A, b, c, cut, N)
     assert O.rel_err(out.cpu().numpy().astype(np.complex128), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("cut,N", [([6, 5, 7], 5), ([4, 4, 4], 20), ([5, 1, 4, 3], 4), ([3, 3, 3, 3, 3], 6)])
+def test_total_cutoff_vjp(cut, N):
+    # gradient of sum_k conj(g_k) p(n_k) over the points below the cutoff; the
+    # oracle differentiates the box of per-mode cutoffs min(C_j, N + 1) with
+    # the cotangent placed on those points (zero elsewhere)
+    print(f"[gpu] total vjp cut={cut} N={N}", flush=True)
+    A, b, c = lossy(len(cut) * 5 + N, len(cut), alpha_var=0.1)
+    dt, dev = torch.complex128, "cuda"
+    plan = F.Plan(cut, 0, dt, "general", total_cutoff=N)
+    wb, sb = plan.workspace(True)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    sv = torch.empty(sb, dtype=torch.uint8, device=dev)
+    T = lambda x: torch.tensor(np.asarray(x), dtype=dt, device=dev)
+    At, bt, ct = T(A), T(b), T([c])
+    out = torch.empty(plan.out_shape, dtype=dt, device=dev)
+    F.fock_diag_fwd(plan, At, bt, ct, out, ws, sv)
+    rng = np.random.default_rng(N)
+    g = rng.standard_normal(out.shape[0]) + 1j * rng.standard_normal(out.shape[0])
+    dA, db, dc = torch.empty_like(At), torch.empty_like(bt), torch.empty_like(ct)
+    F.fock_diag_vjp(plan, At, bt, ct, sv, T(g), dA, db, dc, ws)
+    torch.cuda.synchronize()
+    dims = [min(C, N + 1) for C in cut]
+    pts, _ = O.level_points(cut, N)
+    gbox = np.zeros(dims, dtype=np.complex128)
+    for k, n in enumerate(pts):
+        gbox[n] = g[k]
+    rA, rb, rc = O.fock_diag_vjp(A, b, c, dims, (1 << len(cut)) - 1, gbox)
+    got = np.concatenate([dA.cpu().numpy().ravel(), db.cpu().numpy().ravel(), dc.cpu().numpy().ravel()])
+    ref = np.concatenate([np.asarray(rA).ravel(), np.asarray(rb).ravel(), [rc]])
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL
