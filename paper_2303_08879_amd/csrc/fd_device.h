@@ -116,6 +116,11 @@ __device__ __forceinline__ void wave_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Compiler-only barrier: memory accesses are not moved across it, so the
+// compiler cannot overlap consecutive loop iterations whose live values would
+// otherwise push the register count past an occupancy step.
+__device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
 // Coordinate q of an undetected-block entry: floor(rem / ustride[q]) for
 // 0 <= rem < 4096 without an integer division.  (rem + 1/2) / ustride lies at
 // least 1 / (2 ustride) >= 2^-13 away from an integer, while one double

@@ -267,6 +267,11 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
                                                cx<R>* lf0, cx<R>* lpk) {
   constexpr int NPD = 2 * MD;
   constexpr int NPOS = NQ + NPD;
+  // Fences between loop iterations for the shapes whose unfenced build needs
+  // more than 168 VGPRs (two waves per SIMD): there they lift occupancy by one
+  // or two waves.  Where the unfenced unit already runs three waves, the
+  // overlap of iterations is worth more than a fourth wave.
+  constexpr bool kFence = MD >= 4 || (MD >= 3 && NQ >= 4);
   const int B = P.B, R0 = G.R0;
   const int lane = threadIdx.x & 63;
   const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
@@ -337,6 +342,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
             if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
           }
         }
+        if constexpr (kFence) compiler_fence();
       }
     }
     wave_sync();
@@ -400,7 +406,9 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           for (int l = 2 * K; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
           st(dst, cscale(acc, scale));
         }
+        if constexpr (kFence) compiler_fence();
       }
+      if constexpr (kFence) compiler_fence();
     }
     wave_sync();
   }
