@@ -55,6 +55,26 @@ def test_small_random_triples(M, cut, mask, bz):
         assert O.rel_err(out, ref) <= TOL, b_mode
 
 
+# block shapes with four or more detected modes, or three with two undetected
+# modes: the forward block unit fences its row and bridge iterations there;
+# undetected cutoffs large enough for several row chunks
+FENCED = [
+    (5, [9, 4, 3, 3, 3], 0b11110), (6, [8, 3, 3, 2, 3, 3], 0b111110), (5, [5, 5, 4, 3, 3], 0b11100),
+    (6, [4, 4, 3, 3, 2, 3], 0b111100), (7, [5, 2, 2, 3, 2, 2, 3], 0b1111110),
+]
+
+
+@pytest.mark.parametrize("M,cut,mask", FENCED)
+@pytest.mark.parametrize("bz", [True, False])
+def test_fenced_block_shapes(M, cut, mask, bz):
+    rng = np.random.default_rng(2000 + M * 31 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.2)
+    ref = O.fock_diag(A, b, c, cut, mask)
+    for b_mode in (["auto", "zero"] if bz else ["general"]):
+        out = gpu(A, b, c, cut, mask, b_mode=b_mode)
+        assert O.rel_err(out, ref) <= TOL, b_mode
+
+
 def test_ragged_multi_tile_levels():
     # levels wider than one 256-thread tile, ragged tails, unequal cutoffs
     rng = np.random.default_rng(7)
