@@ -32,7 +32,8 @@ This module writes that definition out in the most direct way:
   hafnians: a different algorithm, used to pin Tier A.
 * ``adjoint_closed_form`` differentiates the generating function directly;
   ``tangent_recurrences`` runs the paper's forward-mode recurrences
-  (Eqs. recrel_dB and recrel_dA, Sec. 2.5) as a cross-check.
+  (Eqs. recrel_dB and recrel_dA, Sec. 2.5) as a cross-check;
+  ``fock_diag_jvp`` sums them along one direction (forward mode of rho).
 
 Index convention: a density-matrix index is interleaved per mode,
 [ket_1, bra_1, ket_2, bra_2, ...] (Sec. 2.1: each pair of consecutive indices
@@ -64,6 +65,7 @@ __all__ = [
     "adjoint_closed_form",
     "fock_diag_vjp",
     "tangent_recurrences",
+    "fock_diag_jvp",
     "rel_err",
 ]
 
@@ -451,6 +453,22 @@ def tangent_recurrences(Ai, bi, c, dims):
             sB[:, k + 1] = newB / s
             sA[:, :, k + 1] = newA / s
     return G, dB, dA
+
+
+def fock_diag_jvp(A, b, c, cutoffs, detected_mask: int, dA, db, dc):
+    """(rho, drho): rho[k_U, l_U, n_D] and its derivative along the direction
+    (dA, db, dc), from the paper's tangent recurrences (Sec. 2.5) over the full
+    interleaved box.  A enters through (A + A^T) / 2 and so does dA; G is
+    proportional to c, so its c-tangent is G dc / c.  Small boxes only: the
+    recurrences carry D + D^2 tangents of every entry."""
+    A, dA = np.asarray(A, dtype=np.complex128), np.asarray(dA, dtype=np.complex128)
+    Ai, bi = to_interleaved(0.5 * (A + A.T), b)
+    dAi, dbi = to_interleaved(0.5 * (dA + dA.T), db)
+    dims = [C for C in cutoffs for _ in range(2)]
+    G, dGb, dGA = tangent_recurrences(Ai, bi, c, dims)
+    dG = (np.tensordot(dbi, dGb, axes=(0, 0)) + np.tensordot(dAi, dGA, axes=([0, 1], [0, 1]))
+          + G * (complex(dc) / complex(c)))
+    return select_outputs(G, detected_mask), select_outputs(dG, detected_mask)
 
 
 # --------------------------------------------------------------------------

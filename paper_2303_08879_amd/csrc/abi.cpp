@@ -316,6 +316,31 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
   return fock_diag_fwd(p, A, b, c, probs, workspace, ws_bytes, nullptr, 0, stream);
 }
 
+fd_status fd_plan_jvp_workspace(fd_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(FD_ERR_INVALID_ARG, "NULL argument");
+  *bytes = 2 * fd::jvp_half_bytes(p->P);
+  return ok();
+}
+
+fd_status fock_diag_jvp(fd_plan p, const void* A, const void* b, const void* c, const void* dA, const void* db,
+                        const void* dc, void* rho, void* drho, void* workspace, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  fd_status s = check_ptrs(P, {A, b, c, dA, db, dc, rho, drho, workspace});
+  if (s != FD_OK) return s;
+  if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (P.B != 1) return fail(FD_ERR_UNSUPPORTED, "forward mode covers plans whose modes are all detected");
+  if (P.flags == FD_B_ZERO)
+    return fail(FD_ERR_UNSUPPORTED, "forward mode needs the odd levels: create the plan with FD_B_AUTO or FD_B_GENERAL");
+  if (ws_bytes < 2 * fd::jvp_half_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
+  std::string err;
+  if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
+  const hipError_t e = fd::run_jvp(P, A, b, c, dA, db, dc, rho, drho, workspace, stream);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return ok();
+}
+
 fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, const void* saved,
                         size_t saved_bytes, const void* drho, void* dA, void* db, void* dc, void* workspace,
                         size_t ws_bytes, hipStream_t stream) {

@@ -253,6 +253,11 @@ struct StopRule {
   int levels_done = 0;   // out: S* + 1 (smax + 1 if the sum never reaches 1 - eps)
   double mass = 0.0;     // out: sum of the returned levels' masses
 };
+// Forward mode (all modes detected): rho and its tangent along (dA, db, dc).
+// The workspace holds two halves of jvp_half_bytes each: values, then tangents.
+size_t jvp_half_bytes(const Plan& P);
+hipError_t run_jvp(const Plan& P, const void* A, const void* b, const void* c, const void* dA, const void* db,
+                   const void* dc, void* rho, void* drho, void* ws, hipStream_t st);
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
                        void* saved, hipStream_t st, StopRule* stop = nullptr);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels

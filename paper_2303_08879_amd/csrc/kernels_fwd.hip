@@ -3,6 +3,7 @@
 // The per-point and per-(node, chunk) work lives in fwd_units.h.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "fwd_units.h"
 
@@ -380,6 +381,228 @@ hipError_t run_forward(const Plan& Pl, bool odd, const void* A, const void* b, c
   if (Pl.dt == FD_C64)
     return run_forward_t<float>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st, stop);
   return run_forward_t<double>(Pl, odd, A, b, c, rho, (char*)ws, (char*)saved, st, stop);
+}
+
+
+// ---------------------------------------------------------------------------
+// Forward mode of Algorithm 1 (the tangent recurrences of Sec. 2.5, summed
+// along one direction (dA, db, dc)): differentiating Eq. recrel gives, for a
+// pivot p and write direction i,
+//   sqrt(p_i + 1) dG_{p+1_i} = db_i G_p + b_i dG_p
+//                              + sum_l sqrt(p_l) (dA_il G_{p-1_l} + A_il dG_{p-1_l}),
+// with dG_0 = dc.  The tangents need exactly the reads and writes of the
+// values, so every kept amplitude gets its tangent in a second workspace of
+// the same layout, dT bytes further on, and one thread carries both.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T* tangent_of(T* p, int64_t dT) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + dT);
+}
+
+template <int MD, typename R>
+__global__ __launch_bounds__(kThreads) void k_fwd_point_jvp(DevPlan P, LevelPtrs<R> L, int64_t dT,
+                                                            const cx<R>* __restrict__ Ai, const cx<R>* __restrict__ bi,
+                                                            const cx<R>* __restrict__ dAi,
+                                                            const cx<R>* __restrict__ dbi, int S, int nwork) {
+  constexpr int NP = 2 * MD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* sq = reinterpret_cast<R*>(smem_raw);
+  R* isq = sq + (kMaxCut + 4);
+  int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+  load_tables(P, spn, sq, isq);
+  __syncthreads();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nwork) return;
+  int m[MD], s[MD + 1], rdn[MD], rup[MD];
+  unrank<MD>(spn, P.pnw, P.CD, S, r, m, s);
+  neighbour_ranks<MD>(spn, P.pnw, s, rdn, rup);
+  // value and tangent of a family entry
+  auto rd2 = [&](int f, int idx, R w, cx<R>& v, cx<R>& t) {
+    v = cscale(ld(at32(L.rd[f], (uint32_t)idx)), w);
+    t = cscale(ld(at32(tangent_of(L.rd[f], dT), (uint32_t)idx)), w);
+  };
+  auto wr2 = [&](cx<R>* dst, const cx<R>& v, const cx<R>& t) {
+    st(dst, v);
+    st(tangent_of(dst, dT), t);
+  };
+  const cx<R> g0 = ld(at32(L.f0cur, (uint32_t)r));
+  const cx<R> t0 = ld(at32(tangent_of(L.f0cur, dT), (uint32_t)r));
+  cx<R> yk[MD], tyk[MD];
+#pragma unroll
+  for (int K = 0; K < MD; ++K) yk[K] = tyk[K] = czero<R>();
+
+  if (m[0] <= P.CD[0] - 2) {
+    // diagonal pivot d(m): reads d(m) - 1_l (type-1 families one level down)
+    cx<R> x[NP], tx[NP];
+#pragma unroll
+    for (int j = 0; j < MD; ++j) {
+      if (m[j] > 0) {
+        rd2(fam_f1b(MD, j), rdn[j], sq[m[j]], x[2 * j], tx[2 * j]);
+        rd2(fam_f1k(j), rdn[j], sq[m[j]], x[2 * j + 1], tx[2 * j + 1]);
+      } else {
+        x[2 * j] = x[2 * j + 1] = tx[2 * j] = tx[2 * j + 1] = czero<R>();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < MD; ++j) {
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int i = 2 * j + side;
+        const cx<R> bv = ld(bi + i), dbv = ld(dbi + i);
+        cx<R> acc = czero<R>(), tacc = czero<R>();
+        cfma(acc, bv, g0);
+        cfma(tacc, dbv, g0);
+        cfma(tacc, bv, t0);
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const cx<R> a = ld(Ai + i * NP + l), da = ld(dAi + i * NP + l);
+          cfma(acc, a, x[l]);
+          cfma(tacc, da, x[l]);
+          cfma(tacc, a, tx[l]);
+        }
+        acc = cscale(acc, isq[m[j] + 1]);
+        tacc = cscale(tacc, isq[m[j] + 1]);
+        if (side == 0) {
+          yk[j] = acc;
+          tyk[j] = tacc;
+          if (j == 0 || m[j] <= P.CD[j] - 2) wr2(at32(L.wr[fam_f1k(j)], (uint32_t)r), acc, tacc);
+        } else {
+          const bool ok = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
+          if (ok) wr2(at32(L.wr[fam_f1b(MD, j)], (uint32_t)r), acc, tacc);
+        }
+      }
+    }
+  }
+
+  int K0 = MD;
+#pragma unroll
+  for (int d = MD - 1; d >= 0; --d)
+    if (m[d] > 0) K0 = d;
+#pragma unroll
+  for (int K = 0; K < MD; ++K) {
+    if (K > K0) break;
+    if (m[K] > P.CD[K] - 2) continue;
+    // pivot d(m) + 1_ket(K): reads p - 1_l for l >= ket(K)
+    cx<R> x[NP], tx[NP];
+    x[2 * K] = cscale(g0, sq[m[K] + 1]);
+    tx[2 * K] = cscale(t0, sq[m[K] + 1]);
+    if (m[K] > 0)
+      rd2(fam_f2(MD, K), rdn[K], sq[m[K]], x[2 * K + 1], tx[2 * K + 1]);
+    else
+      x[2 * K + 1] = tx[2 * K + 1] = czero<R>();
+#pragma unroll
+    for (int j = K + 1; j < MD; ++j) {
+      if (m[j] > 0) {
+        rd2(fam_1001(MD, K, j), rdn[j], sq[m[j]], x[2 * j], tx[2 * j]);
+        rd2(fam_1010(MD, K, j), rdn[j], sq[m[j]], x[2 * j + 1], tx[2 * j + 1]);
+      } else {
+        x[2 * j] = x[2 * j + 1] = tx[2 * j] = tx[2 * j + 1] = czero<R>();
+      }
+    }
+#pragma unroll
+    for (int i = 2 * K; i < NP; ++i) {
+      const int j = i >> 1;
+      bool ok;
+      R scale;
+      cx<R>* dst;
+      if (i == 2 * K + 1) {                 // d(m + 1_K): the next level's F0
+        ok = L.f0nxt != nullptr;
+        scale = isq[m[K] + 1];
+        dst = ok ? at32(L.f0nxt, (uint32_t)rup[K]) : nullptr;
+      } else if (i == 2 * K) {              // F2(K)(m)
+        ok = (m[K] <= P.CD[K] - 3);
+        scale = isq[m[K] + 2];
+        dst = at32(L.wr[fam_f2(MD, K)], (uint32_t)r);
+      } else {                              // F1010(K,j)(m) / F1001(K,j)(m)
+        ok = (m[j] <= P.CD[j] - 2);
+        scale = isq[m[j] + 1];
+        dst = at32(L.wr[(i & 1) ? fam_1001(MD, K, j) : fam_1010(MD, K, j)], (uint32_t)r);
+      }
+      if (!ok) continue;
+      const cx<R> bv = ld(bi + i), dbv = ld(dbi + i);
+      cx<R> acc = czero<R>(), tacc = czero<R>();
+      cfma(acc, bv, yk[K]);
+      cfma(tacc, dbv, yk[K]);
+      cfma(tacc, bv, tyk[K]);
+#pragma unroll
+      for (int l = 2 * K; l < NP; ++l) {
+        const cx<R> a = ld(Ai + i * NP + l), da = ld(dAi + i * NP + l);
+        cfma(acc, a, x[l]);
+        cfma(tacc, da, x[l]);
+        cfma(tacc, a, tx[l]);
+      }
+      wr2(dst, cscale(acc, scale), cscale(tacc, scale));
+    }
+  }
+}
+
+template <typename R>
+static hipError_t run_jvp_t(const Plan& Pl, const void* A, const void* b, const void* c, const void* dA,
+                            const void* db, const void* dc, void* rho, void* drho, char* ws, int64_t half,
+                            hipStream_t st) {
+  const FwdLayout Lw = fwd_layout(Pl, true, false, 0);
+  char* wt = ws + half;
+  cx<R>* Ai = reinterpret_cast<cx<R>*>(ws + Lw.prep);
+  cx<R>* bi = Ai + (size_t)Pl.npos * Pl.npos;
+  cx<R>* dAi = reinterpret_cast<cx<R>*>(wt + Lw.prep);
+  cx<R>* dbi = dAi + (size_t)Pl.npos * Pl.npos;
+  cx<R>* f0 = reinterpret_cast<cx<R>*>(ws + Lw.f0);
+  cx<R>* tf0 = reinterpret_cast<cx<R>*>(wt + Lw.f0);
+  const DevPlan P = make_devplan(Pl, true);
+  hipError_t e;
+  {
+    KTimer kt(Pl, KK_PREP, st);
+    if ((e = launch_prep(Pl, A, b, c, Ai, f0, st)) != hipSuccess) return e;
+    if ((e = launch_prep(Pl, dA, db, dc, dAi, tf0, st)) != hipSuccess) return e;
+  }
+  const size_t tab = 2 * (kMaxCut + 4) * sizeof(R) + (size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int);
+  for (int S = 0; S <= Pl.smax && Pl.MD > 0; ++S) {
+    const int nwork = (int)Pl.ncnt[S];
+    if (nwork <= 0) continue;
+    LevelPtrs<R> L;
+    std::memset(&L, 0, sizeof(L));
+    for (int f = 1; f < Pl.nfam; ++f) {
+      if (Lw.fam[f] == 0) continue;
+      const int g = Pl.fam_group[f];
+      L.rd[f] = fam_level_ptr<R>(Pl, ws, Lw.fam[f], g, S - 1, true);
+      L.wr[f] = fam_level_ptr<R>(Pl, ws, Lw.fam[f], g, S, true);
+    }
+    L.f0cur = fam_level_ptr<R>(Pl, ws, Lw.f0, 0, S, false);
+    L.f0nxt = S < Pl.smax ? fam_level_ptr<R>(Pl, ws, Lw.f0, 0, S + 1, false) : nullptr;
+    const int grid = (nwork + kThreads - 1) / kThreads;
+    KTimer kt(Pl, KK_FWD_LEVEL, st);
+#define FD_LAUNCH_JVP(MDV)                                                                                        \
+  case MDV:                                                                                                       \
+    hipLaunchKernelGGL((k_fwd_point_jvp<MDV, R>), dim3(grid), dim3(kThreads), tab, st, P, L, half, Ai, bi, dAi,  \
+                       dbi, S, nwork);                                                                            \
+    break;
+    switch (Pl.MD) {
+      FD_LAUNCH_JVP(1)
+      FD_LAUNCH_JVP(2)
+      FD_LAUNCH_JVP(3)
+      FD_LAUNCH_JVP(4)
+      FD_LAUNCH_JVP(5)
+      FD_LAUNCH_JVP(6)
+      FD_LAUNCH_JVP(7)
+      FD_LAUNCH_JVP(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef FD_LAUNCH_JVP
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = launch_out_perm_t<R>(Pl, P, f0, rho, st)) != hipSuccess) return e;
+  return launch_out_perm_t<R>(Pl, P, tf0, drho, st);
+}
+
+size_t jvp_half_bytes(const Plan& Pl) { return (fwd_layout(Pl, true, false, 0).total + 255) / 256 * 256; }
+
+hipError_t run_jvp(const Plan& Pl, const void* A, const void* b, const void* c, const void* dA, const void* db,
+                   const void* dc, void* rho, void* drho, void* ws, hipStream_t st) {
+  const int64_t half = (int64_t)jvp_half_bytes(Pl);
+  if (Pl.dt == FD_C64) return run_jvp_t<float>(Pl, A, b, c, dA, db, dc, rho, drho, (char*)ws, half, st);
+  return run_jvp_t<double>(Pl, A, b, c, dA, db, dc, rho, drho, (char*)ws, half, st);
 }
 
 }  // namespace fd

@@ -28,7 +28,7 @@ EXPORTS = [
     "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
     "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
-    "fock_state_vjp", "fock_state_jvp",
+    "fock_state_vjp", "fock_state_jvp", "fd_plan_jvp_workspace", "fock_diag_jvp",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -84,6 +84,8 @@ def lib():
     L.fd_plan_level_offsets.argtypes = [vp, i64p, i32]
     L.detection_probs_until.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    L.fd_plan_jvp_workspace.argtypes = [vp, ctypes.POINTER(sz)]
+    L.fock_diag_jvp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.fd_state_plan_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, u32, ctypes.POINTER(vp)]
     L.fd_state_plan_destroy.argtypes = [vp]
     L.fd_state_plan_vjp_workspace.argtypes = [vp, ctypes.POINTER(sz)]
@@ -170,6 +172,12 @@ class Plan:
         _check(lib().fd_plan_workspace(self.handle, int(bool(with_vjp)), ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
+    def jvp_workspace(self):
+        """Workspace bytes of fock_diag_jvp -- fd_plan_jvp_workspace."""
+        n = ctypes.c_size_t()
+        _check(lib().fd_plan_jvp_workspace(self.handle, ctypes.byref(n)))
+        return n.value
+
     def query(self, what):
         v = ctypes.c_int64()
         _check(lib().fd_plan_query(self.handle, int(what), ctypes.byref(v)))
@@ -244,6 +252,11 @@ def fd_state_plan_kernel_times(plan, kind):
 def fock_diag_fwd(plan, A, b, c, rho, workspace, saved=None, stream=None):
     _check(lib().fock_diag_fwd(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(rho), _ptr(workspace),
                                _nbytes(workspace), _ptr(saved), _nbytes(saved), _stream(stream)))
+
+
+def fock_diag_jvp(plan, A, b, c, dA, db, dc, rho, drho, workspace, stream=None):
+    _check(lib().fock_diag_jvp(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(dA), _ptr(db), _ptr(dc), _ptr(rho),
+                               _ptr(drho), _ptr(workspace), _nbytes(workspace), _stream(stream)))
 
 
 def detection_probs(plan, A, b, c, probs, workspace, stream=None):

@@ -171,6 +171,28 @@ def test_state_plan_host_checks():
     assert L.fd_state_plan_destroy(None) == F.FD_OK
 
 
+def test_density_jvp_host_checks():
+    # fock_diag_jvp: argument checks and unsupported plans are rejected on the
+    # host, before any device work
+    import torch
+    L = F.lib()
+    p = F.Plan([4, 3], 0b11, torch.complex128, "general")
+    half = (p.workspace(False)[0] + 255) // 256 * 256
+    assert p.jvp_workspace() == 2 * half
+    ws = p.jvp_workspace()
+    ptrs = [16] * 8
+    assert L.fock_diag_jvp(None, *ptrs, 256, ws, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_diag_jvp(p.handle, *ptrs[:7], None, 256, ws, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_diag_jvp(p.handle, *ptrs, 256 + 16, ws, None) == F.FD_ERR_INVALID_ARG
+    assert L.fock_diag_jvp(p.handle, *ptrs, 256, ws - 1, None) == F.FD_ERR_WORKSPACE
+    # the b = 0 schedule skips the odd levels a non-zero db reaches
+    pz = F.Plan([4, 3], 0b11, torch.complex128, "zero")
+    assert L.fock_diag_jvp(pz.handle, *ptrs, 256, 1 << 30, None) == F.FD_ERR_UNSUPPORTED
+    # an undetected mode (Algorithm 2) is not covered
+    pu = F.Plan([4, 3], 0b10, torch.complex128, "general")
+    assert L.fock_diag_jvp(pu.handle, *ptrs, 256, 1 << 30, None) == F.FD_ERR_UNSUPPORTED
+
+
 def test_exact_reciprocal_digit_split_of_cindex():
     # The permutations between C order and node order split a C-order index
     # x < 2^31 into digits with trunc((x + 0.5) * (1 / C)), C <= 64, in double

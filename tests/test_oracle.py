@@ -252,6 +252,37 @@ def test_adjoint_matches_paper_tangent_recurrences():
     np.testing.assert_allclose(cbar, np.sum(gbar * np.conj(G / c)), atol=1e-12)
 
 
+def test_jvp_against_finite_differences_of_the_box():
+    # forward mode of rho (tangent recurrences summed along a direction)
+    # against a central difference of the plain Taylor box; the direction
+    # need not be symmetric (A and dA enter through their symmetric parts)
+    rng = np.random.default_rng(31)
+    M, cut, mask = 2, [4, 3], 0b11
+    A = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    A = 0.15 * (A + A.T)
+    b = 0.3 * (rng.standard_normal(4) + 1j * rng.standard_normal(4))
+    c = 0.7 - 0.2j
+    dA = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    db = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    dc = 0.3 + 0.4j
+    rho, drho = O.fock_diag_jvp(A, b, c, cut, mask, dA, db, dc)
+    np.testing.assert_allclose(rho, O.fock_diag(A, b, c, cut, mask), atol=1e-15)
+    h = 1e-6
+    sym = lambda X: 0.5 * (X + X.T)
+    fp = O.fock_diag(sym(A + h * dA), b + h * db, c + h * dc, cut, mask)
+    fm = O.fock_diag(sym(A - h * dA), b - h * db, c - h * dc, cut, mask)
+    fd = (fp - fm) / (2 * h)
+    assert O.rel_err(drho, fd) <= 1e-8
+    # the derivative is linear in the direction, and along (0, 0, c) it is rho
+    _, d2 = O.fock_diag_jvp(A, b, c, cut, mask, 0 * dA, 0 * db, c)
+    np.testing.assert_allclose(d2, rho, atol=1e-15)
+    # with an undetected mode: the ket/bra block of mode 0 as well
+    rho_u, drho_u = O.fock_diag_jvp(A, b, c, cut, 0b10, dA, db, dc)
+    fpu = O.fock_diag(sym(A + h * dA), b + h * db, c + h * dc, cut, 0b10)
+    fmu = O.fock_diag(sym(A - h * dA), b - h * db, c - h * dc, cut, 0b10)
+    assert O.rel_err(drho_u, (fpu - fmu) / (2 * h)) <= 1e-8
+
+
 def test_vjp_finite_differences():
     circ = W.config1()
     cut, mask = [5, 5], 0b11
