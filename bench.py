@@ -316,6 +316,61 @@ def total_leg(steps=20, N=16, eps=0.05):
                 stopping={"eps": eps, "levels_done": levels, "mass": mass, "ms_per_call": 1e3 * sec_stop / steps})
 
 
+def jvp_leg(steps=10):
+    """Forward mode of rho on config 5 (8 modes, all detected, cutoff 8:
+    16.8M outputs; b = 0 at the base point, so the general schedule that a
+    non-zero db needs): rho and its tangent along a seeded direction in one
+    sweep, against the forward alone on the same schedule.  Both timed over
+    `steps` calls; the level kernels also with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+    ci = W.config5()
+    dt, dev = torch.complex128, "cuda"
+    plan = F.Plan(ci.cutoffs, ci.detected_mask, dt, "general")
+    T = lambda x: torch.tensor(np.asarray(x), dtype=dt, device=dev)
+    A, b, c = T(ci.A), T(ci.b), T([ci.c])
+    rng = np.random.default_rng(3)
+    D = 2 * ci.M
+    dA = T(rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D)))
+    db = T(rng.standard_normal(D) + 1j * rng.standard_normal(D))
+    dc = T([0.3 + 0.1j])
+    wj = torch.empty(plan.jvp_workspace(), dtype=torch.uint8, device=dev)
+    wf = torch.empty(plan.workspace(False)[0], dtype=torch.uint8, device=dev)
+    rho = torch.empty(plan.out_shape, dtype=dt, device=dev)
+    drho = torch.empty_like(rho)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        F.fd_plan_timing(plan, 1 << F.FD_K_FWD_LEVEL)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        n, ms = F.fd_plan_kernel_times(plan, F.FD_K_FWD_LEVEL)
+        F.fd_plan_timing(plan, 0)
+        return 1e3 * sec / steps, ms / steps, n // steps
+
+    ms_j, lvl_j, launches = timed(lambda: F.fock_diag_jvp(plan, A, b, c, dA, db, dc, rho, drho, wj))
+    ms_f, lvl_f, _ = timed(lambda: F.fock_diag_fwd(plan, A, b, c, rho, wf))
+    F.fd_device_status(plan)
+    n = plan.query(F.FD_Q_OUT_ELEMS)
+    # algorithmic bytes per computed amplitude: value and tangent each written
+    # once and read once by their reader (64 B; the forward alone 32 B)
+    t = plan.query(F.FD_Q_TARGETS)
+    gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
+    return dict(workload="config5: M=8 all detected C=8 (16.8M outputs), b=0 at the base point, general schedule, "
+                         "one seeded direction (dA, db, dc), complex128",
+                outputs=n, ms_per_call=ms_j, value=n * 1e3 / ms_j, unit="outputs (rho and drho)/s",
+                level_ms_per_call=lvl_j, level_launches=launches, forward_only_ms_per_call=ms_f,
+                forward_only_level_ms_per_call=lvl_f, cost_vs_forward=ms_j / ms_f,
+                level_GBs_algorithmic=gbs(64.0 * t, lvl_j), forward_level_GBs_algorithmic=gbs(32.0 * t, lvl_f))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +382,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
     ap.add_argument("--no-state", action="store_true", help="skip the pure-state (state vector) leg")
     ap.add_argument("--no-total", action="store_true", help="skip the total-photon-cutoff leg")
+    ap.add_argument("--no-jvp", action="store_true", help="skip the forward-mode (JVP) leg")
     ap.add_argument("--gradient-leg", action="store_true",
                     help="also time the 64-circuit gradient workload (forward + VJP per circuit)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -463,6 +519,8 @@ def main():
         line["state_vector"] = state_leg()
     if not args.no_total:
         line["total_cutoff"] = total_leg()
+    if not args.no_jvp:
+        line["density_jvp"] = jvp_leg()
     if args.gradient_leg:
         line["gradient_batch"] = gradient_leg()
     if not args.no_cpu_baseline:
