@@ -89,7 +89,10 @@ def state_vector(A, b, c, cutoffs, dtype=torch.complex128, b_mode="auto", device
 class FockDiagFunction(torch.autograd.Function):
     """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
     intermediate amplitudes (PyTorch's complex-gradient convention: the
-    incoming gradient g yields sum g conj(d rho / d x))."""
+    incoming gradient g yields sum g conj(d rho / d x)); forward-mode AD
+    (torch.func.jvp, torch.autograd.forward_ad) = fock_diag_jvp, for plans
+    whose modes are all detected (rho is holomorphic in A, b, c, so the
+    tangent is sum dx d rho / d x)."""
 
     @staticmethod
     def forward(ctx, A, b, c, cutoffs, detected_mask, b_mode):
@@ -105,7 +108,19 @@ class FockDiagFunction(torch.autograd.Function):
         ctx.saved_buf = saved
         ctx.c_shape = c.shape
         ctx.save_for_backward(A_, b_, c_)
+        ctx.save_for_forward(A_, b_, c_)
         return rho
+
+    @staticmethod
+    def jvp(ctx, dA, db, dc, *_):
+        A, b, c = ctx.saved_tensors
+        plan = ctx.plan
+        tan = lambda t, ref: torch.zeros_like(ref) if t is None else t.reshape(ref.shape).contiguous()
+        ws = _workspace(plan.jvp_workspace(), A.device)
+        rho = torch.empty(plan.out_shape, dtype=A.dtype, device=A.device)
+        drho = torch.empty_like(rho)
+        F.fock_diag_jvp(plan, A, b, c, tan(dA, A), tan(db, b), tan(dc, c), rho, drho, ws)
+        return drho
 
     @staticmethod
     def backward(ctx, grad_rho):

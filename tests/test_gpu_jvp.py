@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 from paper_2303_08879_amd import fockdiag as F
+from paper_2303_08879_amd import ops
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -139,3 +140,22 @@ def test_jvp_c64():
     rho, drho = gpu_jvp(A, b, c, dA, db, dc, cut, dtype=torch.complex64)
     assert O.rel_err(rho.astype(np.complex128), ref) <= 1e-5
     assert O.rel_err(drho.astype(np.complex128), dref) <= 1e-5
+
+
+def test_torch_forward_ad():
+    # torch.autograd.forward_ad through FockDiagFunction (fock_diag_jvp)
+    import torch.autograd.forward_ad as fwAD
+    rng = np.random.default_rng(21)
+    cut = [4, 3, 5]
+    A, b, c = rand_triple(rng, 3, False)
+    dA, db, dc = rand_dir(rng, 3)
+    ref, dref = O.fock_diag_jvp(A, b, c, cut, 0b111, dA, db, dc)
+    T = lambda x: torch.tensor(np.asarray(x), dtype=torch.complex128, device="cuda")
+    print("[gpu] forward_ad cut=[4, 3, 5]", flush=True)
+    with fwAD.dual_level():
+        rho = ops.fock_diag_ad(fwAD.make_dual(T(A), T(dA)), fwAD.make_dual(T(b), T(db)),
+                               fwAD.make_dual(T([c]), T([dc])), cut, 0b111, b_mode="general")
+        p, t = fwAD.unpack_dual(rho)
+        p, t = p.cpu().numpy(), t.cpu().numpy()
+    assert O.rel_err(p, ref) <= TOL
+    assert O.rel_err(t, dref) <= TOL
