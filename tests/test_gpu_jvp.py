@@ -159,3 +159,21 @@ def test_torch_forward_ad():
         p, t = p.cpu().numpy(), t.cpu().numpy()
     assert O.rel_err(p, ref) <= TOL
     assert O.rel_err(t, dref) <= TOL
+
+
+def test_jvp_edges():
+    rng = np.random.default_rng(33)
+    A, b, c = rand_triple(rng, 3, False)
+    dA, db, dc = rand_dir(rng, 3)
+    # every cutoff 1: no level to sweep, rho = c and drho = dc
+    rho, drho = gpu_jvp(A, b, c, dA, db, dc, [1, 1, 1])
+    assert rho.shape == (1, 1, 1) and abs(rho.item() - c) <= 1e-15 and abs(drho.item() - dc) <= 1e-15
+    # total photon cutoff 0: the vacuum only
+    rho, drho = gpu_jvp(A, b, c, dA, db, dc, [4, 4, 4], total=0)
+    assert rho.shape == (1,) and abs(rho[0] - c) <= 1e-15 and abs(drho[0] - dc) <= 1e-15
+    # the zero direction gives a zero tangent; a cutoff-1 mode among detected modes
+    rho, drho = gpu_jvp(A, b, c, 0 * dA, 0 * db, 0j, [4, 1, 5])
+    assert np.all(drho == 0)
+    ref, dref = O.fock_diag_jvp(A, b, c, [4, 1, 5], 0b111, dA, db, dc)
+    rho, drho = gpu_jvp(A, b, c, dA, db, dc, [4, 1, 5])
+    assert O.rel_err(rho, ref) <= TOL and O.rel_err(drho, dref) <= TOL
