@@ -89,8 +89,8 @@ def state_vector(A, b, c, cutoffs, dtype=torch.complex128, b_mode="auto", device
 class FockDiagFunction(torch.autograd.Function):
     """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
     intermediate amplitudes (PyTorch's complex-gradient convention: the
-    incoming gradient g yields sum g conj(d rho / d x)); forward-mode AD
-    (torch.func.jvp, torch.autograd.forward_ad) = fock_diag_jvp, for plans
+    incoming gradient g yields sum g conj(d rho / d x)); forward-mode AD with
+    dual tensors (torch.autograd.forward_ad) = fock_diag_jvp, for plans
     whose modes are all detected (rho is holomorphic in A, b, c, so the
     tangent is sum dx d rho / d x)."""
 
