@@ -144,7 +144,8 @@ def fock_diag_ad(A, b, c, cutoffs, detected_mask, b_mode="auto"):
 class StateVectorFunction(torch.autograd.Function):
     """psi = state_vector(A, b, c); backward = fock_state_vjp (the cotangents
     sum_k g_k conj(d psi_k / d x), PyTorch's convention for holomorphic maps;
-    A enters as its symmetric part)."""
+    A enters as its symmetric part); forward-mode AD with dual tensors
+    (torch.autograd.forward_ad) = fock_state_jvp."""
 
     @staticmethod
     def forward(ctx, A, b, c, cutoffs, b_mode):
@@ -157,7 +158,18 @@ class StateVectorFunction(torch.autograd.Function):
         ctx.plan = plan
         ctx.c_shape = c.shape
         ctx.save_for_backward(c_, psi)
+        ctx.save_for_forward(c_, psi)
         return psi
+
+    @staticmethod
+    def jvp(ctx, dA, db, dc, *_):
+        c, psi = ctx.saved_tensors
+        M = len(ctx.plan.cutoffs)
+        tan = lambda t, shape: (torch.zeros(shape, dtype=psi.dtype, device=psi.device) if t is None
+                                else t.reshape(shape).contiguous())
+        dpsi = torch.empty_like(psi)
+        F.fock_state_jvp(ctx.plan, c, psi, tan(dA, (M, M)), tan(db, (M,)), tan(dc, (1,)), dpsi)
+        return dpsi
 
     @staticmethod
     def backward(ctx, grad_psi):

@@ -247,3 +247,28 @@ def test_state_jvp_c64():
     ref = gpu_state_jvp(A, b, c, cut, tA, tb, tc)
     got = gpu_state_jvp(A, b, c, cut, tA, tb, tc, torch.complex64)
     assert O.rel_err(got.astype(np.complex128), ref) <= 1e-5
+
+
+def test_state_forward_ad():
+    # torch.autograd.forward_ad through StateVectorFunction (fock_state_jvp),
+    # against the oracle's tangent recurrences; b = 0 schedule at the base point
+    import torch.autograd.forward_ad as fwAD
+    from paper_2303_08879_amd import ops
+    rng = np.random.default_rng(61)
+    cut = [5, 4, 6]
+    A, b, c = rand_state(rng, 3, True)
+    tA = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    tb = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    tc = 0.3 - 0.2j
+    G, dB, dAr = O.tangent_recurrences(0.5 * (A + A.T), b, c, cut)
+    ref = (np.tensordot(tb, dB, axes=(0, 0)) + np.tensordot(0.5 * (tA + tA.T), dAr, axes=([0, 1], [0, 1]))
+           + G * (tc / c))
+    T = lambda x: torch.tensor(np.asarray(x), dtype=torch.complex128, device="cuda")
+    print("[gpu] state forward_ad cut=[5, 4, 6]", flush=True)
+    with fwAD.dual_level():
+        psi = ops.state_vector_ad(fwAD.make_dual(T(A), T(tA)), fwAD.make_dual(T(b), T(tb)),
+                                  fwAD.make_dual(T([c]), T([tc])), cut)
+        p, t = fwAD.unpack_dual(psi)
+        p, t = p.cpu().numpy(), t.cpu().numpy()
+    assert O.rel_err(p, G) <= 1e-10
+    assert O.rel_err(t, ref) <= 1e-10
