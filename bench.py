@@ -389,8 +389,8 @@ def main():
                     help="only run plain 1 GiB device-to-device copies (the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this library runs each circuit on a single device and "
-              f"the build targets one-GPU boxes (asked for --gpus {args.gpus}).", file=sys.stderr)
+        print(f"bench.py measures one GPU only: the library runs each circuit on a single device; sharding "
+              f"across GPUs is a design, not an implementation (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
