@@ -1,4 +1,4 @@
-"""Host-side driver of fock_diag_fwd_batch for batches larger than device
+"""Host-side runner of fock_diag_fwd_batch for batches larger than device
 memory, and the autotuner of the batched sweep's scheduling knobs.
 
 A batch whose outputs and workspaces exceed the memory budget is packed into
