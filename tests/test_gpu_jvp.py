@@ -177,3 +177,28 @@ def test_jvp_edges():
     ref, dref = O.fock_diag_jvp(A, b, c, [4, 1, 5], 0b111, dA, db, dc)
     rho, drho = gpu_jvp(A, b, c, dA, db, dc, [4, 1, 5])
     assert O.rel_err(rho, ref) <= TOL and O.rel_err(drho, dref) <= TOL
+
+
+@pytest.mark.parametrize("M", [6, 7, 8])
+def test_jvp_many_modes_sampled(M):
+    # 6-8 detected modes (cutoff 3 each): seeded patterns with total <= 5
+    # against the oracle on each pattern's own box (cutoffs n_j + 1)
+    rng = np.random.default_rng(300 + M)
+    cut = [3] * M
+    A, b, c = rand_triple(rng, M, False, scale=0.12)
+    dA, db, dc = rand_dir(rng, M)
+    rho, drho = gpu_jvp(A, b, c, dA, db, dc, cut)
+    pats = set()
+    while len(pats) < 8:
+        n = tuple(int(v) for v in rng.integers(0, 3, size=M))
+        if 0 < sum(n) <= 5:
+            pats.add(n)
+    got_v, got_t, ref_v, ref_t = [], [], [], []
+    for n in sorted(pats):
+        r, d = O.fock_diag_jvp(A, b, c, [k + 1 for k in n], (1 << M) - 1, dA, db, dc)
+        got_v.append(rho[n])
+        got_t.append(drho[n])
+        ref_v.append(r[n])
+        ref_t.append(d[n])
+    assert O.rel_err(np.array(got_v), np.array(ref_v)) <= TOL
+    assert O.rel_err(np.array(got_t), np.array(ref_t)) <= TOL
