@@ -171,7 +171,8 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c,
  *               fd_plan_jvp_workspace bytes (values, then tangents)
  * Returns FD_ERR_UNSUPPORTED for plans with undetected modes and for plans
  * created with FD_B_ZERO (a non-zero db reaches the odd levels, which that
- * schedule skips). */
+ * schedule skips).  With fd_plan_use_graphs the sweep is captured once per
+ * set of pointers and replayed, as for fock_diag_fwd. */
 fd_status fd_plan_jvp_workspace(fd_plan p, size_t* bytes);
 fd_status fock_diag_jvp(fd_plan p, const void* A, const void* b, const void* c, const void* dA,
                         const void* db, const void* dc, void* rho, void* drho, void* workspace,

@@ -336,7 +336,10 @@ fd_status fock_diag_jvp(fd_plan p, const void* A, const void* b, const void* c, 
   if (ws_bytes < 2 * fd::jvp_half_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
   std::string err;
   if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);
-  const hipError_t e = fd::run_jvp(P, A, b, c, dA, db, dc, rho, drho, workspace, stream);
+  const hipError_t e = run_maybe_graph(P, 2, true, {A, b, c, dA, db, dc, rho, drho, workspace}, stream,
+                                      [&](hipStream_t st) {
+                                        return fd::run_jvp(P, A, b, c, dA, db, dc, rho, drho, workspace, st);
+                                      });
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return ok();
 }

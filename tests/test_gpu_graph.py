@@ -61,3 +61,43 @@ def test_graph_replays_equal_eager(which):
             assert torch.equal(Be[k], Bg[k]), (it, k)
         assert float(torch.linalg.norm(Bg["dA"])) > 0
     F.fd_device_status(pg)
+
+
+@pytest.mark.parametrize("total", [None, 9])
+def test_jvp_graph_replays_equal_eager(total):
+    # forward mode (fock_diag_jvp) on a box and on a total-cutoff plan: every
+    # replay, with new input values and eager work between replays, equals the
+    # eager sweep bit for bit
+    cut = [6, 5, 7]
+    mask = 0 if total is not None else 0b111
+    pe = F.Plan(cut, mask, torch.complex128, "general", total_cutoff=total)
+    pg = F.Plan(cut, mask, torch.complex128, "general", total_cutoff=total)
+    F.fd_plan_use_graphs(pg, True)
+    dev = "cuda"
+    mk = lambda p: dict(A=torch.empty((6, 6), dtype=torch.complex128, device=dev),
+                        b=torch.empty(6, dtype=torch.complex128, device=dev),
+                        c=torch.empty(1, dtype=torch.complex128, device=dev),
+                        dA=torch.empty((6, 6), dtype=torch.complex128, device=dev),
+                        db=torch.empty(6, dtype=torch.complex128, device=dev),
+                        dc=torch.empty(1, dtype=torch.complex128, device=dev),
+                        rho=torch.empty(p.out_shape, dtype=torch.complex128, device=dev),
+                        drho=torch.empty(p.out_shape, dtype=torch.complex128, device=dev),
+                        ws=torch.empty(p.jvp_workspace(), dtype=torch.uint8, device=dev))
+    Be, Bg = mk(pe), mk(pg)
+    rng = np.random.default_rng(8)
+    for it in range(4):
+        print(f"[graph] jvp total={total} replay {it}", flush=True)
+        X = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+        vals = dict(A=0.15 * (X + X.T), b=0.3 * (rng.standard_normal(6) + 1j * rng.standard_normal(6)),
+                    c=np.array([0.8 + 0.1j * it]),
+                    dA=rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6)),
+                    db=rng.standard_normal(6) + 1j * rng.standard_normal(6), dc=np.array([0.2 - 0.3j]))
+        for B in (Be, Bg):
+            for k, v in vals.items():
+                B[k].copy_(torch.tensor(v))
+        for p, B in ((pe, Be), (pg, Bg)):
+            F.fock_diag_jvp(p, B["A"], B["b"], B["c"], B["dA"], B["db"], B["dc"], B["rho"], B["drho"], B["ws"])
+        torch.cuda.synchronize()
+        _ = (Be["drho"].abs().sum() + Bg["drho"].abs().sum()).item()   # eager work between replays
+        for k in ("rho", "drho"):
+            assert torch.equal(Be[k], Bg[k]), (it, k)
