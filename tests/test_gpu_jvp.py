@@ -202,3 +202,51 @@ def test_jvp_many_modes_sampled(M):
         ref_t.append(d[n])
     assert O.rel_err(np.array(got_v), np.array(ref_v)) <= TOL
     assert O.rel_err(np.array(got_t), np.array(ref_t)) <= TOL
+
+
+def test_jvp_config5_full_size():
+    # the bench workload (8 modes, cutoff 8, 16.8M outputs, b = 0 at the base
+    # point, general schedule): rho equals the forward sweep's bit for bit,
+    # sampled tangent entries match the oracle on each pattern's own box, and
+    # the adjoint identity with the reverse sweep holds over all outputs
+    from paper_2303_08879_amd import workloads as W
+    circ = W.config5()
+    M, dt, dev = circ.M, torch.complex128, "cuda"
+    rng = np.random.default_rng(12)
+    dA, db, dc = rand_dir(rng, M)
+    print("[gpu] jvp config5 full size", flush=True)
+    plan = F.Plan(circ.cutoffs, circ.detected_mask, dt, "general")
+    T = lambda x: torch.tensor(np.asarray(x), dtype=dt, device=dev)
+    At, bt, ct = T(circ.A), T(circ.b), T([circ.c])
+    ws = torch.empty(plan.jvp_workspace(), dtype=torch.uint8, device=dev)
+    rho = torch.empty(plan.out_shape, dtype=dt, device=dev)
+    drho = torch.empty_like(rho)
+    F.fock_diag_jvp(plan, At, bt, ct, T(dA), T(db), T([dc]), rho, drho, ws)
+    del ws
+    wb, sb = plan.workspace(True)
+    wsv = torch.empty(wb, dtype=torch.uint8, device=dev)
+    sv = torch.empty(sb, dtype=torch.uint8, device=dev)
+    rf = torch.empty_like(rho)
+    F.fock_diag_fwd(plan, At, bt, ct, rf, wsv, sv)
+    torch.cuda.synchronize()
+    assert torch.equal(rho, rf)
+    pats = set()
+    while len(pats) < 8:
+        n = tuple(int(v) for v in rng.integers(0, 3, size=M))
+        if 0 < sum(n) <= 6:
+            pats.add(n)
+    d_np = drho.cpu().numpy()
+    got, ref = [], []
+    for n in sorted(pats):
+        _, d = O.fock_diag_jvp(circ.A, circ.b, circ.c, [k + 1 for k in n], (1 << M) - 1, dA, db, dc)
+        got.append(d_np[n])
+        ref.append(d[n])
+    assert O.rel_err(np.array(got), np.array(ref)) <= TOL
+    g = T(rng.standard_normal(plan.out_shape) + 1j * rng.standard_normal(plan.out_shape))
+    gA, gb, gc = torch.empty_like(At), torch.empty_like(bt), torch.empty_like(ct)
+    F.fock_diag_vjp(plan, At, bt, ct, sv, g, gA, gb, gc, wsv)
+    torch.cuda.synchronize()
+    lhs = complex(torch.sum(torch.conj(g) * drho).item())
+    rhs = (np.sum(dA * np.conj(gA.cpu().numpy())) + np.sum(db * np.conj(gb.cpu().numpy()))
+           + dc * np.conj(gc.cpu().numpy()[0]))
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
