@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the selective Fock-amplitude path on one MI355X.
 
-Workload (default): the conditional-state circuit with M=4 modes, mode 0
-undetected (cutoff 30) and modes 1..3 detected (cutoff 12), displaced
-(b != 0), seeded synthetic triple; one step = forward (every intermediate
-kept for the reverse sweep) + reverse sweep with a dense seeded cotangent,
-complex128.  `value` = output Fock amplitudes (entries of rho) per second of
-whole-step wall time, inputs already resident in HBM.
+Headline workload (default): 8 modes, all detected, cutoff 8 (the 8^8 =
+16.8M detection probabilities of a lossy squeezed state through a Haar
+interferometer, b = 0), seeded synthetic triple; one step = forward (every
+intermediate kept for the reverse sweep) + reverse sweep with a dense seeded
+cotangent, complex128.  `value` = output Fock amplitudes (entries of rho) per
+second of whole-step wall time, inputs already resident in HBM.
 
 Roofline: the dominant level kernel's algorithmic bytes (32 B per computed
 amplitude forward, 48 B reverse, complex128) over its HIP-event time, against
-8 TB/s.  The `batched` object times the 256-circuit uneven batch through the
-persistent batched launch and through a loop of per-circuit calls.
+8 TB/s.  Extra legs in the same line: the other single-circuit workloads
+(2 modes; 4 modes with an undetected mode; 5 modes with an undetected mode),
+the complex64 variant of every single-circuit workload with its measured
+error against the complex128 result, the 64-circuit gradient batch, the
+256-circuit uneven batch (persistent batched launch against a graph-replayed
+per-circuit loop), the pure-state, total-cutoff and forward-mode legs, and
+the CPU oracle on a bounded sample.
 
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -34,6 +40,8 @@ FP64_PEAK_TFLOPS = 78.6
 
 def workload(name):
     from paper_2303_08879_amd import workloads as W
+    if name == "config1":
+        return W.config1(), "M=2 both detected C=10, eta=0.9, b=0"
     if name == "config2":
         return W.config2(), "M=4 conditional state: mode 0 undetected C_U=30, modes 1-3 detected C_D=12, b!=0"
     if name == "config4":
@@ -43,14 +51,13 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
-    counter reads for a plain copy of known size), or None when the kernel
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per launch of `kernel` on `workload_name` from the committed
+    rocprofv3 counter summary profiles/hbm_traffic_<workload>.md (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by what the counter reads for a
+    plain copy of known size), or None when no summary covers it or the kernel
     sources changed since the counters were taken."""
-    import glob
-    import hashlib
-    path = os.path.join(HERE, "profiles", "hbm_traffic_config2.md")
+    path = os.path.join(HERE, "profiles", f"hbm_traffic_{workload_name}.md")
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -70,41 +77,200 @@ def measured_traffic(kernel):
     return 1024.0 * (fetch * float(vals["fetch_scale"]) + write * float(vals["write_scale"]))
 
 
-def cpu_baseline(circ, rho_gpu, g_full, corner):
-    """The oracle, unchanged, on a bounded sample of the same workload: all
-    conditional blocks rho[:, :, n] with every detected n_j < corner, forward
-    plus the closed-form adjoint for the cotangent restricted to that sample."""
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model}
+
+
+class CircuitStep:
+    """One circuit in one complex dtype: plan, device buffers and the step
+    forward (intermediates kept) + reverse sweep; whole sweeps replay one
+    captured graph each (the buffers stay fixed)."""
+
+    def __init__(self, circ, dtype, cot_seed=7):
+        import numpy as np
+        import torch
+        from paper_2303_08879_amd import fockdiag as F
+        from paper_2303_08879_amd import workloads as W
+        self.F = F
+        dev = "cuda"
+        self.b_zero = not np.any(circ.b)
+        self.plan = F.Plan(circ.cutoffs, circ.detected_mask, dtype, "zero" if self.b_zero else "general")
+        self.A = torch.tensor(circ.A, dtype=dtype, device=dev)
+        self.b = torch.tensor(circ.b, dtype=dtype, device=dev)
+        self.c = torch.tensor([circ.c], dtype=dtype, device=dev)
+        self.g = torch.tensor(W.random_cotangent(self.plan.out_shape, seed=cot_seed), dtype=dtype, device=dev)
+        wsb, svb = self.plan.workspace(True)
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        self.saved = torch.empty(svb, dtype=torch.uint8, device=dev)
+        self.rho = torch.empty(self.plan.out_shape, dtype=dtype, device=dev)
+        self.dA, self.db, self.dc = torch.empty_like(self.A), torch.empty_like(self.b), torch.empty_like(self.c)
+        F.fd_plan_use_graphs(self.plan, True)
+
+    def step(self):
+        F = self.F
+        F.fock_diag_fwd(self.plan, self.A, self.b, self.c, self.rho, self.ws, self.saved)
+        F.fock_diag_vjp(self.plan, self.A, self.b, self.c, self.saved, self.g, self.dA, self.db, self.dc, self.ws)
+
+    def timed(self, steps, warmup):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        self.F.fd_device_status(self.plan)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def level_events(self, steps):
+        """The same steps launched kernel by kernel with HIP events around every
+        level-sweep launch (graph replay is off while timing is on):
+        (forward launches, forward ms, reverse launches, reverse ms)."""
+        import torch
+        F = self.F
+        F.fd_plan_timing(self.plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_VJP_LEVEL))
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        n_f, ms_f = F.fd_plan_kernel_times(self.plan, F.FD_K_FWD_LEVEL)
+        n_v, ms_v = F.fd_plan_kernel_times(self.plan, F.FD_K_VJP_LEVEL)
+        F.fd_plan_timing(self.plan, 0)
+        F.fd_device_status(self.plan)
+        return n_f, ms_f, n_v, ms_v
+
+    def release(self):
+        self.plan.close()
+        for k in ("A", "b", "c", "g", "ws", "saved", "rho", "dA", "db", "dc"):
+            setattr(self, k, None)
+
+
+def errors_vs(x, ref):
+    """Normwise relative error, max |x - ref| / max |ref|, and the largest
+    element-wise relative error over the entries with |ref| >= 1e-6 max |ref|
+    (computed on the device in float64)."""
+    import torch
+    x = x.to(torch.complex128).reshape(-1)
+    ref = ref.to(torch.complex128).reshape(-1)
+    d = (x - ref).abs()
+    a = ref.abs()
+    amax = float(a.max())
+    big = a >= 1e-6 * amax
+    return {"normwise": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(a)),
+            "max_abs_over_max": float(d.max()) / amax,
+            "elementwise_max_on_large": float((d[big] / a[big]).max())}
+
+
+def grad_errors(s64, s128):
+    import torch
+    x = torch.cat([s64.dA.reshape(-1), s64.db.reshape(-1), s64.dc.reshape(-1)]).to(torch.complex128)
+    r = torch.cat([s128.dA.reshape(-1), s128.db.reshape(-1), s128.dc.reshape(-1)])
+    return float(torch.linalg.vector_norm(x - r) / torch.linalg.vector_norm(r))
+
+
+def single_leg(name, steps, warmup, events=True, keep=False):
+    """One single-circuit workload: complex128 step timing (+ level events),
+    then the complex64 variant and its error against the complex128 result."""
+    import torch
+    circ, desc = workload(name)
+    s = CircuitStep(circ, torch.complex128)
+    sec = s.timed(steps, warmup)
+    out_elems = s.plan.query(s.F.FD_Q_OUT_ELEMS)
+    targets = s.plan.query(s.F.FD_Q_TARGETS)
+    terms = s.plan.query(s.F.FD_Q_READ_TERMS)
+    leg = {"workload": f"{name}: {desc}; one step = forward + VJP",
+           "out_amplitudes": out_elems, "computed_amplitudes": targets, "read_terms": terms,
+           "ms_per_step": 1e3 * sec / steps, "value": out_elems * steps / sec, "unit": "Fock amplitudes/s",
+           "computed_amplitudes_per_s": targets * steps / sec, "steps": steps}
+    if events:
+        n_f, ms_f, n_v, ms_v = s.level_events(steps)
+        leg.update({"fwd_level_launches_per_step": n_f // steps, "vjp_level_launches_per_step": n_v // steps,
+                    "fwd_level_ms_per_step": ms_f / steps, "vjp_level_ms_per_step": ms_v / steps,
+                    "fwd_level_GBs": 32.0 * targets * steps / (ms_f * 1e-3) / 1e9,
+                    "vjp_level_GBs": 48.0 * targets * steps / (ms_v * 1e-3) / 1e9,
+                    "fwd_level_GFLOPs": 8.0 * terms * steps / (ms_f * 1e-3) / 1e9,
+                    "_ev": (n_f, ms_f, n_v, ms_v)})
+    s.step()
+    torch.cuda.synchronize()
+    s64 = CircuitStep(circ, torch.complex64)
+    sec64 = s64.timed(steps, warmup)
+    s64.step()
+    torch.cuda.synchronize()
+    leg["c64"] = {"ms_per_step": 1e3 * sec64 / steps, "value": out_elems * steps / sec64,
+                  "rho_error_vs_c128": errors_vs(s64.rho, s.rho),
+                  "grad_rel_error_vs_c128": grad_errors(s64, s),
+                  "note": "the complex128 result it is compared with matches the float64 oracle to <= 1e-10 "
+                          "(tests); errors are relative to the complex128 values"}
+    s64.release()
+    if keep:
+        return leg, s, circ
+    s.release()
+    torch.cuda.empty_cache()
+    return leg
+
+
+def cpu_baseline(circ, s128, s64, corner):
+    """The oracle, unchanged, on a bounded sample of the same workload: every
+    detection pattern with n_j < corner[j] (a Tier B box: the oracle's full
+    Taylor box over the small cutoffs is exact for those patterns), forward
+    plus the closed-form adjoint for the cotangent restricted to that sample;
+    also the GPU's complex128 and complex64 errors on the sample."""
     import numpy as np
     import oracle as O
+    import torch
     M = circ.M
-    cut = [circ.cutoffs[j] if not (circ.detected_mask >> j) & 1 else corner for j in range(M)]
+    cut = [circ.cutoffs[j] if not (circ.detected_mask >> j) & 1 else corner[j] for j in range(M)]
     nU = sum(1 for j in range(M) if not (circ.detected_mask >> j) & 1)
-    sl = (slice(None),) * (2 * nU) + (slice(0, corner),) * (len(rho_gpu.shape) - 2 * nU)
-    t0 = time.perf_counter()
-    out = O.fock_diag(circ.A, circ.b, circ.c, cut, circ.detected_mask)
-    gs = g_full[sl]
-    O.fock_diag_vjp(circ.A, circ.b, circ.c, cut, circ.detected_mask, gs)
-    dt = time.perf_counter() - t0
-    err = O.rel_err(rho_gpu[sl], out)
-    return dict(value=out.size / dt, unit="Fock amplitudes/s", cores=1, kind="oracle",
-                sample=(f"every output block with detected n_j < {corner} ({out.size} of {rho_gpu.size} "
-                        f"amplitudes), forward + closed-form adjoint, numpy float64, single thread; "
-                        f"per-amplitude cost grows with n, so this sample overstates the oracle's full rate"),
-                seconds=dt, sample_rel_err_gpu_vs_oracle=err)
+    sl = (slice(None),) * (2 * nU) + tuple(slice(0, corner[j]) for j in range(M) if (circ.detected_mask >> j) & 1)
+    from threadpoolctl import threadpool_limits
+    g_full = s128.g.cpu().numpy()
+    with threadpool_limits(1):   # one thread, library routines included
+        t0 = time.perf_counter()
+        out = O.fock_diag(circ.A, circ.b, circ.c, cut, circ.detected_mask)
+        O.fock_diag_vjp(circ.A, circ.b, circ.c, cut, circ.detected_mask, g_full[sl])
+        dt = time.perf_counter() - t0
+    rho128 = s128.rho.cpu().numpy()[sl]
+    rho64 = s64.rho.cpu().numpy()[sl].astype(np.complex128) if s64 is not None else None
+    res = dict(value=out.size / dt, unit="Fock amplitudes/s", cores=1, kind="oracle",
+               sample=(f"every detection pattern with n < {list(corner)} ({out.size} of {s128.rho.numel()} "
+                       f"output amplitudes): the oracle's Taylor box over those cutoffs (exact for them), forward "
+                       f"+ closed-form adjoint, numpy float64, one thread"),
+               seconds=dt, host=host_info(),
+               sample_rel_err_gpu_c128_vs_oracle=O.rel_err(rho128, out))
+    if rho64 is not None:
+        res["sample_rel_err_gpu_c64_vs_oracle"] = O.rel_err(rho64, out)
+    del torch
+    return res
 
 
 def batched_leg(reps=1):
     """The uneven batch (256 circuits, M 3..6, cutoffs 8..16, 0 or 1 undetected
     mode with cutoff 20..40, b = 0, complex128): batched persistent launches
     (one per memory group) against a loop of per-circuit fock_diag_fwd calls on
-    the same stream, same buffers."""
+    the same stream and buffers, each replaying its captured graph; then the
+    complex64 variant of every circuit (per-circuit calls, equal to the batched
+    result bit for bit) against its complex128 result."""
     import torch
     from paper_2303_08879_amd import batching as Bt
+    from paper_2303_08879_amd import fockdiag as F
     from paper_2303_08879_amd import workloads as W
     circs = W.config3()
     runner = Bt.BatchRunner([(c.cutoffs, c.detected_mask) for c in circs], [(c.A, c.b, c.c) for c in circs],
                             budget_bytes=int(150e9))
-    best, tune = Bt.autotune(runner, candidates=[(2, 64, 4), (4, 128, 2)], reps=1)
+    best, tune = Bt.autotune(runner, reps=1)
     runner.check_status()
 
     def timed(batched):
@@ -117,16 +283,51 @@ def batched_leg(reps=1):
         return (time.perf_counter() - t0) / reps
 
     tb = timed(True)
+    tl_eager = timed(False)
+    for p in runner.plans:
+        F.fd_plan_use_graphs(p, True)
     tl = timed(False)
     runner.check_status()
     n = len(circs)
+    targets = sum(p.query(F.FD_Q_TARGETS) for p in runner.plans)
+    outs = sum(p.query(F.FD_Q_OUT_ELEMS) for p in runner.plans)
     out = dict(workload="config3: 256 circuits, M~U{3..6}, C_D~U{8..16}, 0/1 undetected mode C_U~U{20..40}, b=0, "
                         "complex128", circuits=n, memory_groups=len(runner.groups),
+               computed_amplitudes=targets, out_amplitudes=outs,
                batched_circuits_per_s=n / tb, loop_circuits_per_s=n / tl, speedup_vs_loop=tl / tb,
-               batched_s=tb, loop_s=tl, tuning=list(best),
-               tuning_trials_s={str(list(k)): v for k, v in tune.items()})
+               loop_eager_circuits_per_s=n / tl_eager,
+               batched_s=tb, loop_s=tl, loop_eager_s=tl_eager, tuning=list(best),
+               tuning_trials_s={str(list(k)): v for k, v in tune.items()},
+               batched_algorithmic_GBs=32.0 * targets / tb / 1e9,
+               note="loop = per-circuit fock_diag_fwd calls replaying one captured graph each (loop_eager: "
+                    "the same calls launched kernel by kernel); algorithmic bytes 32 B per computed amplitude "
+                    "over the whole batched call (its launches of the largest circuits included)")
+    for p in runner.plans:
+        F.fd_plan_use_graphs(p, False)
     del runner
     torch.cuda.empty_cache()
+    # complex64 per circuit against complex128, same calls one after another
+    worst, worst_el, errs = 0.0, 0.0, []
+    for ci in circs:
+        r = {}
+        for dt in (torch.complex128, torch.complex64):
+            p = F.Plan(ci.cutoffs, ci.detected_mask, dt, "zero")
+            ws = torch.empty(max(p.workspace(False)[0], 256), dtype=torch.uint8, device="cuda")
+            rho = torch.empty(p.out_shape, dtype=dt, device="cuda")
+            F.fock_diag_fwd(p, torch.tensor(ci.A, dtype=dt, device="cuda"), torch.tensor(ci.b, dtype=dt, device="cuda"),
+                            torch.tensor([ci.c], dtype=dt, device="cuda"), rho, ws)
+            r[dt] = rho
+            del ws
+            p.close()
+        e = errors_vs(r[torch.complex64], r[torch.complex128])
+        errs.append(e["normwise"])
+        worst = max(worst, e["normwise"])
+        worst_el = max(worst_el, e["elementwise_max_on_large"])
+        del r
+    torch.cuda.empty_cache()
+    errs.sort()
+    out["c64"] = {"worst_circuit_rel_err_vs_c128": worst, "median_circuit_rel_err_vs_c128": errs[len(errs) // 2],
+                  "worst_circuit_elementwise_max_on_large": worst_el}
     return out
 
 
@@ -165,10 +366,14 @@ def gradient_leg(n=64):
     sec = time.perf_counter() - t0
     F.fd_device_status(plan)
     targets = plan.query(F.FD_Q_TARGETS)
-    return dict(workload="config5b: 64 circuits, M=6, mode 0 undetected C_U=30, 5 detected C_D=8, b=0, complex128; "
-                         "forward (intermediates kept) + VJP per circuit",
-                circuits=n, seconds=sec, circuits_per_s=n / sec, computed_amplitudes_per_circuit=targets,
-                output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec)
+    res = dict(workload="config5b: 64 circuits, M=6, mode 0 undetected C_U=30, 5 detected C_D=8, b=0, complex128; "
+                        "forward (intermediates kept) + VJP per circuit",
+               circuits=n, seconds=sec, circuits_per_s=n / sec, computed_amplitudes_per_circuit=targets,
+               output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec)
+    plan.close()
+    del ws, saved, rho, g, ins, grads
+    torch.cuda.empty_cache()
+    return res
 
 
 def level_counts(cutoffs):
@@ -181,13 +386,13 @@ def level_counts(cutoffs):
 
 
 def state_leg(steps=20):
-    import numpy as np
     """The pure-state workload (8 squeezed modes through a Haar interferometer,
     no loss, b = 0, cutoff 8: the 8^8 amplitudes of psi), complex128.  Under
     b = 0 one launch per even level S computes level S from level S - 2 and
     clears level S - 1; algorithmic bytes of that launch: 16 per amplitude
     written (levels S and S - 1) plus 16 per amplitude of level S - 2 read
     once.  The output permutation to C order is timed apart."""
+    import numpy as np
     import torch
     from paper_2303_08879_amd import fockdiag as F
     from paper_2303_08879_amd import workloads as W
@@ -247,14 +452,13 @@ def state_leg(steps=20):
     sec_j = time.perf_counter() - t3
     N = level_counts(ci.cutoffs)
     smax = len(N) - 1
-    terms = 8 + 8 * 9 // 2 + 1          # bbar, the upper triangle of Abar, cbar
-    passes = -(-terms // 16)
     alg = sum(16 * (N[S] + N[S - 1] + N[S - 2]) for S in range(2, smax + 1, 2))
     if smax % 2:
         alg += 16 * N[smax]   # the last odd level, cleared alone
     launches = nl // steps
     amps = int(N.sum())
     gbs = alg * steps / (ms_l * 1e-3) / 1e9
+    plan.close()
     return dict(workload="state8: pure state, M=8 squeezed modes r~U(0.3,0.7), Haar interferometer, no loss, b=0, "
                          "cutoff 8 (8^8 amplitudes of psi), complex128",
                 amplitudes=amps, calls=steps, ms_per_call=1e3 * sec / steps,
@@ -264,24 +468,23 @@ def state_leg(steps=20):
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
                           "launches": launches, "avg_launch_us": round(1e3 * ms_l / nl, 3),
                           "algorithmic_bytes_per_launch": int(alg // max(launches, 1)),
-                          "traffic": measured_traffic("k_state_level")},
+                          "traffic": measured_traffic("state8", "k_state_level")},
                 norm2=float((psi.abs() ** 2).sum()),
-                vjp={"ms_per_call": 1e3 * sec_v / steps, "launches": passes + 1,
-                     "note": f"{passes} launches of up to 16 of the {terms} cotangent dot products (each reads "
-                             "the cotangent and shifted amplitudes once: 32 B per amplitude) and the ordered "
-                             "slot reduction",
-                     "algorithmic_GBs": round(passes * 32 * amps * steps / sec_v / 1e9, 1)},
+                vjp={"ms_per_call": 1e3 * sec_v / steps,
+                     "note": "the 45 cotangent dot products (8 of b, 36 of the symmetric A, 1 of c) over the box",
+                     "algorithmic_GBs": round(32 * amps * steps / sec_v / 1e9, 1),
+                     "algorithmic_bytes": "32 B per amplitude: the cotangent and psi read once"},
                 jvp={"ms_per_call": 1e3 * sec_j / steps, "launches": 1,
                      "note": "one pass: reads psi (and its shifted neighbours), writes the tangent: 32 B per amplitude",
                      "algorithmic_GBs": round(32 * amps * steps / sec_j / 1e9, 1)})
 
 
 def total_leg(steps=20, N=16, eps=0.05):
-    """Total photon cutoff: the 8-mode lossy state of config 5 (r~U(0.5,1.0),
-    eta~U(0.8,0.95), b = 0) with per-mode cutoff 40 and |n| <= N, p(n) of the
-    C(N+8, 8) points in level order (complex128); then the same sweep with
-    probability-sum stopping at 1 - eps (the stream is synchronised once per 4
-    levels)."""
+    """Total photon cutoff: the 8-mode lossy state of the headline workload
+    (r~U(0.5,1.0), eta~U(0.8,0.95), b = 0) with per-mode cutoff 40 and
+    |n| <= N, p(n) of the C(N+8, 8) points in level order (complex128); then
+    the same sweep with probability-sum stopping at 1 - eps (the stream is
+    synchronised once per 4 levels)."""
     import torch
     from paper_2303_08879_amd import fockdiag as F
     from paper_2303_08879_amd import workloads as W
@@ -309,6 +512,7 @@ def total_leg(steps=20, N=16, eps=0.05):
     sec_stop = time.perf_counter() - t1
     F.fd_device_status(plan)
     pts = plan.query(F.FD_Q_OUT_ELEMS)
+    plan.close()
     return dict(workload=f"config5 state (8 modes, b=0), per-mode cutoff 40, total photon cutoff {N}: "
                          f"p(n) for the {pts} points with |n| <= {N}, complex128",
                 points=pts, ms_per_call=1e3 * sec / steps, value=pts * steps / sec, unit="probabilities/s",
@@ -317,11 +521,10 @@ def total_leg(steps=20, N=16, eps=0.05):
 
 
 def jvp_leg(steps=10):
-    """Forward mode of rho on config 5 (8 modes, all detected, cutoff 8:
-    16.8M outputs; b = 0 at the base point, so the general schedule that a
-    non-zero db needs): rho and its tangent along a seeded direction in one
-    sweep, against the forward alone on the same schedule.  Both timed over
-    `steps` calls; the level kernels also with HIP events."""
+    """Forward mode of rho on the headline workload (8 modes, all detected,
+    cutoff 8: 16.8M outputs; b = 0 at the base point, so the general schedule
+    that a non-zero db needs): rho and its tangent along a seeded direction in
+    one sweep, against the forward alone on the same schedule."""
     import numpy as np
     import torch
     from paper_2303_08879_amd import fockdiag as F
@@ -363,6 +566,7 @@ def jvp_leg(steps=10):
     # once and read once by their reader (64 B; the forward alone 32 B)
     t = plan.query(F.FD_Q_TARGETS)
     gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
+    plan.close()
     return dict(workload="config5: M=8 all detected C=8 (16.8M outputs), b=0 at the base point, general schedule, "
                          "one seeded direction (dA, db, dc), complex128",
                 outputs=n, ms_per_call=ms_j, value=n * 1e3 / ms_j, unit="outputs (rho and drho)/s",
@@ -371,20 +575,23 @@ def jvp_leg(steps=10):
                 level_GBs_algorithmic=gbs(64.0 * t, lvl_j), forward_level_GBs_algorithmic=gbs(32.0 * t, lvl_f))
 
 
+def progress(what, t0):
+    print(f"[bench] {what} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="config5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-corner", type=int, default=5)
+    ap.add_argument("--no-legs", action="store_true", help="skip the other single-circuit workloads")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuits leg")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the 64-circuit gradient batch")
     ap.add_argument("--no-state", action="store_true", help="skip the pure-state (state vector) leg")
     ap.add_argument("--no-total", action="store_true", help="skip the total-photon-cutoff leg")
     ap.add_argument("--no-jvp", action="store_true", help="skip the forward-mode (JVP) leg")
-    ap.add_argument("--gradient-leg", action="store_true",
-                    help="also time the 64-circuit gradient workload (forward + VJP per circuit)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device-to-device copies (the reference for HBM byte counters)")
     args = ap.parse_args()
@@ -393,10 +600,7 @@ def main():
               f"across GPUs is a design, not an implementation (asked for --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2303_08879_amd import fockdiag as F
-    from paper_2303_08879_amd import workloads as W
 
     if args.copy_calibration:
         # a plain copy kernel of known size: each copy reads and writes 1 GiB
@@ -408,126 +612,92 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 5}), flush=True)
         return
 
-    circ, desc = workload(args.workload)
-    dev = "cuda"
-    dt = torch.complex128
-    b_zero = not np.any(circ.b)
-    plan = F.Plan(circ.cutoffs, circ.detected_mask, dt, "zero" if b_zero else "general")
-    A = torch.tensor(circ.A, dtype=dt, device=dev)
-    b = torch.tensor(circ.b, dtype=dt, device=dev)
-    c = torch.tensor([circ.c], dtype=dt, device=dev)
-    shape = plan.out_shape
-    g_np = W.random_cotangent(shape, seed=7)
-    g = torch.tensor(g_np, dtype=dt, device=dev)
-    ws_bytes, saved_bytes = plan.workspace(True)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    saved = torch.empty(saved_bytes, dtype=torch.uint8, device=dev)
-    rho = torch.empty(shape, dtype=dt, device=dev)
-    dA, db, dc = torch.empty_like(A), torch.empty_like(b), torch.empty_like(c)
-
-    def step():
-        F.fock_diag_fwd(plan, A, b, c, rho, ws, saved)
-        F.fock_diag_vjp(plan, A, b, c, saved, g, dA, db, dc, ws)
-
-    # the timed steps replay one captured graph per sweep (buffers are fixed)
-    F.fd_plan_use_graphs(plan, True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    F.fd_device_status(plan)
-
-    # timed region: whole steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = t1 - t0
-    out_elems = plan.query(F.FD_Q_OUT_ELEMS)
-    value = out_elems * args.steps / sec
-
-    # same steps again, launched kernel by kernel with HIP events around every
-    # level-sweep launch (graph replay is off while timing is on)
-    F.fd_plan_timing(plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_VJP_LEVEL))
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    n_f, ms_f = F.fd_plan_kernel_times(plan, F.FD_K_FWD_LEVEL)
-    n_v, ms_v = F.fd_plan_kernel_times(plan, F.FD_K_VJP_LEVEL)
-    F.fd_plan_timing(plan, 0)
-    F.fd_device_status(plan)
-
-    targets = plan.query(F.FD_Q_TARGETS)
-    terms = plan.query(F.FD_Q_READ_TERMS)
-    # algorithmic bytes per computed amplitude (c128): forward writes it once and
-    # its reader reads it once (32 B); reverse reads its cotangent, reads the
-    # forward value it was computed from and writes the cotangent of that read (48 B)
-    fwd_bytes = 32.0 * targets * args.steps
-    vjp_bytes = 48.0 * targets * args.steps
-    fwd_gbs = fwd_bytes / (ms_f * 1e-3) / 1e9
-    vjp_gbs = vjp_bytes / (ms_v * 1e-3) / 1e9
-    kind = "block" if plan.query(F.FD_Q_BLOCK) > 1 else "point"
+    # headline: forward + VJP of the named workload, complex128, graph replay
+    t_start = time.perf_counter()
+    head, s128, circ = single_leg(args.workload, args.steps, args.warmup, events=True, keep=True)
+    progress(f"headline {args.workload}", t_start)
+    n_f, ms_f, n_v, ms_v = head.pop("_ev")
+    targets = head["computed_amplitudes"]
+    kind = "block" if s128.plan.query(s128.F.FD_Q_BLOCK) > 1 else "point"
     if ms_v >= ms_f:
-        dom = dict(kernel=f"k_vjp_{kind} (reverse level sweep)", short=f"k_vjp_{kind}", achieved=vjp_gbs,
-                   launches=n_v, avg_launch_us=1e3 * ms_v / max(n_v, 1), bytes_per_unit=48)
+        dom = dict(kernel=f"k_vjp_{kind} (reverse level sweep)", short=f"k_vjp_{kind}", ms=ms_v, launches=n_v,
+                   bytes_per_unit=48)
     else:
-        dom = dict(kernel=f"k_fwd_{kind} (forward level sweep)", short=f"k_fwd_{kind}", achieved=fwd_gbs,
-                   launches=n_f, avg_launch_us=1e3 * ms_f / max(n_f, 1), bytes_per_unit=32)
-    # algorithmic bytes of one launch: bytes per computed amplitude x amplitudes per level launch
-    alg_per_launch = dom["bytes_per_unit"] * targets / max(dom["launches"] / args.steps, 1)
-    traffic = measured_traffic(dom["short"]) if args.workload == "config2" else None
-    roof = {"bound": "hbm", "achieved": round(dom["achieved"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom["achieved"] / HBM_PEAK_GBS, 5),
+        dom = dict(kernel=f"k_fwd_{kind} (forward level sweep)", short=f"k_fwd_{kind}", ms=ms_f, launches=n_f,
+                   bytes_per_unit=32)
+    # algorithmic bytes of one launch: bytes per computed amplitude x computed
+    # amplitudes per level launch (the step's amplitudes over its launches)
+    per_step = max(dom["launches"] // args.steps, 1)
+    alg_per_launch = dom["bytes_per_unit"] * targets / per_step
+    avg_s = dom["ms"] * 1e-3 / max(dom["launches"], 1)
+    achieved = alg_per_launch / avg_s / 1e9
+    traffic = measured_traffic(args.workload, dom["short"])
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": None if traffic is None else round(traffic), "kernel": dom["kernel"],
-            "avg_launch_us": round(dom["avg_launch_us"], 3), "launches": dom["launches"],
+            "avg_launch_us": round(avg_s * 1e6, 3), "launches": dom["launches"],
             "algorithmic_bytes_per_amplitude": dom["bytes_per_unit"],
             "algorithmic_bytes_per_launch": round(alg_per_launch),
             "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_per_launch, 3)}
-    flops_fwd = 8.0 * terms
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "Fock amplitudes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}; one step = forward + VJP, complex128",
-                   "out_amplitudes": out_elems, "computed_amplitudes": targets},
+        "config": {"workload": head["workload"] + ", complex128",
+                   "out_amplitudes": head["out_amplitudes"], "computed_amplitudes": targets},
         "roofline": roof,
-        "detail": {
-            "computed_amplitudes_per_s": targets * args.steps / sec,
-            "fwd_level_ms_per_step": ms_f / args.steps, "vjp_level_ms_per_step": ms_v / args.steps,
-            "fwd_level_GBs": round(fwd_gbs, 2), "vjp_level_GBs": round(vjp_gbs, 2),
-            "fwd_level_GFLOPs": flops_fwd * args.steps / (ms_f * 1e-3) / 1e9,
-            "fp64_peak_TFLOPs": FP64_PEAK_TFLOPS,
-            "events_pass_ms_per_step": 1e3 * (t3 - t2) / args.steps,
-        },
+        "detail": {k: head[k] for k in ("computed_amplitudes_per_s", "fwd_level_ms_per_step",
+                                        "vjp_level_ms_per_step", "fwd_level_GBs", "vjp_level_GBs",
+                                        "fwd_level_GFLOPs", "read_terms")},
+        "c64": head["c64"],
     }
+    line["detail"]["fp64_peak_TFLOPs"] = FP64_PEAK_TFLOPS
+    if not args.no_cpu_baseline:
+        import numpy as np
+        s64 = CircuitStep(circ, torch.complex64)
+        s64.step()
+        torch.cuda.synchronize()
+        corner = [3 if j < 5 else 2 for j in range(circ.M)] if circ.M == 8 else [5] * circ.M
+        line["cpu_baseline"] = cpu_baseline(circ, s128, s64, corner)
+        s64.release()
+        progress("cpu_baseline", t_start)
+        del np
+    s128.release()
+    torch.cuda.empty_cache()
+    if not args.no_legs:
+        line["legs"] = {}
+        for name in ("config1", "config2", "config4", "config5"):
+            if name == args.workload:
+                continue
+            steps = 200 if name == "config1" else 20
+            leg = single_leg(name, steps, 3, events=True)
+            leg.pop("_ev", None)
+            line["legs"][name] = leg
+            progress(name, t_start)
+    if not args.no_gradient:
+        line["gradient_batch"] = gradient_leg()
+        progress("gradient_batch", t_start)
     if not args.no_batched:
         line["batched"] = batched_leg()
+        progress("batched", t_start)
     if not args.no_state:
         line["state_vector"] = state_leg()
+        progress("state_vector", t_start)
     if not args.no_total:
         line["total_cutoff"] = total_leg()
+        progress("total_cutoff", t_start)
     if not args.no_jvp:
         line["density_jvp"] = jvp_leg()
-    if args.gradient_leg:
-        line["gradient_batch"] = gradient_leg()
-    if not args.no_cpu_baseline:
-        torch.cuda.synchronize()
-        step()
-        torch.cuda.synchronize()
-        line["cpu_baseline"] = cpu_baseline(circ, rho.cpu().numpy(), g_np, args.cpu_corner)
+        progress("density_jvp", t_start)
     print(json.dumps(line), flush=True)
 
 

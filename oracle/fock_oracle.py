@@ -66,6 +66,7 @@ __all__ = [
     "fock_diag_vjp",
     "tangent_recurrences",
     "fock_diag_jvp",
+    "probs_vjp_pure",
     "rel_err",
 ]
 
@@ -469,6 +470,70 @@ def fock_diag_jvp(A, b, c, cutoffs, detected_mask: int, dA, db, dc):
     dG = (np.tensordot(dbi, dGb, axes=(0, 0)) + np.tensordot(dAi, dGA, axes=([0, 1], [0, 1]))
           + G * (complex(dc) / complex(c)))
     return select_outputs(G, detected_mask), select_outputs(dG, detected_mask)
+
+
+def _shift(X: np.ndarray, shifts) -> np.ndarray:
+    """Y[n] = X[n - shifts] (zero where some n_j < shifts_j)."""
+    Y = np.zeros_like(X)
+    src = tuple(slice(0, X.shape[j] - s) for j, s in enumerate(shifts))
+    dst = tuple(slice(s, None) for s in shifts)
+    Y[dst] = X[src]
+    return Y
+
+
+def probs_vjp_pure(psi, c, gbar):
+    """Closed-form adjoint of every detection probability of a PURE state, at
+    full size.  For rho = psi psi^dag (Sec. 2.2: the density triple of a pure
+    state is the ket triple and its conjugate), the amplitude at interleaved
+    index (kappa kets, beta bras) is psi_kappa conj(psi_beta), so the
+    off-diagonal amplitudes the closed form needs next to the diagonal are
+    products of two state-vector entries.  With p(n) = rho_{d(n)} and the
+    derivatives of ``adjoint_closed_form`` (d rho_k/d A_il = 1/2 sqrt(k_i k_l)
+    rho_{k-1_i-1_l}, i != l; 1/2 sqrt(k_i (k_i-1)) rho_{k-2*1_i}, i = l;
+    d rho_k/d b_i = sqrt(k_i) rho_{k-1_i}; d rho_k/d c = rho_k / c):
+        k = d(n), i = ket p:  k - 1_i has kets n - 1_p and bras n,
+        i = bra p:            kets n and bras n - 1_p.
+    ``psi`` is the state vector over the whole box (cutoffs C_j), ``c`` the
+    density triple's c (= |c_psi|^2, used by dc only), ``gbar`` the cotangent
+    of p over the same box.  Returns (dA, db, dc) in block order, as
+    ``fock_diag_vjp`` does for the all-detected output of the density triple."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    G = np.asarray(gbar, dtype=np.complex128)
+    M = psi.ndim
+    dims = psi.shape
+    D = 2 * M
+    cpsi = np.conj(psi)
+    e = lambda *ps: tuple(sum(1 for q in ps if q == j) for j in range(M))
+    root = [np.sqrt(np.arange(dims[j], dtype=np.float64)).reshape([dims[j] if a == j else 1 for a in range(M)])
+            for j in range(M)]
+    n_of = [np.arange(dims[j], dtype=np.float64).reshape([dims[j] if a == j else 1 for a in range(M)])
+            for j in range(M)]
+
+    def amp(kets, bras):
+        # rho at kets n - e(kets), bras n - e(bras), as an array over n
+        return _shift(psi, e(*kets)) * _shift(cpsi, e(*bras))
+
+    def side(pos):
+        return ("ket" if pos % 2 == 0 else "bra"), pos // 2
+
+    Abar = np.zeros((D, D), dtype=np.complex128)
+    bbar = np.zeros(D, dtype=np.complex128)
+    for i in range(D):
+        si, p = side(i)
+        R = amp([p], []) if si == "ket" else amp([], [p])
+        bbar[i] = np.sum(G * np.conj(root[p] * R))
+        for l in range(D):
+            sl, q = side(l)
+            kets = [x for s_, x in ((si, p), (sl, q)) if s_ == "ket"]
+            bras = [x for s_, x in ((si, p), (sl, q)) if s_ == "bra"]
+            if i == l:
+                w = 0.5 * np.sqrt(n_of[p] * np.maximum(n_of[p] - 1.0, 0.0))
+            else:
+                w = 0.5 * root[p] * root[q]
+            Abar[i, l] = np.sum(G * np.conj(w * amp(kets, bras)))
+    cbar = np.sum(G * np.conj(psi * cpsi / complex(c)))
+    dA, db = from_interleaved(Abar, bbar)
+    return dA, db, complex(cbar)
 
 
 # --------------------------------------------------------------------------

@@ -9,10 +9,6 @@
 
 #include "fd_internal.h"
 
-struct fd_plan_s {
-  fd::Plan P;
-};
-
 // A state-vector plan: the tables of the all-detected plan over the same
 // modes (the lattice of n, its levels and the output permutation).
 struct fd_state_plan_s {
@@ -133,6 +129,11 @@ fd_status check_ptrs(const fd::Plan& P, std::initializer_list<const void*> ps) {
 }
 }  // namespace
 
+namespace fd {
+fd_status api_fail(fd_status s, const std::string& msg) { return fail(s, msg); }
+fd_status api_ok() { return ok(); }
+}  // namespace fd
+
 extern "C" {
 
 fd_status fd_plan_create(int M, const int* cutoffs, uint32_t detected_mask, fd_dtype dt, uint32_t flags,
@@ -154,6 +155,10 @@ fd_status fd_plan_create(int M, const int* cutoffs, uint32_t detected_mask, fd_d
 fd_status fd_plan_destroy(fd_plan p) {
   if (!p) return ok();
   fd::Plan& P = p->P;
+  if (fd::unloading()) {   // the HIP runtime may be gone: release host memory only
+    delete p;
+    return ok();
+  }
   if (P.d_pn) {
     int cur = 0;
     (void)hipGetDevice(&cur);

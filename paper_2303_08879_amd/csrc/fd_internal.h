@@ -159,6 +159,8 @@ struct Plan {
 };
 
 size_t elem_bytes(fd_dtype dt);
+// True once the library is being unloaded: releases then skip device calls.
+bool unloading();
 // LDS of the undetected-block fill (vjp: its reverse), one wavefront: the
 // block (twice for the reverse: forward values and cotangents), A and b
 // between undetected positions, the square-root tables, the entry list by
@@ -281,4 +283,13 @@ hipError_t run_state_vjp(const Plan& P, const void* c, const void* psi, const vo
 hipError_t run_vjp(const Plan& P, bool odd, const void* A, const void* b, const void* c, const void* saved,
                    const void* drho, void* dA, void* db, void* dc, void* ws, hipStream_t st);
 
+// Error reporting of the C ABI: sets the calling thread's fd_last_error().
+fd_status api_fail(fd_status s, const std::string& msg);
+fd_status api_ok();
+
 }  // namespace fd
+
+// The opaque plan handle of the C ABI.
+struct fd_plan_s {
+  fd::Plan P;
+};

@@ -126,6 +126,7 @@ uint64_t g_clock = 0;
 constexpr size_t kBatchCache = 8;
 
 void free_sched(BatchSched& s) {
+  if (unloading()) return;   // the HIP runtime may be gone
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(s.device);

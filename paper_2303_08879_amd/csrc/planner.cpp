@@ -32,6 +32,15 @@ static int64_t count_box_levels(const std::vector<int>& ub, int smax) {
   return t;
 }
 
+namespace {
+std::atomic<bool> g_unloading{false};
+// Runs when the library is unloaded (process exit or dlclose): the HIP
+// runtime may already be shutting down, so later releases skip device calls.
+__attribute__((destructor)) void mark_unloading() { g_unloading.store(true); }
+}  // namespace
+
+bool unloading() { return g_unloading.load(); }
+
 fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint32_t flags, Plan* P,
                      std::string* err, int level_cap) {
   static std::atomic<uint64_t> next_uid{1};

@@ -7,8 +7,10 @@ calls raise instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -34,6 +36,9 @@ EXPORTS = [
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
 
 _lib = None
+# Every plan object not yet destroyed: released in order at interpreter exit
+# (see _release_all).
+_live = weakref.WeakSet()
 
 
 class BatchTuning(ctypes.Structure):
@@ -100,7 +105,26 @@ def lib():
         if name != "fd_last_error":
             getattr(L, name).restype = i32
     _lib = L
+    atexit.register(_release_all)
     return L
+
+
+def _release_all():
+    """Destroys every live plan at interpreter exit, while the HIP runtime (and
+    any profiler attached to it) is still fully up: plans own device tables,
+    captured graphs, a capture stream and the batched sweep's cached
+    schedules, and leaving them to the garbage collection of module globals
+    would release them at an unspecified point of the shutdown.  Pending work
+    is waited for first."""
+    if _lib is None:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except RuntimeError:
+        pass
+    for p in list(_live):
+        p.close()
 
 
 def _check(status):
@@ -144,12 +168,17 @@ class Plan:
             _check(lib().fd_plan_create_total(self.M, arr, int(total_cutoff), dt, flags, ctypes.byref(h)))
             self.detected_mask = (1 << self.M) - 1
         self.handle = h
+        _live.add(self)
 
-    def __del__(self):
+    def close(self):
+        """fd_plan_destroy (idempotent; the plan is unusable afterwards)."""
         h = getattr(self, "handle", None)
         if h is not None and _lib is not None:
             _lib.fd_plan_destroy(h)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.close()
 
     def level_offsets(self):
         """fd_plan_level_offsets (plans with every mode detected)."""
@@ -198,12 +227,17 @@ class StatePlan:
         h = ctypes.c_void_p()
         _check(lib().fd_state_plan_create(self.M, arr, dt, flags, ctypes.byref(h)))
         self.handle = h
+        _live.add(self)
 
-    def __del__(self):
+    def close(self):
+        """fd_state_plan_destroy (idempotent)."""
         h = getattr(self, "handle", None)
         if h is not None and _lib is not None:
             _lib.fd_state_plan_destroy(h)
-            self.handle = None
+        self.handle = None
+
+    def __del__(self):
+        self.close()
 
     @property
     def out_shape(self):

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import oracle as O
+from parity import assert_close, assert_grad_close  # noqa: F401
 from paper_2303_08879_amd import fockdiag as F
 from paper_2303_08879_amd import ops
 
@@ -58,8 +59,8 @@ def test_jvp_small(M, cut, bz):
     ref, dref = O.fock_diag_jvp(A, b, c, cut, mask, dA, db, dc)
     for b_mode in (["general", "auto"] if bz else ["general"]):
         rho, drho = gpu_jvp(A, b, c, dA, db, dc, cut, b_mode=b_mode)
-        assert O.rel_err(rho, ref) <= TOL
-        assert O.rel_err(drho, dref) <= TOL
+        assert_close(rho, ref, label="gpu_jvp:61")
+        assert_close(drho, dref, label="gpu_jvp:62")
 
 
 def test_jvp_multi_tile_sampled():
@@ -78,7 +79,7 @@ def test_jvp_multi_tile_sampled():
         _, d = O.fock_diag_jvp(A, b, c, [k + 1 for k in n], (1 << M) - 1, dA, db, dc)
         got.append(drho[n])
         ref.append(d[n])
-    assert O.rel_err(np.array(got), np.array(ref)) <= TOL
+    assert_close(np.array(got), np.array(ref), label="gpu_jvp:81")
     plan = F.Plan(cut, (1 << M) - 1, torch.complex128, "general")
     T = lambda x: torch.tensor(np.asarray(x), dtype=torch.complex128, device="cuda")
     ws = torch.empty(plan.workspace(False)[0], dtype=torch.uint8, device="cuda")
@@ -127,8 +128,8 @@ def test_jvp_total_cutoff(cut, N):
     dims = [min(C, N + 1) for C in cut]
     ref, dref = O.fock_diag_jvp(A, b, c, dims, (1 << M) - 1, dA, db, dc)
     pts, _ = O.level_points(cut, N)
-    assert O.rel_err(rho, np.array([ref[n] for n in pts])) <= TOL
-    assert O.rel_err(drho, np.array([dref[n] for n in pts])) <= TOL
+    assert_close(rho, np.array([ref[n] for n in pts]), label="gpu_jvp:130")
+    assert_close(drho, np.array([dref[n] for n in pts]), label="gpu_jvp:131")
 
 
 def test_jvp_c64():
@@ -157,8 +158,8 @@ def test_torch_forward_ad():
                                fwAD.make_dual(T([c]), T([dc])), cut, 0b111, b_mode="general")
         p, t = fwAD.unpack_dual(rho)
         p, t = p.cpu().numpy(), t.cpu().numpy()
-    assert O.rel_err(p, ref) <= TOL
-    assert O.rel_err(t, dref) <= TOL
+    assert_close(p, ref, label="gpu_jvp:160")
+    assert_close(t, dref, label="gpu_jvp:161")
 
 
 def test_jvp_edges():
@@ -176,7 +177,8 @@ def test_jvp_edges():
     assert np.all(drho == 0)
     ref, dref = O.fock_diag_jvp(A, b, c, [4, 1, 5], 0b111, dA, db, dc)
     rho, drho = gpu_jvp(A, b, c, dA, db, dc, [4, 1, 5])
-    assert O.rel_err(rho, ref) <= TOL and O.rel_err(drho, dref) <= TOL
+    assert_close(rho, ref, label="jvp rho")
+    assert_close(drho, dref, label="jvp drho")
 
 
 @pytest.mark.parametrize("M", [6, 7, 8])
@@ -200,8 +202,8 @@ def test_jvp_many_modes_sampled(M):
         got_t.append(drho[n])
         ref_v.append(r[n])
         ref_t.append(d[n])
-    assert O.rel_err(np.array(got_v), np.array(ref_v)) <= TOL
-    assert O.rel_err(np.array(got_t), np.array(ref_t)) <= TOL
+    assert_close(np.array(got_v), np.array(ref_v), label="gpu_jvp:203")
+    assert_close(np.array(got_t), np.array(ref_t), label="gpu_jvp:204")
 
 
 def test_jvp_config5_full_size():
@@ -241,7 +243,7 @@ def test_jvp_config5_full_size():
         _, d = O.fock_diag_jvp(circ.A, circ.b, circ.c, [k + 1 for k in n], (1 << M) - 1, dA, db, dc)
         got.append(d_np[n])
         ref.append(d[n])
-    assert O.rel_err(np.array(got), np.array(ref)) <= TOL
+    assert_close(np.array(got), np.array(ref), label="gpu_jvp:244")
     g = T(rng.standard_normal(plan.out_shape) + 1j * rng.standard_normal(plan.out_shape))
     gA, gb, gc = torch.empty_like(At), torch.empty_like(bt), torch.empty_like(ct)
     F.fock_diag_vjp(plan, At, bt, ct, sv, g, gA, gb, gc, wsv)

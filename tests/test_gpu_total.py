@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle as O
+from parity import assert_close, assert_grad_close  # noqa: F401
 from paper_2303_08879_amd import fockdiag as F
 from paper_2303_08879_amd import workloads as W
 
@@ -55,7 +56,7 @@ def test_total_cutoff_parity(cut, N, alpha_var):
     p, offs, _ = run_total(A, b, c, cut, N)
     ref, roffs = O.probs_total(A, b, c, cut, N)
     assert offs == roffs
-    assert O.rel_err(p, ref) <= TOL
+    assert_close(p, ref, label="gpu_total:58")
 
 
 def test_large_box_small_simplex():
@@ -76,7 +77,7 @@ def test_large_box_small_simplex():
     where = {n: k for k, n in enumerate(pts)}
     corner = O.detection_probs(A, b, c, [2] * 8)
     got = np.array([p[where[n]] for n in itertools.product((0, 1), repeat=8)])
-    assert O.rel_err(got, corner.reshape(-1)) <= TOL
+    assert_close(got, corner.reshape(-1), label="gpu_total:79")
 
 
 @pytest.mark.parametrize("eps,expect", [(1e-2, 4), (1e-5, 10), (1e-8, None)])
@@ -95,7 +96,7 @@ def test_probability_sum_stopping(eps, expect):
     if expect is not None:
         assert mass >= 1 - eps
     cut_at = offs[levels]
-    assert O.rel_err(p[:cut_at], ref[:cut_at]) <= TOL
+    assert_close(p[:cut_at], ref[:cut_at], label="gpu_total:98")
     assert np.all(p[cut_at:] == 0)
 
 
@@ -115,7 +116,7 @@ def test_stopping_on_a_box_plan():
     assert levels == O.stop_level(lm, 1e-3) + 1
     S = np.add.outer(np.arange(10), np.arange(10))
     assert np.all(p[S >= levels] == 0)
-    assert O.rel_err(p[S < levels], ref[S < levels]) <= TOL
+    assert_close(p[S < levels], ref[S < levels], label="gpu_total:118")
 
 
 def test_total_cutoff_edges():
@@ -129,7 +130,8 @@ def test_total_cutoff_edges():
     # N above the box's top level: the whole box in level order
     p, offs, _ = run_total(A, b, c, [3, 2, 3], 50)
     ref, roffs = O.probs_total(A, b, c, [3, 2, 3], 50)
-    assert offs == roffs and O.rel_err(p, ref) <= TOL
+    assert offs == roffs
+    assert_close(p, ref, label="total offsets")
 
 
 def test_total_cutoff_c64():

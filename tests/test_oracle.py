@@ -428,3 +428,74 @@ def test_state_vector_vjp_finite_differences():
         fd = np.real(np.sum(np.conj(g) * (fp - fm))) / (2 * h)
         pred = np.real(np.sum(np.conj(dA) * EA) + np.sum(np.conj(db) * Eb) + np.conj(dc) * Ec)
         assert abs(fd - pred) < 1e-7 * max(1.0, abs(pred))
+
+
+def test_select_outputs_two_undetected_axis_order():
+    # rho[k_u0, k_u1, l_u0, l_u1, n_d] = <k_u0 k_u1 n_d| rho |l_u0 l_u1 n_d>: written
+    # out entry by entry from the interleaved full box (axes ket_j, bra_j per mode)
+    rng = np.random.default_rng(81)
+    U = W.haar_unitary(rng, 3)
+    A, b, c = triple([0.5, 0.35, 0.45], U, [0.9, 0.8, 0.85], [0.15, -0.1j, 0.05])
+    cut = [3, 4, 2]
+    R = O.full_density_matrix(A, b, c, cut)          # axes (k0, l0, k1, l1, k2, l2)
+    out = O.fock_diag(A, b, c, cut, 0b010)           # modes 0 and 2 undetected, mode 1 detected
+    assert out.shape == (3, 2, 3, 2, 4)
+    for k0 in range(3):
+        for k2 in range(2):
+            for l0 in range(3):
+                for l2 in range(2):
+                    for n1 in range(4):
+                        assert out[k0, k2, l0, l2, n1] == R[k0, l0, n1, n1, k2, l2]
+    # undetected modes 0 and 1 first, detected mode 2 last
+    out2 = O.fock_diag(A, b, c, cut, 0b100)
+    assert out2.shape == (3, 4, 3, 4, 2)
+    for k0, k1, l0, l1, n2 in np.ndindex(*out2.shape):
+        assert out2[k0, k1, l0, l1, n2] == R[k0, l0, k1, l1, n2, n2]
+
+
+@pytest.mark.parametrize("M,cut,mask", [
+    (2, [5, 4], 0b10),        # one undetected mode, first
+    (3, [3, 4, 3], 0b101),    # one undetected mode, not first
+    (3, [3, 3, 3], 0b010),    # two undetected modes around a detected one
+    (3, [3, 3, 2], 0b100),    # two undetected modes first
+])
+def test_vjp_with_undetected_modes_finite_differences(M, cut, mask):
+    # the closed-form adjoint scattered onto undetected blocks, against central
+    # differences of the plain Taylor box along random directions
+    # (dL/dh = Re sum conj(grad) E for L = Re sum conj(g) rho)
+    rng = np.random.default_rng(90 + 7 * M + mask)
+    U = W.haar_unitary(rng, M)
+    A, b, c = triple(rng.uniform(0.3, 0.6, M), U, rng.uniform(0.8, 0.95, M),
+                     0.2 * (rng.standard_normal(M) + 1j * rng.standard_normal(M)))
+    out = O.fock_diag(A, b, c, cut, mask)
+    g = rng.standard_normal(out.shape) + 1j * rng.standard_normal(out.shape)
+    dA, db, dc = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    assert np.allclose(dA, dA.T, atol=1e-14)
+    h = 1e-6
+    L = lambda Av, bv, cv: float(np.real(np.sum(np.conj(g) * O.fock_diag(Av, bv, cv, cut, mask))))
+    for _ in range(4):
+        EA = rng.standard_normal(A.shape) + 1j * rng.standard_normal(A.shape)
+        EA = 0.5 * (EA + EA.T)
+        Eb = rng.standard_normal(2 * M) + 1j * rng.standard_normal(2 * M)
+        Ec = complex(rng.standard_normal(), rng.standard_normal())
+        fd = (L(A + h * EA, b + h * Eb, c + h * Ec) - L(A - h * EA, b - h * Eb, c - h * Ec)) / (2 * h)
+        pred = float(np.real(np.sum(np.conj(dA) * EA) + np.sum(np.conj(db) * Eb) + np.conj(dc) * Ec))
+        assert abs(fd - pred) <= 1e-7 * max(1.0, abs(pred))
+
+
+@pytest.mark.parametrize("M,cut,alpha", [(2, [4, 3], 0.0), (3, [3, 3, 2], 0.3), (3, [2, 4, 3], 0.0)])
+def test_probs_vjp_pure_matches_full_box_adjoint(M, cut, alpha):
+    # the full-size pure-state adjoint (state-vector products) against the
+    # closed-form adjoint evaluated on the full density-matrix box of the same
+    # (pure) triple, for a dense cotangent of every detection probability
+    ci = W.pure_state(70 + M, M, cut, alpha_var=alpha)
+    A, b, c = ci.params["rho_triple"]
+    psi = O.state_vector(ci.A, ci.b, ci.c, cut)
+    p = O.detection_probs(A, b, c, cut)
+    np.testing.assert_allclose(p, np.abs(psi) ** 2, atol=1e-15)
+    rng = np.random.default_rng(5 + M)
+    g = rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)
+    ref = O.fock_diag_vjp(A, b, c, cut, (1 << M) - 1, g)
+    got = O.probs_vjp_pure(psi, c, g)
+    for x, r in zip(got, ref):
+        np.testing.assert_allclose(x, r, rtol=1e-12, atol=1e-14 * np.max(np.abs(ref[0])))
