@@ -157,6 +157,30 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c,
                         void* dA, void* db, void* dc, void* workspace, size_t ws_bytes,
                         hipStream_t stream);
 
+/* fock_diag_fwd_static -- fock_diag_fwd without a caller workspace and
+ * without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The sweep's intermediates go to a library-owned static device
+ * array of 64 MiB (one per device, held from module load until the process
+ * ends); its address is resolved on the first call on each device
+ * (hipGetSymbolAddress, no allocation: make that first call outside a graph
+ * capture).  Same arguments and result as fock_diag_fwd with saved == NULL.
+ *   - Errors (host side, nothing launched): FD_ERR_WORKSPACE if the sweep
+ *     needs more than 64 MiB (fd_plan_workspace with with_vjp = 0 reports
+ *     the need), FD_ERR_INVALID_ARG for NULL or misaligned pointers and for a
+ *     plan whose device tables do not exist yet on the current device (make
+ *     one fock_diag_fwd / detection_probs / fock_diag_vjp / fock_diag_jvp
+ *     call with the plan there first).
+ *   - b is never read on the host: the b = 0 schedule is taken only for
+ *     plans created with FD_B_ZERO; FD_B_AUTO plans take the general
+ *     schedule (same amplitudes).  No graph replay and no per-kernel timing.
+ *   - Every call on one device shares that device's array, which keeps the
+ *     last call's contents (the sweep writes every entry before reading it):
+ *     calls that overlap in time on one device race and give wrong results;
+ *     serialise them (one stream, or events). */
+fd_status fock_diag_fwd_static(fd_plan p, const void* A, const void* b, const void* c, void* rho,
+                               hipStream_t stream);
+
 /* Forward mode (Sec. 2.5, the tangent recurrences summed along one
  * direction): rho and its directional derivative
  *     drho = sum_ij dA_ij d rho / d A_ij + sum_i db_i d rho / d b_i + dc d rho / d c

@@ -30,7 +30,7 @@ EXPORTS = [
     "fock_diag_vjp_batch", "fd_state_plan_create", "fd_state_plan_destroy", "fd_state_plan_workspace",
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
     "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
-    "fock_state_vjp", "fock_state_jvp", "fd_plan_jvp_workspace", "fock_diag_jvp",
+    "fock_state_vjp", "fock_state_jvp", "fd_plan_jvp_workspace", "fock_diag_jvp", "fock_diag_fwd_static",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -70,6 +70,7 @@ def lib():
     L.fd_plan_workspace.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     L.fd_plan_query.argtypes = [vp, i32, i64p]
     L.fock_diag_fwd.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, sz, vp]
+    L.fock_diag_fwd_static.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fock_diag_vjp.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp, vp, vp, sz, vp]
     L.detection_probs.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.fock_diag_fwd_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -286,6 +287,11 @@ def fd_state_plan_kernel_times(plan, kind):
 def fock_diag_fwd(plan, A, b, c, rho, workspace, saved=None, stream=None):
     _check(lib().fock_diag_fwd(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(rho), _ptr(workspace),
                                _nbytes(workspace), _ptr(saved), _nbytes(saved), _stream(stream)))
+
+
+def fock_diag_fwd_static(plan, A, b, c, rho, stream=None):
+    """fock_diag_fwd with the library's static scratch (no allocation)."""
+    _check(lib().fock_diag_fwd_static(plan.handle, _ptr(A), _ptr(b), _ptr(c), _ptr(rho), _stream(stream)))
 
 
 def fock_diag_jvp(plan, A, b, c, dA, db, dc, rho, drho, workspace, stream=None):
