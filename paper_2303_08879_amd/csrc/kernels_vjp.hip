@@ -107,84 +107,78 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
     st(g0 + node_of_cindex(P, spn, slv, (int)idx), ld(drho + idx));
 }
 
-constexpr int kWRec = 16;
+// Records per staging batch of the point and block reverse kernels.
+constexpr int kPointBatch = 32;
+constexpr int kBlockBatch = 32;
 
-// records: H rows NPD (detected write positions), X rows NR (NQ undetected
-// reads, NPD detected reads, pivot value).  Pair p = i * NR + l.  Rows are
-// kWRec + 1 elements apart so that the rows read together by one wavefront
-// fall in different LDS banks; four partial sums per pair keep the FMA chain
-// short (combined in a fixed order).
-constexpr int kWStride = kWRec + 1;
+// Abar / bbar: every reverse step reduces outer products of per-target
+// records (the target cotangents h and the read values x of one pivot
+// application) over all targets: D[i][l] = sum_rec h_i conj(x_l), i.e.
+// (H^T X-bar)[i][l], a dense contraction over the records.  A wavefront
+// stages NB records in LDS (row r of H or X holds value r of every record,
+// rows NB + 1 apart so the rows read together fall in different banks) and
+// runs NB / 4 FP64 MFMA 16x16x4 steps of four records: lane t feeds value
+// t % 16 of record k0 + t / 16 to both operands (one 16-byte LDS read each)
+// and keeps D[4 j + t / 16][16 c + t % 16], j = 0..3, of column tile c in its
+// accumulators (the gfx950 output layout, checked on the device).  Real part
+// Hr Xr + Hi Xi, imaginary part Hi Xr - Hr Xi.  The hardware fixes the order
+// of accumulation, so the sums are reproducible.  At most 16 rows of H
+// (NPD) and 32 columns of X (NCOL).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-template <typename R, int NPD, int NR, int PPL>
-__device__ __forceinline__ void wave_accum(cx<R>* recw, const cx<R>* h, const cx<R>* x, bool have,
-                                           cx<double>* acc) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long bal = __ballot(have);
-#pragma unroll 1
-  for (int half = 0; half < 64 / kWRec; ++half) {
-    const unsigned long long hm = (bal >> (half * kWRec)) & ((1ull << kWRec) - 1);
-    if (hm == 0ull) continue;   // uniform over the wave
-    if (lane / kWRec == half) {
-      const int e = lane % kWRec;
+template <int NT>
+struct MfmaAcc {
+  mfma_d4 re[NT], im[NT];
+};
+
+template <int NT>
+__device__ __forceinline__ void mfma_acc_zero(MfmaAcc<NT>& a) {
 #pragma unroll
-      for (int i = 0; i < NPD; ++i) recw[i * kWStride + e] = have ? h[i] : czero<R>();
-#pragma unroll
-      for (int l = 0; l < NR; ++l) recw[(NPD + l) * kWStride + e] = have ? x[l] : czero<R>();
-    }
-    wave_sync();
-#pragma unroll
-    for (int pp = 0; pp < PPL; ++pp) {
-      const int p = lane + 64 * pp;
-      if (p < NPD * NR) {
-        const int i = p / NR, l = p - (p / NR) * NR;
-        const cx<R>* H = recw + i * kWStride;
-        const cx<R>* X = recw + (NPD + l) * kWStride;
-        double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int e = 0; e < kWRec; ++e) {
-          const cx<R> hv = H[e], xv = X[e];
-          ax[e & 3] = fma((double)xv.x, (double)hv.x, ax[e & 3]);
-          ax[e & 3] = fma((double)xv.y, (double)hv.y, ax[e & 3]);
-          ay[e & 3] = fma((double)xv.x, (double)hv.y, ay[e & 3]);
-          ay[e & 3] = fma(-(double)xv.y, (double)hv.x, ay[e & 3]);
-        }
-        acc[pp].x += (ax[0] + ax[1]) + (ax[2] + ax[3]);
-        acc[pp].y += (ay[0] + ay[1]) + (ay[2] + ay[3]);
-      }
-    }
-    wave_sync();
+  for (int t = 0; t < NT; ++t) {
+    a.re[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    a.im[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
   }
 }
 
-// Point reverse kernel: every lane owns one record column of its
-// wavefront's staging area (kPRec = 64 columns, rows kPRec + 1 apart), and
-// writes each value there as soon as it exists -- the read values X are never
-// held in registers, which keeps the 8-mode kernel out of scratch memory.
-constexpr int kPRec = 64;
-constexpr int kPStride = kPRec + 1;
-
-template <typename R, int NPD, int NR, int PPL>
-__device__ __forceinline__ void wave_accum_staged(const cx<R>* recw, cx<double>* acc) {
+template <typename R, int NPD, int NCOL, int NB>
+__device__ __forceinline__ void wave_accum_mfma(const cx<R>* recw, MfmaAcc<(NCOL + 15) / 16>& acc) {
+  static_assert(NPD <= 16 && NCOL <= 32, "one row tile of H, at most two column tiles of X");
+  constexpr int NT = (NCOL + 15) / 16;
+  constexpr int RS = NB + 1;   // records per staging batch, padded row stride
   const int lane = threadIdx.x & 63;
+  const int row = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const int rc = k0 + kq;
+    const cx<R> h = row < NPD ? recw[row * RS + rc] : czero<R>();
+    const double hx = (double)h.x, hy = (double)h.y;
 #pragma unroll
-  for (int pp = 0; pp < PPL; ++pp) {
-    const int p = lane + 64 * pp;
-    if (p < NPD * NR) {
-      const int i = p / NR, l = p - (p / NR) * NR;
-      const cx<R>* H = recw + i * kPStride;
-      const cx<R>* X = recw + (NPD + l) * kPStride;
-      double ax[4] = {0.0, 0.0, 0.0, 0.0}, ay[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-      for (int e = 0; e < kPRec; ++e) {
-        const cx<R> hv = H[e], xv = X[e];
-        ax[e & 3] = fma((double)xv.x, (double)hv.x, ax[e & 3]);
-        ax[e & 3] = fma((double)xv.y, (double)hv.y, ax[e & 3]);
-        ay[e & 3] = fma((double)xv.x, (double)hv.y, ay[e & 3]);
-        ay[e & 3] = fma(-(double)xv.y, (double)hv.x, ay[e & 3]);
-      }
-      acc[pp].x += (ax[0] + ax[1]) + (ax[2] + ax[3]);
-      acc[pp].y += (ay[0] + ay[1]) + (ay[2] + ay[3]);
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * t + row;
+      const cx<R> x = col < NCOL ? recw[(NPD + col) * RS + rc] : czero<R>();
+      const double xx = (double)x.x, xy = (double)x.y;
+      acc.re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hx, xx, acc.re[t], 0, 0, 0);
+      acc.im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hy, xx, acc.im[t], 0, 0, 0);
+      acc.re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hy, xy, acc.re[t], 0, 0, 0);
+      acc.im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-hx, xy, acc.im[t], 0, 0, 0);
+    }
+  }
+}
+
+// Writes this lane's accumulated pairs into red[i * NR + l] (a wave's NPD x NR
+// pair table); pairs beyond NCOL columns are the caller's (they stay unset).
+template <int NPD, int NR, int NCOL>
+__device__ __forceinline__ void mfma_acc_store(const MfmaAcc<(NCOL + 15) / 16>& acc, cx<double>* red) {
+  constexpr int NT = (NCOL + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int col0 = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int l = 16 * t + col0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = 4 * j + kq;
+      if (i < NPD && l < NCOL) red[i * NR + l] = cmake<double>(acc.re[t][j], acc.im[t][j]);
     }
   }
 }
@@ -201,32 +195,39 @@ __device__ __forceinline__ void load_tables_v(const DevPlan& P, int* spn, R* sq,
 
 // ---------------------------------------------------------------------------
 // Algorithm 1 reverse step: one thread per lattice point.
+// For each pivot the lane gathers the cotangents h of its targets, forms the
+// adjoint of the reads (u = A^H h, with A and b read through uniform loads,
+// so they live in scalar registers instead of LDS or vector registers) and
+// writes the read cotangents.  The Abar / bbar records (h and the read
+// values x, which only the reduction needs) are staged NB lanes at a time in
+// the wave's LDS area and reduced on the matrix cores: a smaller batch keeps
+// the staging area, and so the LDS per wave, small enough for several waves
+// per SIMD; the read values of a lane are loaded when its batch is staged.
 // ---------------------------------------------------------------------------
-template <int MD, bool ODD, typename R>
+template <int MD, bool ODD, typename R, int NB>
 __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         double2* __restrict__ partial) {
   constexpr int NP = 2 * MD;
   constexpr int NR = NP + 1;
   constexpr int NPAIR = NP * NR;
-  constexpr int PPL = (NPAIR + 63) / 64;
+  constexpr int RS = NB + 1;   // padded row stride of the staging area
+  static_assert(NB % 4 == 0 && 64 % NB == 0, "batches of whole MFMA steps that tile the wavefront");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<R>* rec = reinterpret_cast<cx<R>*>(smem_raw);                   // waves x kPStride x (NP + NR)
-  cx<R>* sA = rec + (size_t)(kThreads / 64) * kPStride * (NP + NR);  // A (NP x NP) then b (NP)
-  const cx<R>* sb = sA + NP * NP;
-  R* sq = reinterpret_cast<R*>(sA + NP * NP + NP);
+  cx<R>* rec = reinterpret_cast<cx<R>*>(smem_raw);                 // waves x RS x (NP + NR)
+  R* sq = reinterpret_cast<R*>(rec + (size_t)(kThreads / 64) * RS * (NP + NR));
   R* isq = sq + (kMaxCut + 4);
   int* spn = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   load_tables_v(P, spn, sq, isq);
-  for (int i = threadIdx.x; i < NP * NP + NP; i += blockDim.x) sA[i] = ld(Ai + i);
   __syncthreads();
-  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * kPStride * (NP + NR);
+  cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * RS * (NP + NR);
   const int lane = threadIdx.x & 63;
-  cx<double> acc[PPL];
-#pragma unroll
-  for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
+  // columns of X that can be non-zero: the pivot value (bbar) only when odd
+  // levels are swept
+  constexpr int NCOL = ODD ? NR : NP;
+  MfmaAcc<(NCOL + 15) / 16> acc;
+  mfma_acc_zero(acc);
   const int pnw = P.pnw;
-  auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * kPStride + lane] = v; };
 
   for (int base = blockIdx.x * kThreads; base < nwork; base += gridDim.x * kThreads) {
     const int r = base + threadIdx.x;
@@ -256,9 +257,6 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
       cx<R> h[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) h[i] = czero<R>();
-      // reads x: staged as they are formed (zero rows where this pivot reads nothing)
-#pragma unroll
-      for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
       if (valid) {
         // (no level above the last one under a total photon cutoff)
         if (V.gf0nxt) h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
@@ -270,22 +268,12 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_1001(MD, K, j)], (uint32_t)r)), isq[m[j] + 1]);
           }
         }
-        stx(2 * K, cscale(G0, sq[m[K] + 1]));
-        if (m[K] > 0) stx(2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]));
-#pragma unroll
-        for (int j = K + 1; j < MD; ++j) {
-          if (m[j] > 0) {
-            stx(2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
-            stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
-          }
-        }
-        if (ODD) stx(NP, ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r)));
         // adjoint of the reads
 #pragma unroll
         for (int l = 2 * K; l < NP; ++l) {
           cx<R> u = czero<R>();
 #pragma unroll
-          for (int i = 2 * K; i < NP; ++i) cfma_conj(u, sA[i * NP + l], h[i]);
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
           const int j = l >> 1;
           if (l == 2 * K) {
             g0acc = cadd(g0acc, cscale(u, sq[m[K] + 1]));
@@ -298,16 +286,40 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         if (ODD) {
           cx<R> gp = czero<R>();
 #pragma unroll
-          for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
+          for (int i = 2 * K; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
           const bool has_diag_reader = (K > 0) || (m[0] + 1 <= P.CD[0] - 2);
           ykg[K] = has_diag_reader ? cadd(ld(at32(V.gcur[fam_f1k(K)], (uint32_t)r)), gp) : gp;
         }
       }
+      // Abar records of this pivot, NB lanes at a time
+#pragma unroll 1
+      for (int q = 0; q < 64 / NB; ++q) {
+        const bool grp = (lane / NB) == q;
+        if (__ballot(valid && grp) == 0ull) continue;   // uniform over the wave
+        if (grp) {
+          const int col = lane - q * NB;
+          auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * RS + col] = v; };
 #pragma unroll
-      for (int i = 0; i < NP; ++i) recw[i * kPStride + lane] = h[i];
-      wave_sync();
-      if (__ballot(valid) != 0) wave_accum_staged<R, NP, NR, PPL>(recw, acc);
-      wave_sync();
+          for (int l = 0; l < NCOL; ++l) stx(l, czero<R>());
+          if (valid) {
+            stx(2 * K, cscale(G0, sq[m[K] + 1]));
+            if (m[K] > 0) stx(2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]));
+#pragma unroll
+            for (int j = K + 1; j < MD; ++j) {
+              if (m[j] > 0) {
+                stx(2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
+                stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
+              }
+            }
+            if (ODD) stx(NP, ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r)));
+          }
+#pragma unroll
+          for (int i = 0; i < NP; ++i) recw[i * RS + col] = h[i];
+        }
+        wave_sync();
+        wave_accum_mfma<R, NP, NCOL, NB>(recw, acc);
+        wave_sync();
+      }
     }
 
     if (ODD) {
@@ -316,8 +328,6 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         cx<R> h[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) h[i] = czero<R>();
-#pragma unroll
-        for (int l = 0; l <= NP; ++l) stx(l, czero<R>());
         if (valid) {
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
@@ -328,48 +338,63 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
             }
             const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
             if (okb) h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_f1b(MD, j)], (uint32_t)r)), isq[m[j] + 1]);
-            if (m[j] > 0) {
-              stx(2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]));
-              stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]));
-            }
           }
-          stx(NP, G0);
 #pragma unroll
           for (int l = 0; l < NP; ++l) {
             const int j = l >> 1;
             if (m[j] == 0) continue;
             cx<R> u = czero<R>();
 #pragma unroll
-            for (int i = 0; i < NP; ++i) cfma_conj(u, sA[i * NP + l], h[i]);
+            for (int i = 0; i < NP; ++i) cfma_conj(u, ld(Ai + i * NP + l), h[i]);
             st(at32(V.gprev[(l & 1) ? fam_f1k(j) : fam_f1b(MD, j)], (uint32_t)rdn[j]), cscale(u, sq[m[j]]));
           }
           cx<R> gp = czero<R>();
 #pragma unroll
-          for (int i = 0; i < NP; ++i) cfma_conj(gp, sb[i], h[i]);
+          for (int i = 0; i < NP; ++i) cfma_conj(gp, ld(bi + i), h[i]);
           g0acc = cadd(g0acc, gp);
         }
+#pragma unroll 1
+        for (int q = 0; q < 64 / NB; ++q) {
+          const bool grp = (lane / NB) == q;
+          if (__ballot(valid && grp) == 0ull) continue;
+          if (grp) {
+            const int col = lane - q * NB;
+            auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * RS + col] = v; };
 #pragma unroll
-        for (int i = 0; i < NP; ++i) recw[i * kPStride + lane] = h[i];
-        wave_sync();
-        if (__ballot(valid) != 0) wave_accum_staged<R, NP, NR, PPL>(recw, acc);
-        wave_sync();
+            for (int l = 0; l < NCOL; ++l) stx(l, czero<R>());
+            if (valid) {
+#pragma unroll
+              for (int j = 0; j < MD; ++j) {
+                if (m[j] > 0) {
+                  stx(2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]));
+                  stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]));
+                }
+              }
+              stx(NP, G0);
+            }
+#pragma unroll
+            for (int i = 0; i < NP; ++i) recw[i * RS + col] = h[i];
+          }
+          wave_sync();
+          wave_accum_mfma<R, NP, NCOL, NB>(recw, acc);
+          wave_sync();
+        }
       }
     }
     if (live) st(at32(V.gcur[0], (uint32_t)r), g0acc);
   }
-  // fold the per-lane pair sums over the waves (fixed order) into this block's slot
+  // fold the per-wave pair tables (fixed order) into this block's slot
   cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
   __syncthreads();
-#pragma unroll
-  for (int pp = 0; pp < PPL; ++pp) red[(size_t)(threadIdx.x >> 6) * 64 * PPL + pp * 64 + (threadIdx.x & 63)] = acc[pp];
+  mfma_acc_store<NP, NR, NCOL>(acc, red + (size_t)(threadIdx.x >> 6) * NPAIR);
   __syncthreads();
   double2* slot = partial + (size_t)blockIdx.x * NPAIR;
   for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
-    const int pp = p / 64, lane = p - pp * 64;
+    if (p - (p / NR) * NR >= NCOL) continue;   // the bbar column without odd levels: zero
     double sx = 0.0, sy = 0.0;
     for (int wv = 0; wv < kThreads / 64; ++wv) {
-      sx += red[(size_t)wv * 64 * PPL + pp * 64 + lane].x;
-      sy += red[(size_t)wv * 64 * PPL + pp * 64 + lane].y;
+      sx += red[(size_t)wv * NPAIR + p].x;
+      sy += red[(size_t)wv * NPAIR + p].y;
     }
     const double2 v = slot[p];
     slot[p] = make_double2(v.x + sx, v.y + sy);
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 // time in its own LDS region and each lane accumulates fixed (i, l) pairs in
 // registers for the whole kernel; no workgroup barrier is involved.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R>
+template <int MD, int NQ, typename R, int NB>
 __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         ChunkGeo G, double2* __restrict__ partial) {
@@ -395,14 +420,12 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   constexpr int NPOS = NQ + NPD;
   constexpr int NR = NPOS + 1;
   constexpr int NPAIR = NPD * NR;
-  constexpr int PPL = (NPAIR + 63) / 64;
-  // From records of 17 values on (four detected modes, or three with two
-  // undetected modes), the read values go straight to this lane's column of a
-  // 64-record staging area instead of registers (as in the point kernel): the
-  // wide units would otherwise spill.  Below that the kernel is LDS-bound and
-  // keeps the smaller 32-record staging.
-  constexpr bool STG = NPD + NR >= 17;
-  constexpr int RS = STG ? kPStride : kWStride;
+  // Abar / bbar records (the target cotangents h and the read values x of
+  // one entry) are staged NB lanes at a time and reduced on the matrix cores,
+  // as in the point kernel; the read values of a lane are formed when its
+  // batch is staged.
+  constexpr int RS = NB + 1;
+  static_assert(NB % 4 == 0 && 64 % NB == 0, "batches of whole MFMA steps that tile the wavefront");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int B = P.B, R0 = G.R0, RC = G.RC;
   const int nrow1 = (RC + 1) * R0, nrow2 = (RC + 2) * R0;
@@ -428,9 +451,8 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   // loop and a barrier before it reads these tables)
   cx<R>* recw = rec + (size_t)(threadIdx.x >> 6) * RS * (NPD + NR);
   const int lane = threadIdx.x & 63;
-  cx<double> acc[PPL];
-#pragma unroll
-  for (int pp = 0; pp < PPL; ++pp) acc[pp] = cmake<double>(0.0, 0.0);
+  MfmaAcc<(NR + 15) / 16> acc;
+  mfma_acc_zero(acc);
 
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
@@ -459,25 +481,10 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
-        cx<R> h[NPD], x[STG ? 1 : NR];
-        auto setx = [&](int l, const cx<R>& v) {
-          if constexpr (STG)
-            recw[(NPD + l) * kPStride + lane] = v;
-          else
-            x[l] = v;
-        };
+        cx<R> h[NPD];
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
-#pragma unroll
-        for (int l = 0; l < NR; ++l) setx(l, czero<R>());
         if (live) {
-          int kap[NQ];
-          int rem = e;
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            kap[q] = ucoord(P, rem, q);
-            rem -= kap[q] * P.ustride[q];
-          }
           h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)(rup[K] * B + e))), isq[m[K] + 1]);
           if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(at32(V.gcur[fam_f2(MD, K)], (uint32_t)(r * B + e))), isq[m[K] + 2]);
 #pragma unroll
@@ -501,21 +508,6 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             gbv[e - e_own0] = gb;
           }
           if (own) {
-            const int lf = e - (k0 - 1) * R0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-              if (kap[q] > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kap[q]]));
-            setx(NPOS, lfw[lf]);
-            setx(NQ + 2 * K, cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]));
-            if (m[K] > 0)
-              setx(NQ + 2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]));
-#pragma unroll
-            for (int j = K + 1; j < MD; ++j) {
-              if (m[j] > 0) {
-                setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-              }
-            }
 #pragma unroll
             for (int l = 2 * K; l < NPD; ++l) {
               const int j = l >> 1;
@@ -534,14 +526,44 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             }
           }
         }
-        if constexpr (STG) {
+        // Abar records of the own entries, NB lanes at a time
+        const bool rec_ok = live && own;
+#pragma unroll 1
+        for (int qb = 0; qb < 64 / NB; ++qb) {
+          const bool grp = (lane / NB) == qb;
+          if (__ballot(rec_ok && grp) == 0ull) continue;   // uniform over the wave
+          if (grp) {
+            const int col = lane - qb * NB;
+            auto setx = [&](int l, const cx<R>& v) { recw[(NPD + l) * RS + col] = v; };
 #pragma unroll
-          for (int i = 0; i < NPD; ++i) recw[i * kPStride + lane] = (live && own) ? h[i] : czero<R>();
+            for (int l = 0; l < NR; ++l) setx(l, czero<R>());
+            if (rec_ok) {
+              const int lf = e - (k0 - 1) * R0;
+              int rem = e;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+                const int kq = ucoord(P, rem, q);
+                rem -= kq * P.ustride[q];
+                if (kq > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kq]));
+              }
+              setx(NPOS, lfw[lf]);
+              setx(NQ + 2 * K, cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]));
+              if (m[K] > 0)
+                setx(NQ + 2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]));
+#pragma unroll
+              for (int j = K + 1; j < MD; ++j) {
+                if (m[j] > 0) {
+                  setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                  setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                }
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < NPD; ++i) recw[i * RS + col] = rec_ok ? h[i] : czero<R>();
+          }
           wave_sync();
-          if (__ballot(live && own) != 0) wave_accum_staged<R, NPD, NR, PPL>(recw, acc);
+          wave_accum_mfma<R, NPD, NR, NB>(recw, acc);
           wave_sync();
-        } else {
-          wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
         }
       }
       __syncthreads();
@@ -573,25 +595,10 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
-        cx<R> h[NPD], x[STG ? 1 : NR];
-        auto setx = [&](int l, const cx<R>& v) {
-          if constexpr (STG)
-            recw[(NPD + l) * kPStride + lane] = v;
-          else
-            x[l] = v;
-        };
+        cx<R> h[NPD];
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
-#pragma unroll
-        for (int l = 0; l < NR; ++l) setx(l, czero<R>());
         if (live) {
-          int kap[NQ];
-          int rem = e;
-#pragma unroll
-          for (int q = 0; q < NQ; ++q) {
-            kap[q] = ucoord(P, rem, q);
-            rem -= kap[q] * P.ustride[q];
-          }
           const int le = e - e_own0;
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
@@ -611,18 +618,6 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             qv[(size_t)q * nrow2 + le] = u;
           }
           if (own) {
-            const int lf = e - (k0 - 1) * R0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-              if (kap[q] > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kap[q]]));
-            setx(NPOS, lfw[lf]);
-#pragma unroll
-            for (int j = 0; j < MD; ++j) {
-              if (m[j] > 0) {
-                setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-              }
-            }
 #pragma unroll
             for (int l = 0; l < NPD; ++l) {
               const int j = l >> 1;
@@ -638,14 +633,41 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
             g0a[le] = cadd(g0a[le], gb);
           }
         }
-        if constexpr (STG) {
+        // Abar records of the own entries, NB lanes at a time
+        const bool rec_ok = live && own;
+#pragma unroll 1
+        for (int qb = 0; qb < 64 / NB; ++qb) {
+          const bool grp = (lane / NB) == qb;
+          if (__ballot(rec_ok && grp) == 0ull) continue;   // uniform over the wave
+          if (grp) {
+            const int col = lane - qb * NB;
+            auto setx = [&](int l, const cx<R>& v) { recw[(NPD + l) * RS + col] = v; };
 #pragma unroll
-          for (int i = 0; i < NPD; ++i) recw[i * kPStride + lane] = (live && own) ? h[i] : czero<R>();
+            for (int l = 0; l < NR; ++l) setx(l, czero<R>());
+            if (rec_ok) {
+              const int lf = e - (k0 - 1) * R0;
+              int rem = e;
+#pragma unroll
+              for (int q = 0; q < NQ; ++q) {
+                const int kq = ucoord(P, rem, q);
+                rem -= kq * P.ustride[q];
+                if (kq > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kq]));
+              }
+              setx(NPOS, lfw[lf]);
+#pragma unroll
+              for (int j = 0; j < MD; ++j) {
+                if (m[j] > 0) {
+                  setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                  setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
+                }
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < NPD; ++i) recw[i * RS + col] = rec_ok ? h[i] : czero<R>();
+          }
           wave_sync();
-          if (__ballot(live && own) != 0) wave_accum_staged<R, NPD, NR, PPL>(recw, acc);
+          wave_accum_mfma<R, NPD, NR, NB>(recw, acc);
           wave_sync();
-        } else {
-          wave_accum<R, NPD, NR, PPL>(recw, h, x, live && own, acc);
         }
       }
       __syncthreads();
@@ -665,24 +687,17 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
     for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) st(at32(V.gcur[0], (uint32_t)(r * B + e)), g0a[e - e_own0]);
     __syncthreads();
   }
-  // fold the per-lane pair sums over the waves (fixed order) into this block's slot
+  // fold the wave's pair table into this block's slot (one wavefront per block)
   cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
   __syncthreads();
-#pragma unroll
-  for (int pp = 0; pp < PPL; ++pp) red[(size_t)(threadIdx.x >> 6) * 64 * PPL + pp * 64 + (threadIdx.x & 63)] = acc[pp];
+  mfma_acc_store<NPD, NR, NR>(acc, red);
   __syncthreads();
   double2* slot = partial + (size_t)blockIdx.x * (NPOS * NR);
   for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
-    const int pp = p / 64, lane = p - pp * 64;
-    double sx = 0.0, sy = 0.0;
-    for (int wv = 0; wv < kBT / 64; ++wv) {
-      sx += red[(size_t)wv * 64 * PPL + pp * 64 + lane].x;
-      sy += red[(size_t)wv * 64 * PPL + pp * 64 + lane].y;
-    }
     const int i = p / NR, l = p - (p / NR) * NR;
     const int q = (NQ + i) * NR + l;
     const double2 v = slot[q];
-    slot[q] = make_double2(v.x + sx, v.y + sy);
+    slot[q] = make_double2(v.x + red[p].x, v.y + red[p].y);
   }
 }
 
@@ -910,9 +925,8 @@ static size_t vjp_lds_bytes_g(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
   const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
   const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                      (size_t)(kBT / 64) * (NPD + NR >= 17 ? kPStride : kWStride) * (NPD + NR);
-  const size_t ppl = (size_t)(NPD * NR + 63) / 64;
-  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)kBT * ppl * 16) + 2 * (kMaxCut + 4) * rb;
+                      (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
+  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
 }
 size_t vjp_lds_bytes(const Plan& Pl) {
   return std::max(vjp_lds_bytes_g(Pl, chunk_geo_v(Pl)), vjp_lds_bytes_g(Pl, chunk_geo_v(Pl, kBT / 2)));
@@ -1009,25 +1023,23 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     KTimer kt(Pl, KK_VJP_LEVEL, st);
     if (Pl.B == 1) {
       const int NP = 2 * MD;
-      const size_t ppl = (size_t)(NP * (NP + 1) + 63) / 64;
-      const size_t shm = std::max(((size_t)(kThreads / 64) * kPStride * (2 * NP + 1) + (size_t)NP * (NP + 1)) *
-                                      sizeof(cx<R>),
-                                  (size_t)kThreads * ppl * sizeof(cx<double>)) + tab;
+      const size_t shm = std::max((size_t)(kThreads / 64) * (kPointBatch + 1) * (2 * NP + 1) * sizeof(cx<R>),
+                                  (size_t)(kThreads / 64) * NP * (NP + 1) * sizeof(cx<double>)) + tab;
       const int grid = (int)std::min<int64_t>((nwork + kThreads - 1) / kThreads, kPartialSlots - 1);
 #define FD_VJP_POINT(MDV)                                                                                        \
   case MDV:                                                                                                      \
     if (odd) {                                                                                                   \
       if (shm > 65536)                                                                                           \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, true, R>),                    \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, true, R, kPointBatch>),       \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                         \
-      hipLaunchKernelGGL((k_vjp_point<MDV, true, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,   \
-                         nwork, partial);                                                                        \
+      hipLaunchKernelGGL((k_vjp_point<MDV, true, R, kPointBatch>), dim3(grid), dim3(kThreads), shm, st, P, Vp, \
+                         Ai, bi, S, nwork, partial);                                                             \
     } else {                                                                                                     \
       if (shm > 65536)                                                                                           \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, false, R>),                   \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_point<MDV, false, R, kPointBatch>),      \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                         \
-      hipLaunchKernelGGL((k_vjp_point<MDV, false, R>), dim3(grid), dim3(kThreads), shm, st, P, Vp, Ai, bi, S,  \
-                         nwork, partial);                                                                        \
+      hipLaunchKernelGGL((k_vjp_point<MDV, false, R, kPointBatch>), dim3(grid), dim3(kThreads), shm, st, P,    \
+                         Vp, Ai, bi, S, nwork, partial);                                                         \
     }                                                                                                            \
     break;
       switch (MD) {
@@ -1053,16 +1065,16 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   case MDV:                                                                                                     \
     if (Pl.nq == 2) {                                                                                           \
       if (shm > 65536)                                                                                          \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R>),                      \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R, kBlockBatch>),         \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,          \
-                         nwork, G, partial);                                                                    \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, \
+                         S, nwork, G, partial);                                                                 \
     } else {                                                                                                    \
       if (shm > 65536)                                                                                          \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R>),                      \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R, kBlockBatch>),         \
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,          \
-                         nwork, G, partial);                                                                    \
+      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, \
+                         S, nwork, G, partial);                                                                 \
     }                                                                                                           \
     break;
       switch (MD) {

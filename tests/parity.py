@@ -5,8 +5,12 @@ The bar in complex128 is a relative error of 1e-10.  Every comparison checks
   * entry by entry, on the entries with |r| >= floor * max|r|:
                    |x - r| <= tol * |r|;
   * the remaining (tiny) entries in absolute terms:
-                   |x - r| <= tol * floor * max|r|,
+                   |x - r| <= SMALL_ABS * max|r|,
 so an error confined to small entries cannot hide behind the large ones.
+SMALL_ABS = 1e-14 is about 45 units in the last place of the largest entry:
+tiny entries come out of sums of terms as large as that entry, so their
+rounding is measured on its scale (the full 8-mode pure-state forward, 16.8M
+entries, shows 3.9e-16).
 The measured figures are printed (pytest -s / -v logs keep them).
 """
 from __future__ import annotations
@@ -15,6 +19,7 @@ import numpy as np
 
 TOL = 1e-10
 FLOOR = 1e-6
+SMALL_ABS = 1e-14
 
 
 def compare(got, ref, floor=FLOOR):
@@ -43,7 +48,7 @@ def assert_close(got, ref, tol=TOL, floor=FLOOR, label=""):
           f"elementwise={s['elementwise_large']:.2e} small_abs/max={s['small_abs_over_max']:.2e}", flush=True)
     assert s["normwise"] <= tol, (label, s)
     assert s["elementwise_large"] <= tol, (label, s)
-    assert s["small_abs_over_max"] <= tol * floor, (label, s)
+    assert s["small_abs_over_max"] <= max(tol * floor, SMALL_ABS), (label, s)
     return s
 
 
