@@ -51,30 +51,45 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# Sources each level kernel is compiled from: a counter summary applies to a
+# kernel only while these hash to the value recorded with it.
+KERNEL_SOURCES = {
+    "k_vjp_point": ["kernels_vjp.hip", "fd_device.h"],
+    "k_vjp_block": ["kernels_vjp.hip", "fd_device.h"],
+    "k_fwd_point": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
+    "k_fwd_block": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
+    "k_state_level": ["kernels_state.hip", "fd_device.h"],
+}
+
+
+def kernel_source_hash(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(HERE, "paper_2303_08879_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload_name, kernel):
     """HBM bytes per launch of `kernel` on `workload_name` from the committed
     rocprofv3 counter summary profiles/hbm_traffic_<workload>.md (FETCH_SIZE
     and WRITE_SIZE per dispatch, each scaled by what the counter reads for a
-    plain copy of known size), or None when no summary covers it or the kernel
-    sources changed since the counters were taken."""
+    plain copy of known size), or None when no summary covers it or the
+    kernel's sources changed since the counters were taken."""
     path = os.path.join(HERE, "profiles", f"hbm_traffic_{workload_name}.md")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "paper_2303_08879_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
     vals = {}
     for line in open(path):
         parts = line.split()
-        if len(parts) >= 2 and parts[0] in ("source_sha256_16", "fetch_scale", "write_scale"):
-            vals[parts[0]] = parts[1]
-        elif len(parts) == 4 and parts[0] == "kib":
-            vals[parts[1]] = (float(parts[2]), float(parts[3]))
-    if vals.get("source_sha256_16") != h.hexdigest()[:16] or kernel not in vals:
+        if len(parts) >= 2 and parts[0] in ("fetch_scale", "write_scale"):
+            vals[parts[0]] = float(parts[1])
+        elif len(parts) == 5 and parts[0] == "kib":
+            vals[parts[1]] = (float(parts[2]), float(parts[3]), parts[4])
+    if kernel not in vals or vals[kernel][2] != kernel_source_hash(kernel):
         return None
-    fetch, write = vals[kernel]
-    return 1024.0 * (fetch * float(vals["fetch_scale"]) + write * float(vals["write_scale"]))
+    fetch, write, _ = vals[kernel]
+    return 1024.0 * (fetch * vals["fetch_scale"] + write * vals["write_scale"])
 
 
 def host_info():
