@@ -26,6 +26,7 @@ import argparse
 import glob
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -384,9 +385,30 @@ def gradient_leg(n=64):
     res = dict(workload="config5b: 64 circuits, M=6, mode 0 undetected C_U=30, 5 detected C_D=8, b=0, complex128; "
                         "forward (intermediates kept) + VJP per circuit",
                circuits=n, seconds=sec, circuits_per_s=n / sec, computed_amplitudes_per_circuit=targets,
-               output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec)
+               output_amplitudes_per_s=n * plan.query(F.FD_Q_OUT_ELEMS) / sec,
+               saved_bytes_per_circuit=sb, workspace_bytes=wb)
+    # the same step with checkpointed reverse sweeps (every ceil(sqrt(L)) levels)
+    levels = plan.query(F.FD_Q_LEVELS)
+    every = math.ceil(math.sqrt(levels))
+    ref = [(dA.clone(), db.clone(), dc.clone()) for dA, db, dc in grads]
+    del ws, saved
+    torch.cuda.empty_cache()
+    F.fd_plan_set_checkpoint(plan, every)
+    wb, sb = plan.workspace(True)
+    ws = torch.empty(wb, dtype=torch.uint8, device=dev)
+    saved = torch.empty(sb, dtype=torch.uint8, device=dev)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    sec_c = time.perf_counter() - t0
+    F.fd_device_status(plan)
+    same = all(torch.equal(a, r) for x, y in zip(grads, ref) for a, r in zip(x, y))
+    res["checkpointed"] = dict(every_levels=every, levels=levels, saved_bytes_per_circuit=sb, workspace_bytes=wb,
+                               seconds=sec_c, circuits_per_s=n / sec_c, gradients_bitwise_equal=bool(same))
     plan.close()
-    del ws, saved, rho, g, ins, grads
+    del ws, saved, rho, g, ins, grads, ref
     torch.cuda.empty_cache()
     return res
 

@@ -110,6 +110,23 @@ fd_status fd_plan_destroy(fd_plan p);
  *                 NULL needs fwd_bytes + saved_bytes of workspace. */
 fd_status fd_plan_workspace(fd_plan p, int with_vjp, size_t* fwd_bytes, size_t* saved_bytes);
 
+/* fd_plan_set_checkpoint -- memory of the reverse sweep.  Sec. 2.5's
+ * derivatives need, in reverse level order, the forward values of the two
+ * levels a pivot reads; by default the saved buffer keeps every level of
+ * every intermediate family.  With every = s >= 1 it keeps only F0 (every
+ * level: it is the output) and, for each segment of s levels, the families
+ * of the level just below it (the state the forward needs to restart there,
+ * Sec. 3.1.4's two-level buffer); fock_diag_vjp then recomputes each
+ * segment's intermediates from its checkpoint into a segment buffer of s + 1
+ * levels in the workspace, walking the segments from the top.  Memory falls
+ * from all levels to about L / s + s levels of intermediates (L levels;
+ * s ~ sqrt(L) is the least); the forward work is done twice.  Results are
+ * bitwise those of the store-all sweep (same kernels on the same values).
+ * every = 0 restores store-all.  fd_plan_workspace(with_vjp = 1) reports the
+ * sizes for the current setting; a saved buffer filled under one setting
+ * must be used under the same one.  Drops the plan's captured graphs. */
+fd_status fd_plan_set_checkpoint(fd_plan p, int every);
+
 /* fd_plan_query -- integer facts about the plan (host only, for tests and
  * reports).  `what`: see FD_Q_* below. */
 enum {

@@ -192,10 +192,18 @@ fd_status fd_plan_workspace(fd_plan p, int with_vjp, size_t* fwd_bytes, size_t* 
     *fwd_bytes = fd::fwd_layout(P, true, false, 0).total;
     *saved_bytes = 0;
   } else {
-    *saved_bytes = fd::fwd_layout(P, true, true, 0).total;
-    size_t v = fd::vjp_layout(P, true, 0).total;
-    *fwd_bytes = std::max(v, fd::prep_bytes(P));
+    *saved_bytes = fd::saved_bytes(P);
+    *fwd_bytes = std::max(fd::vjp_ws_bytes(P), fd::prep_bytes(P));
   }
+  return ok();
+}
+
+fd_status fd_plan_set_checkpoint(fd_plan p, int every) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  if (every < 0) return fail(FD_ERR_INVALID_ARG, "the checkpoint interval must be >= 0");
+  fd::Plan& P = p->P;
+  if (P.ckpt != every) drop_graphs(P);
+  P.ckpt = every;
   return ok();
 }
 
@@ -242,8 +250,10 @@ fd_status fock_diag_fwd(fd_plan p, const void* A, const void* b, const void* c, 
   if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;
   const bool odd = P.odd_for(b_zero);
   if (saved) {
-    if (saved_bytes < fd::fwd_layout(P, true, true, 0).total) return fail(FD_ERR_WORKSPACE, "saved buffer too small");
-    if (ws_bytes < fd::prep_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");
+    if (saved_bytes < fd::saved_bytes(P)) return fail(FD_ERR_WORKSPACE, "saved buffer too small");
+    // a checkpointed forward runs its ring in the reverse sweep's segment buffer
+    if (ws_bytes < (P.ckpt > 0 ? fd::vjp_ws_bytes(P) : fd::prep_bytes(P)))
+      return fail(FD_ERR_WORKSPACE, "workspace too small");
   } else if (ws_bytes < fd::fwd_layout(P, odd, false, 0).total) {
     return fail(FD_ERR_WORKSPACE, "workspace too small");
   }
@@ -364,8 +374,8 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
   bool b_zero = false;
   if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;
   const bool odd = P.odd_for(b_zero);
-  const size_t vneed = fd::vjp_layout(P, odd, 0).total;
-  const size_t sneed = fd::fwd_layout(P, true, true, 0).total;
+  const size_t vneed = P.ckpt > 0 ? fd::vjp_ws_bytes(P) : fd::vjp_layout(P, odd, 0).total;
+  const size_t sneed = fd::saved_bytes(P);
   const void* sv = saved;
   std::string err;
   if ((s = fd::ensure_device(&P, &err)) != FD_OK) return fail(s, err);

@@ -49,6 +49,9 @@ constexpr int kPartialSlots = 4096;      // deterministic VJP partial accumulato
 constexpr int kThreads = 256;
 constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
+constexpr int kPointBatch = 32;          // Abar records per LDS staging batch, point reverse kernel
+constexpr int kBlockBatch = 32;          // the same, block reverse kernel
+constexpr int kVjpSlots = 1024;          // reduction slots of the state-vector cotangents
 
 enum FamType { F_F0 = 0, F_F1K, F_F1B, F_F2, F_1010, F_1001 };
 
@@ -155,6 +158,9 @@ struct Plan {
   std::vector<GraphEntry> graphs;
   hipStream_t capture_stream = nullptr;
   uint64_t graph_clock = 0;
+  // reverse-sweep checkpoint interval in levels (0: the saved buffer keeps
+  // every level of every family)
+  int ckpt = 0;
   bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
 };
 
@@ -199,10 +205,43 @@ struct VjpLayout {
 // pivot cotangent blocks (MD rows sets), their b-terms and the own F0
 // cotangent rows, each read only by the lane that wrote it.
 size_t vjp_private_entries(const Plan& P);
-size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel
+size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel (largest geometry used)
+size_t vjp_lds_bytes_for(const Plan& P, const ChunkGeo& G);   // ... for one chunk geometry
 constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);
 size_t prep_bytes(const Plan& P);
+// Checkpointed reverse sweeps (Plan::ckpt = s > 0): the saved buffer keeps F0
+// at every level and, for each segment of s levels after the first, the
+// families of the level just below the segment (what the forward needs to
+// restart there).  Segment c covers levels [c s, min((c + 1) s, smax + 1)).
+// Levels are stored at their exact sizes; the odd-level families are left
+// out when the plan promises b = 0 and every mode is detected.
+struct CkptLayout {
+  size_t f0 = 0;                     // F0, every level (output-sized); never 0, which means "absent"
+  std::vector<size_t> ck;            // [(c - 1) * nfam + f]: family f in checkpoint c >= 1
+  int nseg = 0;                      // segments; checkpoints = nseg - 1
+  size_t total = 0;
+};
+CkptLayout ckpt_layout(const Plan& P);
+// The segment buffer of a checkpointed sweep, in the workspace after the
+// reverse sweep's own layout: per family, the levels seg_lo - 1 .. seg_hi of
+// the largest segment, packed at their exact sizes (seg_node gives where
+// level L starts); the forward's two-level ring uses slots of maxN nodes.
+struct SegLayout {
+  size_t base = 0;
+  std::vector<size_t> fam;           // per family: start of its region (0: none)
+  size_t total = 0;
+};
+SegLayout seg_layout(const Plan& P);
+bool ckpt_keeps_family(const Plan& P, int f);
+// Node offset of level L inside a segment buffer region holding levels
+// seg_lo - 1 .. (group g).
+int64_t seg_node(const Plan& P, int g, int seg_lo, int L);
+// Bytes of the saved buffer for fock_diag_vjp (every level, or checkpoints).
+size_t saved_bytes(const Plan& P);
+// Workspace bytes of fock_diag_vjp with a saved buffer (and of fock_diag_fwd
+// with one); includes the segment buffer of a checkpointed plan.
+size_t vjp_ws_bytes(const Plan& P);
 void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms);
 // Batched forward (one persistent sweep launch over every circuit); plans
 // already on the current device, workspaces checked by the caller.
@@ -262,6 +301,14 @@ hipError_t run_jvp(const Plan& P, const void* A, const void* b, const void* c, c
                    const void* dc, void* rho, void* drho, void* ws, hipStream_t st);
 hipError_t run_forward(const Plan& P, bool odd, const void* A, const void* b, const void* c, void* rho, void* ws,
                        void* saved, hipStream_t st, StopRule* stop = nullptr);
+// One forward level launch with explicit family pointers (rd: level S-1,
+// wr: level S, indexed by family; F0 of levels S and S+1); Ai/bi the
+// interleaved, symmetrised triple from launch_prep.
+hipError_t launch_fwd_level(const Plan& P, bool odd, int S, const void* const* rd, void* const* wr,
+                            const void* f0cur, void* f0nxt, const void* Ai, const void* bi, hipStream_t st);
+// Copies n[f] complex entries from src[f] to dst[f] for every family f with
+// a non-null src (one launch).
+hipError_t launch_copy_fams(const Plan& P, const void* const* src, void* const* dst, const int64_t* n, hipStream_t st);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
 constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
 // LDS tile of the permutations between rho's C order and node order:

@@ -196,13 +196,16 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
     }
     for (int s = 0; s < C.steps; ++s) work[i] += (double)Pl.ncnt[s] * Pl.B;
   }
-  // per-wave bytes: PN, A/b, then the block unit rows (largest circuit)
+  // per-wave bytes: PN, A/b, then the block unit rows (largest circuit): a
+  // unit of chunk geometry G touches F0 rows [k0-2, k1) and MD bridge pivot
+  // blocks of rows [k0-1, k1) (fwd_block_unit), for either of the circuit's
+  // two geometries (full- and half-height chunks)
   size_t rows = 0;
+  auto unit_rows = [&](const ChunkGeo& G, int MD) {
+    return ((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 * eb;
+  };
   for (int i = 0; i < n; ++i)
-    if (hc[i].kind) {
-      const ChunkGeo& G = hc[i].G;
-      rows = std::max(rows, ((size_t)(G.RC + 2) + (size_t)hc[i].P.MD * (G.RC + 1)) * G.R0 * eb);
-    }
+    if (hc[i].kind) rows = std::max({rows, unit_rows(hc[i].G, hc[i].P.MD), unit_rows(hc[i].Gh, hc[i].P.MD)});
   lds.wave_bytes = (int)align16((size_t)lds.pn_bytes + lds.sa_bytes + rows);
   lds.waves = 4;
   while (lds.waves > 1 && kTabBytes + (size_t)lds.waves * lds.wave_bytes > kMaxLds) --lds.waves;
@@ -276,6 +279,10 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
       const int64_t units = hc[i].kind ? pts * (half ? hc[i].Gh.nchunks : hc[i].G.nchunks) : pts;
       int64_t per = std::max<int64_t>(hc[i].kind ? T.min_block_units : T.min_point_units, (units + div - 1) / div);
       if (!hc[i].kind) per = (per + 63) / 64 * 64;   // whole wavefronts of lattice points
+      if (units > 0x7fffffff) {
+        *err = "a step of circuit " + std::to_string(i) + " has too many units for one work item table";
+        return FD_ERR_UNSUPPORTED;
+      }
       for (int64_t u0 = 0; u0 < units; u0 += per) {
         BatchItem I;
         std::memset(&I, 0, sizeof(I));
@@ -284,6 +291,12 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
         I.u0 = (int)u0;
         I.u1 = (int)std::min(units, u0 + per);
         I.half = half ? 1 : 0;
+        // an item covers whole units of its own geometry: (lattice point, chunk)
+        // pairs below pts x nchunks, or lattice points below pts
+        if (I.u0 < 0 || I.u1 <= I.u0 || I.u1 > units) {
+          *err = "internal error: batch work item outside its step's units";
+          return FD_ERR_HIP;
+        }
         S->h_items.push_back(I);
       }
     }

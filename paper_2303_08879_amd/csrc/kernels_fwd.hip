@@ -100,16 +100,6 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // ---------------------------------------------------------------------------
 // Rows of the first undetected coordinate per chunk: about `target` own
 // entries (default one wavefront), spread evenly over the rows.
-ChunkGeo chunk_geo(const Plan& Pl, int target) {
-  ChunkGeo G;
-  G.C0 = Pl.udims[0];
-  G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, (target + G.R0 / 2) / G.R0);
-  rc = std::min(rc, G.C0);
-  G.nchunks = (G.C0 + rc - 1) / rc;
-  G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
-  return G;
-}
 
 template <typename R>
 static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd, int S, const LevelPtrs<R>& L,
@@ -194,6 +184,72 @@ static cx<R>* fam_level_ptr(const Plan& Pl, char* base, size_t off, int g, int S
   const size_t eb = sizeof(cx<R>);
   size_t node = ring ? (size_t)(S & 1) * Pl.maxN[g] : (size_t)Pl.lvl[(size_t)g * (Pl.smax + 2) + S];
   return reinterpret_cast<cx<R>*>(base + off + node * Pl.B * eb);
+}
+
+hipError_t launch_fwd_level(const Plan& Pl, bool odd, int S, const void* const* rd, void* const* wr,
+                            const void* f0cur, void* f0nxt, const void* Ai, const void* bi, hipStream_t st) {
+  if (!f0cur || !Ai || !bi) return hipErrorInvalidValue;   // read by every unit
+  const DevPlan P = make_devplan(Pl, odd);
+  if (Pl.dt == FD_C64) {
+    LevelPtrs<float> L;
+    std::memset(&L, 0, sizeof(L));
+    for (int f = 1; f < Pl.nfam; ++f) {
+      L.rd[f] = static_cast<const cx<float>*>(rd[f]);
+      L.wr[f] = static_cast<cx<float>*>(wr[f]);
+    }
+    L.f0cur = static_cast<const cx<float>*>(f0cur);
+    L.f0nxt = static_cast<cx<float>*>(f0nxt);
+    L.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
+    return launch_fwd_level_t<float>(Pl, P, odd, S, L, Ai, bi, st);
+  }
+  LevelPtrs<double> L;
+  std::memset(&L, 0, sizeof(L));
+  for (int f = 1; f < Pl.nfam; ++f) {
+    L.rd[f] = static_cast<const cx<double>*>(rd[f]);
+    L.wr[f] = static_cast<cx<double>*>(wr[f]);
+  }
+  L.f0cur = static_cast<const cx<double>*>(f0cur);
+  L.f0nxt = static_cast<cx<double>*>(f0nxt);
+  L.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
+  return launch_fwd_level_t<double>(Pl, P, odd, S, L, Ai, bi, st);
+}
+
+// Copy of one level of every family (checkpoints of a checkpointed sweep):
+// family blockIdx.y, n[f] 16-byte (complex128) or 8-byte entries.
+struct CopyFams {
+  const void* src[kMaxFam];
+  void* dst[kMaxFam];
+  int64_t n[kMaxFam];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_copy_fams(CopyFams a) {
+  const int f = blockIdx.y;
+  const cx<R>* src = static_cast<const cx<R>*>(a.src[f]);
+  cx<R>* dst = static_cast<cx<R>*>(a.dst[f]);
+  if (!src) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n[f]; i += (int64_t)gridDim.x * blockDim.x)
+    st(dst + i, ld(src + i));
+}
+
+hipError_t launch_copy_fams(const Plan& Pl, const void* const* src, void* const* dst, const int64_t* n,
+                            hipStream_t st) {
+  CopyFams a;
+  std::memset(&a, 0, sizeof(a));
+  int64_t nmax = 0;
+  for (int f = 0; f < Pl.nfam; ++f) {
+    a.src[f] = src[f];
+    a.dst[f] = dst[f];
+    a.n[f] = src[f] ? n[f] : 0;
+    nmax = std::max(nmax, a.n[f]);
+  }
+  if (nmax == 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min<int64_t>((nmax + kThreads - 1) / kThreads, 1024);
+  if (Pl.dt == FD_C64)
+    hipLaunchKernelGGL((k_copy_fams<float>), dim3(gx, Pl.nfam), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_copy_fams<double>), dim3(gx, Pl.nfam), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const Plan& Pl, const void* A, const void* b, const void* c, void* Ai, void* f0node0,
@@ -284,9 +340,79 @@ static hipError_t launch_out_perm_t(const Plan& Pl, const DevPlan& P, const cx<R
   return hipGetLastError();
 }
 
+// Forward sweep for a checkpointed reverse sweep: F0 at every level goes to
+// the saved buffer, the other families run in a two-level ring (the first
+// two slots of the segment buffer), and the level just below each segment is
+// copied into its checkpoint.
+template <typename R>
+static hipError_t run_forward_ckpt_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c,
+                                     void* rho, char* ws, char* saved, hipStream_t st) {
+  const CkptLayout Lc = ckpt_layout(Pl);
+  const SegLayout Sg = seg_layout(Pl);
+  const size_t eb = sizeof(cx<R>);
+  cx<R>* Ai = reinterpret_cast<cx<R>*>(ws);   // prep block at the start of the workspace
+  cx<R>* bi = Ai + (size_t)Pl.npos * Pl.npos;
+  cx<R>* f0 = reinterpret_cast<cx<R>*>(saved + Lc.f0);
+  const DevPlan P = make_devplan(Pl, odd);
+  hipError_t e;
+  {
+    KTimer kt(Pl, KK_PREP, st);
+    e = launch_prep(Pl, A, b, c, Ai, f0, st);
+  }
+  if (e != hipSuccess) return e;
+  if (Pl.B > 1) {
+    KTimer kt(Pl, KK_UFILL, st);
+    const size_t shm = ufill_lds_bytes(Pl, false);
+    auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : &k_ufill<R, 4>;
+    if (shm > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int s = Pl.ckpt, MD = Pl.MD;
+  auto used = [&](int f) { return ckpt_keeps_family(Pl, f) && (odd || f >= 1 + 2 * MD); };
+  auto slot = [&](int f, int k) {   // ring slot k of family f
+    return ws + Sg.fam[f] + (size_t)k * Pl.maxN[Pl.fam_group[f]] * Pl.B * eb;
+  };
+  for (int S = 0; S <= Pl.smax && MD > 0; ++S) {
+    const void* rd[kMaxFam] = {};
+    void* wr[kMaxFam] = {};
+    for (int f = 1; f < Pl.nfam; ++f) {
+      if (!used(f)) continue;
+      rd[f] = S > 0 ? slot(f, (S - 1) & 1) : nullptr;
+      wr[f] = slot(f, S & 1);
+    }
+    const cx<R>* f0cur = f0 + (size_t)Pl.lvl[S] * Pl.B;
+    cx<R>* f0nxt = S < Pl.smax ? f0 + (size_t)Pl.lvl[S + 1] * Pl.B : nullptr;
+    {
+      KTimer kt(Pl, KK_FWD_LEVEL, st);
+      e = launch_fwd_level(Pl, odd, S, rd, wr, f0cur, f0nxt, Ai, bi, st);
+    }
+    if (e != hipSuccess) return e;
+    if ((S + 1) % s == 0 && S < Pl.smax) {
+      // level S is the one below segment (S + 1) / s: keep it
+      const int ck = (S + 1) / s - 1;
+      const void* src[kMaxFam] = {};
+      void* dst[kMaxFam] = {};
+      int64_t n[kMaxFam] = {};
+      for (int f = 1; f < Pl.nfam; ++f) {
+        if (!used(f)) continue;
+        src[f] = wr[f];
+        dst[f] = saved + Lc.ck[(size_t)ck * Pl.nfam + f];
+        n[f] = Pl.ncnt[(size_t)Pl.fam_group[f] * (Pl.smax + 1) + S] * Pl.B;
+      }
+      if ((e = launch_copy_fams(Pl, src, dst, n, st)) != hipSuccess) return e;
+    }
+  }
+  if (!rho) return hipSuccess;
+  return launch_out_perm_t<R>(Pl, P, f0, rho, st);
+}
+
 template <typename R>
 static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c, void* rho,
                                 char* ws, char* saved, hipStream_t st, StopRule* stop) {
+  if (saved && Pl.ckpt > 0) return run_forward_ckpt_t<R>(Pl, odd, A, b, c, rho, ws, saved, st);
   const bool store_all = saved != nullptr;
   // prep lives in the workspace; intermediates in `saved` (store-all) or the workspace (ring)
   FwdLayout Lw = fwd_layout(Pl, odd, false, 0);
@@ -595,8 +721,6 @@ static hipError_t run_jvp_t(const Plan& Pl, const void* A, const void* b, const 
   if ((e = launch_out_perm_t<R>(Pl, P, f0, rho, st)) != hipSuccess) return e;
   return launch_out_perm_t<R>(Pl, P, tf0, drho, st);
 }
-
-size_t jvp_half_bytes(const Plan& Pl) { return (fwd_layout(Pl, true, false, 0).total + 255) / 256 * 256; }
 
 hipError_t run_jvp(const Plan& Pl, const void* A, const void* b, const void* c, const void* dA, const void* db,
                    const void* dc, void* rho, void* drho, void* ws, hipStream_t st) {

@@ -139,7 +139,6 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
 // the final kernel adds the slots in order (bitwise reproducible).
 // ---------------------------------------------------------------------------
 constexpr int kVjpGroup = 16;
-constexpr int kVjpSlots = 1024;
 
 struct StateVjpTerms {
   int n;                    // terms in this launch (<= kVjpGroup)
@@ -369,11 +368,6 @@ hipError_t run_state_jvp(const Plan& Pl, const void* c, const void* psi, const v
   return hipGetLastError();
 }
 
-size_t state_vjp_ws_bytes(const Plan& Pl) {
-  const int ncol = Pl.MD + Pl.MD * (Pl.MD + 1) / 2 + 1;
-  return (size_t)kVjpSlots * ncol * sizeof(double2);
-}
-
 template <typename R>
 static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi, const void* g, void* dA, void* db,
                                   void* dc, void* ws, hipStream_t st) {
@@ -428,12 +422,6 @@ hipError_t run_state_vjp(const Plan& Pl, const void* c, const void* psi, const v
                          void* ws, hipStream_t st) {
   if (Pl.dt == FD_C64) return run_state_vjp_t<float>(Pl, c, psi, g, dA, db, dc, ws, st);
   return run_state_vjp_t<double>(Pl, c, psi, g, dA, db, dc, ws, st);
-}
-
-size_t state_ws_bytes(const Plan& Pl) {
-  const size_t eb = elem_bytes(Pl.dt);
-  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return al((size_t)Pl.nodes_total * eb) + al((size_t)(Pl.MD * Pl.MD + Pl.MD) * eb);
 }
 
 template <typename R>

@@ -107,10 +107,6 @@ __global__ __launch_bounds__(kThreads) void k_perm_in(DevPlan P, const cx<R>* __
     st(g0 + node_of_cindex(P, spn, slv, (int)idx), ld(drho + idx));
 }
 
-// Records per staging batch of the point and block reverse kernels.
-constexpr int kPointBatch = 32;
-constexpr int kBlockBatch = 32;
-
 // Abar / bbar: every reverse step reduces outer products of per-target
 // records (the target cotangents h and the read values x of one pivot
 // application) over all targets: D[i][l] = sum_rec h_i conj(x_l), i.e.
@@ -908,30 +904,6 @@ __global__ __launch_bounds__(kThreads) void k_vjp_final(const double2* __restric
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
-static ChunkGeo chunk_geo_v(const Plan& Pl, int target = kBT) {
-  ChunkGeo G;
-  G.C0 = Pl.udims[0];
-  G.R0 = Pl.B / G.C0;
-  int rc = std::max(1, (target + G.R0 / 2) / G.R0);
-  rc = std::min(rc, G.C0);
-  G.nchunks = (G.C0 + rc - 1) / rc;
-  G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
-  return G;
-}
-
-// Dynamic LDS of k_vjp_block for a chunk geometry (exact; the launcher uses
-// it); without one, the largest the launcher uses for this plan.
-static size_t vjp_lds_bytes_g(const Plan& Pl, const ChunkGeo& G) {
-  const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
-  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
-  const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                      (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
-  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
-}
-size_t vjp_lds_bytes(const Plan& Pl) {
-  return std::max(vjp_lds_bytes_g(Pl, chunk_geo_v(Pl)), vjp_lds_bytes_g(Pl, chunk_geo_v(Pl, kBT / 2)));
-}
-
 template <typename R>
 static const cx<R>* fptr(const Plan& Pl, const char* base, size_t off, int g, int S) {
   if (S < 0 || off == 0) return nullptr;
@@ -1002,18 +974,71 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     }
   }
   const size_t tab = 2 * (kMaxCut + 4) * sizeof(R) + (size_t)(MD + 1) * (Pl.smax + 3) * sizeof(int);
+  // Checkpointed plans: the forward values of one segment of levels at a
+  // time, recomputed from the segment's checkpoint into the segment buffer
+  // (slot k holds level seg_lo - 1 + k); F0 of every level is in `saved`.
+  const bool ck = Pl.ckpt > 0;
+  const CkptLayout Lc = ck ? ckpt_layout(Pl) : CkptLayout();
+  const SegLayout Sg = ck ? seg_layout(Pl) : SegLayout();
+  const size_t f0off = ck ? Lc.f0 : Ls.f0;
+  auto used = [&](int f) { return ckpt_keeps_family(Pl, f) && (odd || f >= 1 + 2 * MD); };
+  // level L of family f in the segment buffer (levels seg_lo - 1 .. held)
+  auto seg_slot = [&](int f, int lo, int L) {
+    return reinterpret_cast<cx<R>*>(ws + Sg.fam[f] +
+                                    (size_t)seg_node(Pl, Pl.fam_group[f], lo, L) * Pl.B * sizeof(cx<R>));
+  };
+  int seg_lo = Pl.smax + 1;
   for (int S = Pl.smax; S >= 0 && MD > 0; --S) {
+    if (ck && S < seg_lo) {
+      seg_lo = (S / Pl.ckpt) * Pl.ckpt;
+      const int c = S / Pl.ckpt;
+      if (c > 0) {
+        const void* src[kMaxFam] = {};
+        void* dst[kMaxFam] = {};
+        int64_t n[kMaxFam] = {};
+        for (int f = 1; f < Pl.nfam; ++f) {
+          if (!used(f)) continue;
+          src[f] = sv + Lc.ck[(size_t)(c - 1) * Pl.nfam + f];
+          dst[f] = seg_slot(f, seg_lo, seg_lo - 1);
+          n[f] = Pl.ncnt[(size_t)Pl.fam_group[f] * (Pl.smax + 1) + seg_lo - 1] * Pl.B;
+        }
+        if ((e = launch_copy_fams(Pl, src, dst, n, st)) != hipSuccess) return e;
+      }
+      const cx<R>* f0all = reinterpret_cast<const cx<R>*>(sv + f0off);
+      for (int L = seg_lo; L <= S; ++L) {
+        const void* rd[kMaxFam] = {};
+        void* wr[kMaxFam] = {};
+        for (int f = 1; f < Pl.nfam; ++f) {
+          if (!used(f)) continue;
+          rd[f] = L > 0 ? seg_slot(f, seg_lo, L - 1) : nullptr;
+          wr[f] = seg_slot(f, seg_lo, L);
+        }
+        // F0 of level L + 1 is written again with the values it already holds
+        cx<R>* f0nxt = L < Pl.smax ? const_cast<cx<R>*>(f0all) + (size_t)Pl.lvl[L + 1] * Pl.B : nullptr;
+        KTimer kt(Pl, KK_FWD_LEVEL, st);
+        if ((e = launch_fwd_level(Pl, odd, L, rd, wr, f0all + (size_t)Pl.lvl[L] * Pl.B, f0nxt, Ai, bi, st)) !=
+            hipSuccess)
+          return e;
+      }
+    }
     VjpPtrs<R> Vp;
     std::memset(&Vp, 0, sizeof(Vp));
     for (int f = 0; f < Pl.nfam; ++f) {
-      const size_t foff = f == 0 ? Ls.f0 : Ls.fam[f];
       const int g = Pl.fam_group[f];
-      Vp.fprev[f] = fptr<R>(Pl, sv, foff, g, S - 1);
-      Vp.fcur[f] = fptr<R>(Pl, sv, foff, g, S);
+      if (!ck || f == 0) {
+        const size_t foff = f == 0 ? f0off : Ls.fam[f];
+        Vp.fprev[f] = fptr<R>(Pl, sv, foff, g, S - 1);
+        Vp.fcur[f] = fptr<R>(Pl, sv, foff, g, S);
+      } else if (used(f)) {
+        Vp.fprev[f] = S > 0 ? seg_slot(f, seg_lo, S - 1) : nullptr;
+        Vp.fcur[f] = seg_slot(f, seg_lo, S);
+      }
       Vp.gprev[f] = gptr<R>(Pl, ws, V.gfam[f], g, S - 1);
       Vp.gcur[f] = gptr<R>(Pl, ws, V.gfam[f], g, S);
     }
     Vp.gf0nxt = (Pl.level_cap >= 0 && S == Pl.smax) ? nullptr : gptr<R>(Pl, ws, V.gfam[0], 0, S + 1);
+    // every level kernel reads these unconditionally
+    if (!Vp.fcur[0] || !Vp.gcur[0]) return hipErrorInvalidValue;
     Vp.d0cur = reinterpret_cast<const cx<R>*>(reinterpret_cast<const char*>(g0) +
                                               (size_t)Pl.lvl[S] * Pl.B * sizeof(cx<R>));
     Vp.node = Pl.d_node ? Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride : nullptr;
@@ -1057,9 +1082,9 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
 #undef FD_VJP_POINT
     } else {
       // as in the forward sweep: half-size row chunks on levels with few units
-      ChunkGeo G = chunk_geo_v(Pl);
-      if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo_v(Pl, kBT / 2);
-      const size_t shm = vjp_lds_bytes_g(Pl, G);
+      ChunkGeo G = chunk_geo(Pl);
+      if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
+      const size_t shm = vjp_lds_bytes_for(Pl, G);
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
 #define FD_VJP_BLOCK(MDV)                                                                                       \
   case MDV:                                                                                                     \
@@ -1097,7 +1122,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   const cx<R>* gseed = MD > 0 ? gptr<R>(Pl, ws, V.gfam[0], 0, 0) : g0;
   const cx<R>* cbar_src = gseed;
   if (Pl.B > 1) {
-    const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + Ls.f0);
+    const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + f0off);
     KTimer kt(Pl, KK_UFILL_VJP, st);
     const size_t shm = ufill_lds_bytes(Pl, true);
     auto* kfn = Pl.nq == 2 ? &k_ufill_vjp<R, 2> : &k_ufill_vjp<R, 4>;

@@ -357,6 +357,114 @@ FwdLayout fwd_layout(const Plan& P, bool odd, bool store_all, size_t base) {
   return L;
 }
 
+// Chunks of whole rows of the first undetected coordinate, about `target`
+// entries each (one wavefront per (lattice point, chunk) unit).
+ChunkGeo chunk_geo(const Plan& Pl, int target) {
+  ChunkGeo G;
+  G.C0 = Pl.udims[0];
+  G.R0 = Pl.B / G.C0;
+  int rc = std::max(1, (target + G.R0 / 2) / G.R0);
+  rc = std::min(rc, G.C0);
+  G.nchunks = (G.C0 + rc - 1) / rc;
+  G.RC = (G.C0 + G.nchunks - 1) / G.nchunks;
+  return G;
+}
+
+// Dynamic LDS of the block reverse kernel for a chunk geometry: the forward
+// pivot rows, the undetected-neighbour terms, one wavefront's record staging
+// batch and A, b (or the pair table of the final fold, if larger), then the
+// square-root tables.
+size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
+  const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
+  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
+  const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
+                      (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
+  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
+}
+
+size_t vjp_lds_bytes(const Plan& Pl) {
+  return std::max(vjp_lds_bytes_for(Pl, chunk_geo(Pl)), vjp_lds_bytes_for(Pl, chunk_geo(Pl, kBT / 2)));
+}
+
+size_t jvp_half_bytes(const Plan& Pl) { return (fwd_layout(Pl, true, false, 0).total + 255) / 256 * 256; }
+
+// State vectors: the amplitudes in level order plus A and b of the kept modes.
+size_t state_ws_bytes(const Plan& Pl) {
+  const size_t eb = elem_bytes(Pl.dt);
+  return align256((size_t)Pl.nodes_total * eb) + align256((size_t)(Pl.MD * Pl.MD + Pl.MD) * eb);
+}
+
+// One double2 per reduction slot and cotangent term (bbar, upper triangle of
+// Abar, sum g conj(psi)).
+size_t state_vjp_ws_bytes(const Plan& Pl) {
+  const int ncol = Pl.MD + Pl.MD * (Pl.MD + 1) / 2 + 1;
+  return (size_t)kVjpSlots * ncol * sizeof(double2);
+}
+
+bool ckpt_keeps_family(const Plan& P, int f) {
+  const bool odd_family = f >= 1 && f < 1 + 2 * P.MD;
+  return f >= 1 && (!odd_family || P.odd_for(P.flags == FD_B_ZERO));
+}
+
+static int64_t level_nodes(const Plan& P, int g, int L) {
+  return (L < 0 || L > P.smax) ? 0 : P.ncnt[(size_t)g * (P.smax + 1) + L];
+}
+
+int64_t seg_node(const Plan& P, int g, int seg_lo, int L) {
+  int64_t n = 0;
+  for (int l = std::max(seg_lo - 1, 0); l < L; ++l) n += level_nodes(P, g, l);
+  return n;
+}
+
+CkptLayout ckpt_layout(const Plan& P) {
+  CkptLayout L;
+  const size_t eb = elem_bytes(P.dt);
+  const int s = std::max(P.ckpt, 1);
+  L.nseg = P.MD > 0 ? (P.smax + 1 + s - 1) / s : 1;
+  // offset 0 means "not kept" in every layout: F0 starts after a 256-byte gap
+  L.f0 = 256;
+  size_t off = align256(L.f0 + (size_t)P.nodes_total * P.B * eb);
+  L.ck.assign((size_t)std::max(L.nseg - 1, 0) * P.nfam, 0);
+  for (int c = 1; c < L.nseg; ++c)
+    for (int f = 1; f < P.nfam; ++f) {
+      if (!ckpt_keeps_family(P, f)) continue;
+      L.ck[(size_t)(c - 1) * P.nfam + f] = off;
+      off = align256(off + (size_t)level_nodes(P, P.fam_group[f], c * s - 1) * P.B * eb);
+    }
+  L.total = off;
+  return L;
+}
+
+SegLayout seg_layout(const Plan& P) {
+  SegLayout L;
+  const size_t eb = elem_bytes(P.dt);
+  L.base = align256(vjp_layout(P, true, 0).total);
+  size_t off = L.base;
+  L.fam.assign(P.nfam, 0);
+  const int s = std::max(P.ckpt, 1);
+  for (int f = 1; f < P.nfam; ++f) {
+    if (!ckpt_keeps_family(P, f)) continue;
+    const int g = P.fam_group[f];
+    int64_t most = 2 * P.maxN[g];   // the forward's ring
+    for (int lo = 0; lo <= P.smax; lo += s) {
+      const int hi = std::min(lo + s - 1, P.smax);
+      most = std::max(most, seg_node(P, g, lo, hi + 1));
+    }
+    L.fam[f] = off;
+    off = align256(off + (size_t)most * P.B * eb);
+  }
+  L.total = off;
+  return L;
+}
+
+size_t saved_bytes(const Plan& P) {
+  return P.ckpt > 0 ? ckpt_layout(P).total : fwd_layout(P, true, true, 0).total;
+}
+
+size_t vjp_ws_bytes(const Plan& P) {
+  return P.ckpt > 0 ? seg_layout(P).total : vjp_layout(P, true, 0).total;
+}
+
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   VjpLayout L;
   const size_t eb = elem_bytes(P.dt);

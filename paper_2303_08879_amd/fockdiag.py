@@ -31,6 +31,7 @@ EXPORTS = [
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
     "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
     "fock_state_vjp", "fock_state_jvp", "fd_plan_jvp_workspace", "fock_diag_jvp", "fock_diag_fwd_static",
+    "fd_plan_set_checkpoint",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -83,6 +84,7 @@ def lib():
     L.fd_device_status.argtypes = [vp, vp]
     L.fd_plan_timing.argtypes = [vp, u32]
     L.fd_plan_use_graphs.argtypes = [vp, i32]
+    L.fd_plan_set_checkpoint.argtypes = [vp, i32]
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     L.fd_batch_set_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.fd_batch_get_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
@@ -353,6 +355,11 @@ def fock_diag_vjp_batch(plans, As, bs, cs, saveds, drhos, dAs, dbs, dcs, workspa
 
 def fd_device_status(plan, stream=None):
     _check(lib().fd_device_status(plan.handle, _stream(stream)))
+
+
+def fd_plan_set_checkpoint(plan, every):
+    """Reverse-sweep checkpoint interval in levels (0: keep every level)."""
+    _check(lib().fd_plan_set_checkpoint(plan.handle, int(every)))
 
 
 def fd_plan_use_graphs(plan, enable=True):

@@ -7,6 +7,7 @@ import os
 import re
 
 import pytest
+import torch
 
 from paper_2303_08879_amd import fockdiag as F
 
@@ -257,3 +258,21 @@ def test_total_cutoff_pivot_count_app_b1(M, Nmax):
     expect = sum(math.comb(N + M - 1, N) + math.comb(N + M, N + 1) for N in range(Nmax))
     assert p.query(F.FD_Q_PIVOTS) == expect
     assert p.query(F.FD_Q_OUT_ELEMS) == math.comb(Nmax - 1 + M, M)
+
+
+def test_checkpoint_setting_and_memory():
+    L = F.lib()
+    plan = F.Plan([8] * 8, 0xFF, torch.complex128, "zero")
+    ws0, sv0 = plan.workspace(True)
+    assert L.fd_plan_set_checkpoint(plan.handle, -1) == F.FD_ERR_INVALID_ARG
+    F.fd_plan_set_checkpoint(plan, 8)
+    ws8, sv8 = plan.workspace(True)
+    # F0 (the output, 16.8M entries) plus 6 checkpoints of one level of every
+    # family, against every level of every family
+    out = 16 * 8 ** 8
+    assert out < sv8 < 0.3 * sv0
+    assert ws8 > ws0                      # the segment buffer of 9 levels
+    F.fd_plan_set_checkpoint(plan, 0)
+    assert plan.workspace(True) == (ws0, sv0)
+    with pytest.raises(F.FockDiagError):
+        F.fd_plan_set_checkpoint(type("P", (), {"handle": None})(), 2)
