@@ -703,8 +703,18 @@ def main():
         s64 = CircuitStep(circ, torch.complex64)
         s64.step()
         torch.cuda.synchronize()
-        corner = [3 if j < 5 else 2 for j in range(circ.M)] if circ.M == 8 else [5] * circ.M
-        line["cpu_baseline"] = cpu_baseline(circ, s128, s64, corner)
+        # the oracle's cost grows with the box (prod of the sample's cutoffs, squared):
+        # time the smallest sample, then report the largest one predicted to take
+        # at most ~25 s on this host
+        if circ.M == 8:
+            corners = [[3] * k + [2] * (8 - k) for k in (5, 6, 7)]
+        else:
+            corners = [[c] * circ.M for c in (3, 4, 5)]
+        size = lambda cn: math.prod(c * c for c in cn)
+        first = cpu_baseline(circ, s128, s64, corners[0])
+        per = first["seconds"] / size(corners[0])
+        pick = max((cn for cn in corners if per * size(cn) <= 25.0), key=size, default=corners[0])
+        line["cpu_baseline"] = first if pick is corners[0] else cpu_baseline(circ, s128, s64, pick)
         s64.release()
         progress("cpu_baseline", t_start)
         del np
