@@ -72,14 +72,24 @@ typedef enum { FD_C128 = 0, FD_C64 = 1 } fd_dtype;
 enum { FD_B_AUTO = 0u, FD_B_ZERO = 1u, FD_B_GENERAL = 2u };
 
 /* Compiled limits: M <= 16 modes, at most 8 detected modes with cutoff >= 2,
- * at most 2 undetected modes with cutoff >= 2, every cutoff in [1, 64],
+ * at most 3 undetected modes with cutoff >= 2, every cutoff in [1, 64],
  * prod over detected cutoffs < 2^31 (<= 2^22 when a mode is undetected: the
  * plan keeps a 96-byte record per detected lattice point), one level of the
  * detected lattice times the undetected block <= 2^28 amplitudes,
- * undetected block prod C_u^2 <= 4096
- * (the block of one node is staged in LDS; the reverse sweep also needs
- * (1 + 2|U|) blocks to fit in 160 KiB, else fock_diag_vjp returns
- * FD_ERR_UNSUPPORTED).  Modes with cutoff 1 carry no photons and are dropped
+ * undetected block B = prod C_u^2 <= 16384, and the LDS staging (160 KiB per
+ * workgroup) must hold
+ *   forward:  the block fill (B elements and B + sum 2(C_u - 1) + 2 ints) and
+ *             (3 + 2 |D|) rows of B / C_u0 elements (C_u0 the first
+ *             undetected cutoff), else fd_plan_create returns
+ *             FD_ERR_UNSUPPORTED;
+ *   reverse:  the block fill (2 B elements) and (2 + 2|U|) such rows plus
+ *             the record staging, else fock_diag_vjp returns
+ *             FD_ERR_UNSUPPORTED.
+ * E.g. in complex128: two undetected modes at cutoff 9, forward with up to
+ * 5 detected modes and no reverse sweep (complex64: both); three undetected
+ * modes at cutoff 3, forward and reverse with up to 8 detected modes; at
+ * cutoff 4, forward with up to 3 detected modes.  Blocks are not streamed
+ * from HBM.  Modes with cutoff 1 carry no photons and are dropped
  * internally. */
 
 typedef struct fd_plan_s* fd_plan;

@@ -122,10 +122,10 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
 // Coordinate q of an undetected-block entry: floor(rem / ustride[q]) for
-// 0 <= rem < 4096 without an integer division.  (rem + 1/2) / ustride lies at
-// least 1 / (2 ustride) >= 2^-13 away from an integer, while one double
-// multiply by the rounded reciprocal is off by under 2^-38 for rem < 4096, so
-// truncating the product is exact.
+// 0 <= rem < 16384 without an integer division.  (rem + 1/2) / ustride lies
+// at least 1 / (2 ustride) >= 2^-15 away from an integer, while one double
+// multiply by the rounded reciprocal is off by under 2^-37 for rem < 16384,
+// so truncating the product is exact.
 __device__ __forceinline__ int ucoord(const DevPlan& P, int rem, int q) { return (int)((rem + 0.5) * P.uinv[q]); }
 
 // PN[d][x] for x in [-1, smax+1]; table row width pnw.

@@ -38,8 +38,8 @@ namespace fd {
 
 constexpr int kMaxModes = 16;
 constexpr int kMaxD = 8;                 // detected modes with cutoff >= 2
-constexpr int kMaxUq = 4;                // undetected block coordinates (2 per U mode)
-constexpr int kMaxBlock = 4096;          // entries per node (prod_U C_u^2)
+constexpr int kMaxUq = 6;                // undetected block coordinates (2 per U mode, at most 3 modes)
+constexpr int kMaxBlock = 16384;         // entries per node (prod_U C_u^2); the LDS staging limits it further
 constexpr int kMaxCut = 64;
 constexpr int kMaxPos = kMaxUq + 2 * kMaxD;   // positions of the active index
 constexpr int kMaxFam = 1 + 3 * kMaxD + kMaxD * (kMaxD - 1);
@@ -206,6 +206,10 @@ struct VjpLayout {
 // cotangent rows, each read only by the lane that wrote it.
 size_t vjp_private_entries(const Plan& P);
 size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel (largest geometry used)
+// Dynamic LDS of the forward block kernel for one chunk geometry: F0 rows
+// [k0-2, k1), MD bridge pivot blocks of rows [k0-1, k1), A and b, the
+// square-root tables.
+size_t fwd_lds_bytes_for(const Plan& P, const ChunkGeo& G);
 size_t vjp_lds_bytes_for(const Plan& P, const ChunkGeo& G);   // ... for one chunk geometry
 constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);

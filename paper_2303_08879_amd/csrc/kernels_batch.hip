@@ -158,6 +158,10 @@ fd_status build_sched(int n, Plan* const* plans, const bool* odd, const void* co
     std::memset(&C, 0, sizeof(C));
     C.P = make_devplan(Pl, odd[i]);
     C.kind = Pl.B > 1 ? 1 : 0;
+    if (Pl.nq > 4) {
+      *err = "the batched sweep runs at most two undetected modes";
+      return FD_ERR_UNSUPPORTED;
+    }
     if (C.kind) {
       C.G = chunk_geo(Pl);
       C.Gh = chunk_geo(Pl, kBT / 2);
@@ -398,13 +402,28 @@ static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* 
                                          const void* const* b, const void* const* c, void* const* rho,
                                          void* const* ws, hipStream_t st, std::string* err);
 
+// The persistent sweep runs blocks of at most four coordinates (two
+// undetected modes) whose unit rows and fill fit its LDS staging; other
+// circuits take their own level launches.
+static bool sweep_takes(const Plan& Pl) {
+  if (Pl.B == 1) return true;
+  if (Pl.nq > 4) return false;
+  const size_t eb = elem_bytes(Pl.dt);
+  const size_t pnb = align16((size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int));
+  const size_t sa = align16((size_t)Pl.npos * (Pl.npos + 1) * eb);
+  size_t rows = 0;
+  for (const ChunkGeo& G : {chunk_geo(Pl), chunk_geo(Pl, kBT / 2)})
+    rows = std::max(rows, ((size_t)(G.RC + 2) + (size_t)Pl.MD * (G.RC + 1)) * G.R0 * eb);
+  return kTabBytes + align16(pnb + sa + rows) <= kMaxLds && ufill_lds_bytes(Pl, false) <= kMaxLds;
+}
+
 fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
                             const void* const* b, const void* const* c, void* const* rho, void* const* ws,
                             hipStream_t st, std::string* err) {
-  // circuits that fill the device: their own level launches, largest first;
-  // the others: one persistent sweep
+  // circuits that fill the device or that the sweep cannot stage: their own
+  // level launches; the others: one persistent sweep
   std::vector<int> big, small;
-  for (int i = 0; i < n; ++i) (fills_device(*plans[i]) ? big : small).push_back(i);
+  for (int i = 0; i < n; ++i) (fills_device(*plans[i]) || !sweep_takes(*plans[i]) ? big : small).push_back(i);
   for (int i : big) {
     const hipError_t e = run_forward(*plans[i], odd[i], A[i], b[i], c[i], rho[i], ws[i], nullptr, st);
     if (e != hipSuccess) {

@@ -101,6 +101,29 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // Rows of the first undetected coordinate per chunk: about `target` own
 // entries (default one wavefront), spread evenly over the rows.
 
+template <int MD, int NQ, typename R>
+static void launch_fwd_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const LevelPtrs<R>& L,
+                               const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G) {
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G);
+}
+
+// The undetected-block fill for the plan's number of block coordinates.
+template <typename R>
+static hipError_t launch_ufill(const Plan& Pl, const DevPlan& P, const cx<R>* Ai, const cx<R>* bi, cx<R>* f0,
+                               hipStream_t st) {
+  const size_t shm = ufill_lds_bytes(Pl, false);
+  if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected at plan creation
+  auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : Pl.nq == 4 ? &k_ufill<R, 4> : &k_ufill<R, 6>;
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+  hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
+  return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd, int S, const LevelPtrs<R>& L,
                                      const void* Ai, const void* bi, hipStream_t st) {
@@ -141,24 +164,17 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
     // whole-wavefront chunks (halving them costs 30-40 % there)
     ChunkGeo G = chunk_geo(Pl);
     if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
-    const size_t shm = (((size_t)(G.RC + 2) + (size_t)MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
-                           sizeof(cx<R>) + 2 * (kMaxCut + 4) * sizeof(R);
+    const size_t shm = fwd_lds_bytes_for(Pl, G);
+    if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected at plan creation
     const int grid = nwork * G.nchunks;
-#define FD_LAUNCH_BLOCK(MDV)                                                                               \
-  case MDV:                                                                                                \
-    if (Pl.nq == 2) {                                                                                      \
-      if (shm > 65536)                                                                                     \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 2, R>),                 \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
-      hipLaunchKernelGGL((k_fwd_block<MDV, 2, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S,         \
-                         nwork, G);                                                                        \
-    } else {                                                                                               \
-      if (shm > 65536)                                                                                     \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MDV, 4, R>),                 \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                   \
-      hipLaunchKernelGGL((k_fwd_block<MDV, 4, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S,         \
-                         nwork, G);                                                                        \
-    }                                                                                                      \
+#define FD_LAUNCH_BLOCK(MDV)                                                                     \
+  case MDV:                                                                                      \
+    if (Pl.nq == 2)                                                                              \
+      launch_fwd_block_k<MDV, 2, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
+    else if (Pl.nq == 4)                                                                         \
+      launch_fwd_block_k<MDV, 4, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
+    else                                                                                         \
+      launch_fwd_block_k<MDV, 6, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
     break;
     switch (MD) {
       FD_LAUNCH_BLOCK(1)
@@ -362,13 +378,7 @@ static hipError_t run_forward_ckpt_t(const Plan& Pl, bool odd, const void* A, co
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
     KTimer kt(Pl, KK_UFILL, st);
-    const size_t shm = ufill_lds_bytes(Pl, false);
-    auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : &k_ufill<R, 4>;
-    if (shm > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shm);
-    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_ufill<R>(Pl, P, Ai, bi, f0, st)) != hipSuccess) return e;
   }
   const int s = Pl.ckpt, MD = Pl.MD;
   auto used = [&](int f) { return ckpt_keeps_family(Pl, f) && (odd || f >= 1 + 2 * MD); };
@@ -437,13 +447,7 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   if (e != hipSuccess) return e;
   if (Pl.B > 1) {
     KTimer kt(Pl, KK_UFILL, st);
-    const size_t shm = ufill_lds_bytes(Pl, false);
-    auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : &k_ufill<R, 4>;
-    if (shm > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)shm);
-    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_ufill<R>(Pl, P, Ai, bi, f0, st)) != hipSuccess) return e;
   }
   for (int S = 0; S <= Pl.smax && Pl.MD > 0; ++S) {
     LevelPtrs<R> L;

@@ -916,6 +916,17 @@ static cx<R>* gptr(const Plan& Pl, char* base, size_t off, int g, int S) {
   return reinterpret_cast<cx<R>*>(base + off + (size_t)(S & 1) * Pl.maxN[g] * Pl.B * sizeof(cx<R>));
 }
 
+template <int MD, int NQ, typename R>
+static void launch_vjp_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const VjpPtrs<R>& Vp,
+                               const cx<R>* Ai, const cx<R>* bi, int S, int nwork, const ChunkGeo& G,
+                               double2* partial) {
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MD, NQ, R, kBlockBatch>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_vjp_block<MD, NQ, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S, nwork,
+                     G, partial);
+}
+
 template <typename R>
 static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void* b, const void* c,
                             const void* saved, const void* drho, void* dA, void* db, void* dc, char* ws,
@@ -1085,22 +1096,16 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       ChunkGeo G = chunk_geo(Pl);
       if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
       const size_t shm = vjp_lds_bytes_for(Pl, G);
+      if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
       const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
-#define FD_VJP_BLOCK(MDV)                                                                                       \
-  case MDV:                                                                                                     \
-    if (Pl.nq == 2) {                                                                                           \
-      if (shm > 65536)                                                                                          \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 2, R, kBlockBatch>),         \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 2, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, \
-                         S, nwork, G, partial);                                                                 \
-    } else {                                                                                                    \
-      if (shm > 65536)                                                                                          \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MDV, 4, R, kBlockBatch>),         \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);                        \
-      hipLaunchKernelGGL((k_vjp_block<MDV, 4, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, \
-                         S, nwork, G, partial);                                                                 \
-    }                                                                                                           \
+#define FD_VJP_BLOCK(MDV)                                                                         \
+  case MDV:                                                                                       \
+    if (Pl.nq == 2)                                                                               \
+      launch_vjp_block_k<MDV, 2, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
+    else if (Pl.nq == 4)                                                                          \
+      launch_vjp_block_k<MDV, 4, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
+    else                                                                                          \
+      launch_vjp_block_k<MDV, 6, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
     break;
       switch (MD) {
         FD_VJP_BLOCK(1)
@@ -1125,7 +1130,8 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
     const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + f0off);
     KTimer kt(Pl, KK_UFILL_VJP, st);
     const size_t shm = ufill_lds_bytes(Pl, true);
-    auto* kfn = Pl.nq == 2 ? &k_ufill_vjp<R, 2> : &k_ufill_vjp<R, 4>;
+    if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
+    auto* kfn = Pl.nq == 2 ? &k_ufill_vjp<R, 2> : Pl.nq == 4 ? &k_ufill_vjp<R, 4> : &k_ufill_vjp<R, 6>;
     if (shm > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm);

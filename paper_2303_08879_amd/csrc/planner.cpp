@@ -92,7 +92,7 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     return FD_ERR_UNSUPPORTED;
   }
   if (P->MU > kMaxUq / 2) {
-    *err = "at most 2 undetected modes with cutoff >= 2 are supported";
+    *err = "at most 3 undetected modes with cutoff >= 2 are supported";
     return FD_ERR_UNSUPPORTED;
   }
   P->CU.clear();
@@ -111,7 +111,7 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     B *= P->udims[q];
   }
   if (B > kMaxBlock) {
-    *err = "undetected block prod C_u^2 exceeds 4096";
+    *err = "undetected block prod C_u^2 exceeds 16384";
     return FD_ERR_UNSUPPORTED;
   }
   P->B = (int)B;
@@ -300,6 +300,14 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     std::vector<int> pos(P->woff.begin(), P->woff.end() - 1);
     for (int e = 0; e < P->B; ++e) P->elist[pos[wt[e]]++] = e;
   }
+  // the forward block kernel and the block fill hold their rows in LDS
+  if (P->B > 1) {
+    const size_t rows = std::max(fwd_lds_bytes_for(*P, chunk_geo(*P)), fwd_lds_bytes_for(*P, chunk_geo(*P, kBT / 2)));
+    if ((P->MD > 0 && rows > kMaxLds) || ufill_lds_bytes(*P, false) > kMaxLds) {
+      *err = "undetected block too large for the forward sweep's LDS staging";
+      return FD_ERR_UNSUPPORTED;
+    }
+  }
   P->targets = -1;
   P->terms = -1;
   return FD_OK;
@@ -380,6 +388,12 @@ size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
                       (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
+}
+
+size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
+  return (((size_t)(G.RC + 2) + (size_t)Pl.MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
+             elem_bytes(Pl.dt) +
+         2 * (kMaxCut + 4) * (elem_bytes(Pl.dt) / 2);
 }
 
 size_t vjp_lds_bytes(const Plan& Pl) {

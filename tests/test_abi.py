@@ -41,9 +41,41 @@ def test_plan_create_rejects_bad_arguments():
     assert L.fd_plan_create(2, bad, 0b11, 0, 0, ctypes.byref(h)) == F.FD_ERR_INVALID_ARG
     nine = (ctypes.c_int * 9)(*([3] * 9))
     assert L.fd_plan_create(9, nine, 0x1FF, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
-    three_u = (ctypes.c_int * 3)(3, 3, 3)
-    assert L.fd_plan_create(3, three_u, 0, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    four_u = (ctypes.c_int * 4)(3, 3, 3, 3)
+    assert L.fd_plan_create(4, four_u, 0, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
     assert "undetected" in F.fd_last_error()
+    # two undetected modes at cutoff 12: a block of 20736 entries
+    big2 = (ctypes.c_int * 3)(12, 12, 3)
+    assert L.fd_plan_create(3, big2, 0b100, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    assert "16384" in F.fd_last_error()
+    # three at cutoff 5: 15625 entries, whose fill does not fit the LDS
+    big3 = (ctypes.c_int * 4)(5, 5, 5, 2)
+    assert L.fd_plan_create(4, big3, 0b1000, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    assert "LDS" in F.fd_last_error()
+
+
+@pytest.mark.parametrize("cut,mask,dtype", [
+    ((3, 3, 3), 0, 0), ((4, 4, 4, 3), 0b1000, 0), ((3, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3), 0b11111111000, 0),
+    ((9, 9, 3), 0b100, 0), ((9, 9, 3, 3, 3, 3, 3), 0b1111100, 0), ((9, 9, 3, 3, 3, 3, 3, 3), 0b11111100, 1)])
+def test_plan_create_three_undetected_modes_and_large_blocks(cut, mask, dtype):
+    # blocks up to what the LDS staging holds: three undetected modes, and two
+    # at cutoff 9 (6561 entries) with up to five detected modes in complex128
+    # (six in complex64, whose rows take half the bytes)
+    L = F.lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int * len(cut))(*cut)
+    assert L.fd_plan_create(len(cut), arr, mask, dtype, 0, ctypes.byref(h)) == F.FD_OK, F.fd_last_error()
+    assert L.fd_plan_destroy(h) == F.FD_OK
+
+
+def test_plan_create_rejects_rows_beyond_lds():
+    # two undetected modes at cutoff 9 with six detected modes: 15 rows of
+    # 729 complex128 entries exceed 160 KiB
+    L = F.lib()
+    h = ctypes.c_void_p()
+    cut = (ctypes.c_int * 8)(9, 9, 3, 3, 3, 3, 3, 3)
+    assert L.fd_plan_create(8, cut, 0b11111100, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
+    assert "LDS" in F.fd_last_error()
 
 
 def test_calls_reject_null_plan_and_pointers():
@@ -144,10 +176,11 @@ def test_exact_reciprocal_coordinate_split():
     # trunc((rem + 0.5) * (1 / stride)) in double precision instead of an
     # integer division; exhaustively equal to floor division on its range
     import numpy as np
-    rem = np.arange(4096, dtype=np.float64)
-    for d in range(1, 4097):
+    rem = np.arange(16384, dtype=np.float64)
+    ref = np.arange(16384)
+    for d in range(1, 16385):
         q = ((rem + 0.5) * (1.0 / d)).astype(np.int64)
-        assert np.array_equal(q, np.arange(4096) // d), d
+        assert np.array_equal(q, ref // d), d
 
 
 def test_state_plan_host_checks():

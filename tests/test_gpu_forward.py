@@ -80,6 +80,33 @@ def test_fenced_block_shapes(M, cut, mask, bz):
         assert_close(out, ref, label=str(b_mode))
 
 
+# three undetected modes (six block coordinates), with zero to four detected
+# modes; blocks of several row chunks; two undetected modes at cutoff 9 (6561
+# entries per node, more than one LDS tile per row chunk)
+THREE_U = [
+    (3, [3, 3, 3], 0b000, False), (4, [3, 2, 3, 3], 0b1000, False), (4, [3, 2, 3, 3], 0b1000, True),
+    (5, [2, 3, 2, 3, 3], 0b11000, False), (5, [3, 3, 3, 2, 2], 0b11000, True),
+    (6, [2, 2, 2, 3, 2, 2], 0b111000, False), (7, [2, 2, 2, 2, 2, 2, 2], 0b1111000, True),
+    (4, [4, 4, 4, 3], 0b1000, False), (4, [4, 3, 3, 3], 0b1000, False), (3, [9, 9, 3], 0b100, False),
+]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", THREE_U)
+def test_three_undetected_modes_and_large_blocks(M, cut, mask, bz):
+    rng = np.random.default_rng(3000 + M * 41 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.2)
+    ref = O.fock_diag(A, b, c, cut, mask)
+    for b_mode in (["auto", "zero"] if bz else ["auto", "general"]):
+        out = gpu(A, b, c, cut, mask, b_mode=b_mode)
+        assert out.shape == ref.shape
+        assert_close(out, ref, label=f"{cut} {bin(mask)} {b_mode}")
+    if M == 4 and cut[0] == 3:
+        out = gpu(A.astype(np.complex64), b.astype(np.complex64), np.complex64(c), cut, mask, dtype=torch.complex64)
+        err = O.rel_err(out, ref)
+        print(f"c64 rel_err {cut} {bin(mask)} = {err:.3e}", flush=True)
+        assert err < 1e-5
+
+
 def test_ragged_multi_tile_levels():
     # levels wider than one 256-thread tile, ragged tails, unequal cutoffs
     rng = np.random.default_rng(7)

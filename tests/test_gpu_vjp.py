@@ -89,6 +89,49 @@ def test_vjp_small_random(M, cut, mask, bz):
         check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref)
 
 
+# three undetected modes (six block coordinates) with zero to three detected
+# modes, and a mixed-cutoff block of 1296 entries
+THREE_U = [
+    (3, [3, 3, 3], 0b000, False), (4, [3, 2, 3, 3], 0b1000, False), (4, [3, 2, 3, 3], 0b1000, True),
+    (5, [2, 3, 2, 3, 3], 0b11000, False), (5, [3, 3, 3, 2, 2], 0b11000, True),
+    (6, [2, 2, 2, 3, 2, 2], 0b111000, False), (4, [4, 3, 3, 2], 0b1000, False),
+]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", THREE_U)
+def test_vjp_three_undetected_modes(M, cut, mask, bz):
+    rng = np.random.default_rng(4000 + M * 43 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.2)
+    shape = O.fock_diag(A, b, c, cut, mask).shape
+    g = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    check(gpu_vjp(A, b, c, cut, mask, g), ref, label=f"{cut} {bin(mask)}")
+    check(gpu_vjp(A, b, c, cut, mask, g, use_saved=False), ref, label=f"{cut} {bin(mask)} recompute")
+    if bz:
+        check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref, label=f"{cut} {bin(mask)} b=0")
+
+
+def test_vjp_block_beyond_lds_is_rejected_and_complex64_runs():
+    # two undetected modes at cutoff 9: the reverse fill holds 2 x 6561
+    # entries, too many complex128 values for the LDS (FD_ERR_UNSUPPORTED
+    # before any device work); complex64 values fit
+    rng = np.random.default_rng(45)
+    cut, mask = [9, 9, 3], 0b100
+    A, b, c = rand_triple(rng, 3, False, scale=0.2)
+    shape = O.fock_diag(A, b, c, cut, mask).shape
+    g = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    with pytest.raises(F.FockDiagError) as ei:
+        gpu_vjp(A, b, c, cut, mask, g)
+    assert ei.value.status == F.FD_ERR_UNSUPPORTED
+    ref = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    got = gpu_vjp(A.astype(np.complex64), b.astype(np.complex64), np.complex64(c), cut, mask, g,
+                  dtype=torch.complex64)
+    err = O.rel_err(np.concatenate([got[0].ravel(), got[1].ravel(), [got[2]]]),
+                    np.concatenate([ref[0].ravel(), ref[1].ravel(), [ref[2]]]))
+    print(f"c64 vjp rel_err {cut} {bin(mask)} = {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
 def test_vjp_ragged_multi_tile():
     rng = np.random.default_rng(21)
     A, b, c = rand_triple(rng, 4, False, scale=0.2)
