@@ -245,8 +245,9 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
  * barrier between steps.  Launches: prep (+ undetected block fill), the
  * sweep, the output permutation.  A circuit whose levels average at least
  * 2048 wavefront-sized units fills the device by itself and runs its own
- * level launches first (as fock_diag_fwd); the persistent sweep takes the
- * rest.
+ * level launches first (as fock_diag_fwd), and so does a circuit the sweep
+ * cannot stage (three undetected modes, or rows beyond its LDS); the
+ * persistent sweep takes the rest.
  *   plans      n plans of one dtype, created on the current device
  *   workspace  per circuit, >= fd_plan_workspace(plan, 0) bytes, 256-byte
  *              aligned; the n workspaces must not overlap (FD_ERR_INVALID_ARG)
@@ -255,8 +256,7 @@ fd_status detection_probs(fd_plan p, const void* A, const void* b, const void* c
  * table, per-circuit descriptors and the sweep's control words of the last 8
  * (plan set, pointer set) combinations in device memory (freed with the
  * plans); two batched calls with the same plans and pointers must not overlap
- * in time.  A circuit whose block is too large for the sweep's LDS staging,
- * or a device without cooperative launches, gives FD_ERR_UNSUPPORTED.  A
+ * in time.  A device without cooperative launches gives FD_ERR_UNSUPPORTED.  A
  * barrier wait that exceeds its bound (a few seconds) is reported by
  * fd_device_status of the first plan as FD_ERR_HIP. */
 fd_status fock_diag_fwd_batch(int n, const fd_plan* plans, const void* const* A,
@@ -278,16 +278,33 @@ fd_status fock_diag_vjp_batch(int n, const fd_plan* plans, const void* const* A,
                               void* const* workspace, const size_t* ws_bytes, hipStream_t stream);
 
 /* Scheduling knobs of fock_diag_fwd_batch (process-wide; a schedule built
- * under other knobs is rebuilt on next use): every step of a circuit is cut
- * into items of units / (items_per_wave x resident wavefronts) units, at
- * least min_block_units (lattice point, row chunk) units (Algorithm 2) or
- * min_point_units lattice points (Algorithm 1).  Defaults {2, 64, 4}; the
- * package's autotuner picks them per batch by timing.  Values below 1 give
+ * under other knobs is rebuilt on next use):
+ *   min_block_units, min_point_units, items_per_wave
+ *              every step of a circuit is cut into items of units /
+ *              (items_per_wave x resident wavefronts) units, at least
+ *              min_block_units (lattice point, row chunk) units (Algorithm 2)
+ *              or min_point_units lattice points (Algorithm 1);
+ *   fill_waves a circuit whose levels average at least fill_waves
+ *              wavefront-sized units runs its own level launches instead of
+ *              joining the persistent sweep;
+ *   use_graph  1: the first call with a given (plan set, pointer set) is
+ *              captured into a HIP graph on a private stream (nothing runs
+ *              during capture) and later calls with the same plans, pointers
+ *              and knobs replay it on the caller's stream (buffer contents
+ *              may change between calls); the last 8 graphs are kept and
+ *              freed with their plans.  fd_batch_get_tuning reads -1 if the
+ *              runtime refused a capture (a cooperative launch, say): calls
+ *              then run their launches directly.  Graphs are not used while
+ *              a plan of the batch records kernel times.
+ * Defaults {2, 64, 4, 2048, 0}; the package's autotuner picks them per batch
+ * signature by timing.  Values below 1 (use_graph: other than 0 or 1) give
  * FD_ERR_INVALID_ARG. */
 typedef struct {
   int32_t min_block_units;
   int32_t min_point_units;
   int32_t items_per_wave;
+  int32_t fill_waves;
+  int32_t use_graph;
 } fd_batch_tuning;
 fd_status fd_batch_set_tuning(const fd_batch_tuning* t);
 fd_status fd_batch_get_tuning(fd_batch_tuning* t);

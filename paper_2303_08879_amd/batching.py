@@ -86,23 +86,64 @@ class BatchRunner:
             F.fd_device_status(p)
 
 
-def autotune(runner, candidates=None, reps=1):
-    """Times the batched sweep of the runner's batch under each candidate
-    (min_block_units, min_point_units, items_per_wave), keeps the fastest
-    (set process-wide through fd_batch_set_tuning) and returns
-    (best, {candidate: seconds})."""
-    if candidates is None:
-        candidates = [(2, 64, 4), (4, 128, 2), (1, 64, 8), (8, 256, 2)]
+# Winners of earlier autotune calls, per batch signature (dtype and every
+# circuit's cutoffs and detection mask).
+_tuned = {}
+
+DEFAULT_TUNING = (2, 64, 4, 2048, 0)
+
+
+def _signature(runner):
+    return (str(runner.dtype),) + tuple((tuple(p.cutoffs), p.detected_mask) for p in runner.plans)
+
+
+def _time(runner, cand, reps):
+    F.fd_batch_set_tuning(*cand)
+    runner.run(True)           # builds the schedules (and graphs) under this tuning
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        runner.run(True)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def autotune(runner, candidates=None, reps=1, use_cache=True):
+    """Times the runner's batched calls under candidate knob sets
+    (min_block_units, min_point_units, items_per_wave, fill_waves, use_graph),
+    keeps the fastest (set process-wide through fd_batch_set_tuning) and
+    returns (best, {candidate: seconds}).
+
+    Without explicit candidates the search goes one knob group at a time from
+    the defaults: the item sizes, then the routing threshold fill_waves
+    (circuits whose levels average that many wavefront units run their own
+    level launches), then graph replay of the whole call.  The winner is
+    remembered per batch signature; a later call with the same signature sets
+    it without timing (``use_cache=False`` times again)."""
+    sig = _signature(runner)
+    if candidates is None and use_cache and sig in _tuned:
+        F.fd_batch_set_tuning(*_tuned[sig])
+        return _tuned[sig], {}
     times = {}
-    for cand in candidates:
-        F.fd_batch_set_tuning(*cand)
-        runner.run(True)           # builds the schedules under this tuning
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            runner.run(True)
-        torch.cuda.synchronize()
-        times[cand] = (time.perf_counter() - t0) / reps
+    if candidates is not None:
+        for cand in candidates:
+            cand = tuple(cand) + DEFAULT_TUNING[len(cand):]
+            times[cand] = _time(runner, cand, reps)
+    else:
+        best = DEFAULT_TUNING
+        for items in [(2, 64, 4), (4, 128, 2), (1, 64, 8), (8, 256, 2)]:
+            cand = items + best[3:]
+            times[cand] = _time(runner, cand, reps)
+        best = min(times, key=times.get)
+        for fill in (1024, 4096):
+            cand = best[:3] + (fill, best[4])
+            times[cand] = _time(runner, cand, reps)
+        best = min(times, key=times.get)
+        cand = best[:4] + (1,)
+        t = _time(runner, cand, reps)
+        if F.fd_batch_get_tuning()[4] == 1:   # -1: the runtime refused the capture
+            times[cand] = t
     best = min(times, key=times.get)
     F.fd_batch_set_tuning(*best)
+    _tuned[sig] = best
     return best, times

@@ -119,7 +119,7 @@ struct BatchSched {
 
 std::mutex g_mu;
 std::vector<BatchSched> g_cache;
-fd_batch_tuning g_tuning = {2, 64, 4};
+fd_batch_tuning g_tuning = {2, 64, 4, 2048, 0};
 
 fd_batch_tuning batch_tuning() { return g_tuning; }
 uint64_t g_clock = 0;
@@ -385,81 +385,55 @@ hipError_t launch_batch(const BatchSched& S, int n, const Plan& P0, hipStream_t 
 }  // namespace
 
 // A circuit fills the device on its own when its levels average at least
-// kFillWaves wavefront-sized units (about what the device holds at once):
-// such circuits run their own level launches, interleaving them with other
-// large circuits only multiplies the working set the L2s and the MALL hold.
-constexpr double kFillWaves = 2048.0;
-static bool fills_device(const Plan& Pl) {
+// `fill_waves` wavefront-sized units (about what the device holds at once,
+// 2048 by default): such circuits run their own level launches, interleaving
+// them with other large circuits only multiplies the working set the L2s and
+// the MALL hold.
+static bool fills_device(const Plan& Pl, double fill_waves) {
   if (Pl.MD == 0) return false;
   double units = 0.0;
   const ChunkGeo G = Pl.B > 1 ? chunk_geo(Pl) : ChunkGeo{1, 1, 1, 1};
   for (int s = 0; s <= Pl.smax; ++s)
     units += Pl.B > 1 ? (double)Pl.ncnt[s] * G.nchunks : (double)Pl.ncnt[s] / 64.0;
-  return units / (Pl.smax + 1) >= kFillWaves;
+  return units / (Pl.smax + 1) >= fill_waves;
 }
-
-static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* odd, const void* const* A,
-                                         const void* const* b, const void* const* c, void* const* rho,
-                                         void* const* ws, hipStream_t st, std::string* err);
 
 // The persistent sweep runs blocks of at most four coordinates (two
 // undetected modes) whose unit rows and fill fit its LDS staging; other
 // circuits take their own level launches.
+// Per-wave LDS parts of a circuit in the sweep (as build_sched lays them
+// out): its PN table, A and b, its block unit rows.
+struct WaveParts {
+  size_t pn = 0, sa = 0, rows = 0;
+};
+static WaveParts wave_parts(const Plan& Pl) {
+  const size_t eb = elem_bytes(Pl.dt);
+  WaveParts w;
+  w.pn = align16((size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int));
+  if (Pl.B > 1) {
+    w.sa = align16((size_t)Pl.npos * (Pl.npos + 1) * eb);
+    for (const ChunkGeo& G : {chunk_geo(Pl), chunk_geo(Pl, kBT / 2)})
+      w.rows = std::max(w.rows, ((size_t)(G.RC + 2) + (size_t)Pl.MD * (G.RC + 1)) * G.R0 * eb);
+  }
+  return w;
+}
 static bool sweep_takes(const Plan& Pl) {
   if (Pl.B == 1) return true;
   if (Pl.nq > 4) return false;
-  const size_t eb = elem_bytes(Pl.dt);
-  const size_t pnb = align16((size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int));
-  const size_t sa = align16((size_t)Pl.npos * (Pl.npos + 1) * eb);
-  size_t rows = 0;
-  for (const ChunkGeo& G : {chunk_geo(Pl), chunk_geo(Pl, kBT / 2)})
-    rows = std::max(rows, ((size_t)(G.RC + 2) + (size_t)Pl.MD * (G.RC + 1)) * G.R0 * eb);
-  return kTabBytes + align16(pnb + sa + rows) <= kMaxLds && ufill_lds_bytes(Pl, false) <= kMaxLds;
+  const WaveParts w = wave_parts(Pl);
+  return kTabBytes + align16(w.pn + w.sa + w.rows) <= kMaxLds && ufill_lds_bytes(Pl, false) <= kMaxLds;
 }
 
-fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
-                            const void* const* b, const void* const* c, void* const* rho, void* const* ws,
-                            hipStream_t st, std::string* err) {
-  // circuits that fill the device or that the sweep cannot stage: their own
-  // level launches; the others: one persistent sweep
-  std::vector<int> big, small;
-  for (int i = 0; i < n; ++i) (fills_device(*plans[i]) || !sweep_takes(*plans[i]) ? big : small).push_back(i);
-  for (int i : big) {
-    const hipError_t e = run_forward(*plans[i], odd[i], A[i], b[i], c[i], rho[i], ws[i], nullptr, st);
-    if (e != hipSuccess) {
-      *err = std::string("kernel launch failed: ") + hipGetErrorString(e);
-      return FD_ERR_HIP;
-    }
-  }
-  if (small.empty()) return FD_OK;
-  if (big.empty()) return run_forward_batch_small(n, plans, odd, A, b, c, rho, ws, st, err);
-  const size_t m = small.size();
-  std::vector<Plan*> p2(m);
-  std::unique_ptr<bool[]> o2(new bool[m]);
-  std::vector<const void*> A2(m), b2(m), c2(m);
-  std::vector<void*> r2(m), w2(m);
-  for (size_t k = 0; k < m; ++k) {
-    const int i = small[k];
-    p2[k] = plans[i];
-    o2[k] = odd[i];
-    A2[k] = A[i];
-    b2[k] = b[i];
-    c2[k] = c[i];
-    r2[k] = rho[i];
-    w2[k] = ws[i];
-  }
-  return run_forward_batch_small((int)m, p2.data(), o2.get(), A2.data(), b2.data(), c2.data(), r2.data(), w2.data(),
-                                 st, err);
-}
+namespace {
 
-static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* odd, const void* const* A,
-                                         const void* const* b, const void* const* c, void* const* rho,
-                                         void* const* ws, hipStream_t st, std::string* err) {
-  if (n == 0) return FD_OK;
+// Cache key of a batched call: device, plans, schedules, pointers, knobs.
+std::vector<uint64_t> batch_key(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                                const void* const* b, const void* const* c, void* const* rho, void* const* ws,
+                                const fd_batch_tuning& T) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::vector<uint64_t> key;
-  key.reserve(2 + 7 * (size_t)n);
+  key.reserve(7 + 7 * (size_t)n);
   key.push_back((uint64_t)dev);
   key.push_back((uint64_t)n);
   for (int i = 0; i < n; ++i) {
@@ -468,41 +442,207 @@ static fd_status run_forward_batch_small(int n, Plan* const* plans, const bool* 
     for (const void* p : {A[i], b[i], c[i], (const void*)rho[i], (const void*)ws[i]})
       key.push_back((uint64_t)reinterpret_cast<uintptr_t>(p));
   }
-  std::lock_guard<std::mutex> lock(g_mu);
-  key.push_back((uint64_t)g_tuning.min_block_units);
-  key.push_back((uint64_t)g_tuning.min_point_units);
-  key.push_back((uint64_t)g_tuning.items_per_wave);
-  BatchSched* S = nullptr;
+  key.push_back((uint64_t)T.min_block_units);
+  key.push_back((uint64_t)T.min_point_units);
+  key.push_back((uint64_t)T.items_per_wave);
+  key.push_back((uint64_t)T.fill_waves);
+  return key;
+}
+
+// The schedule of the persistent sweep over these circuits, built and
+// uploaded on `st` on first use.  Caller holds g_mu.
+fd_status sweep_sched(int n, Plan* const* plans, const bool* odd, const void* const* A, const void* const* b,
+                      const void* const* c, void* const* rho, void* const* ws, const fd_batch_tuning& T,
+                      hipStream_t st, BatchSched** out, std::string* err) {
+  std::vector<uint64_t> key = batch_key(n, plans, odd, A, b, c, rho, ws, T);
   for (BatchSched& s : g_cache)
-    if (s.key == key) S = &s;
-  if (!S) {
-    BatchSched ns;
-    ns.key = key;
-    for (int i = 0; i < n; ++i) ns.uids.push_back(plans[i]->uid);
-    const fd_status bs = plans[0]->dt == FD_C64 ? build_sched<float>(n, plans, odd, A, b, c, rho, ws, st, &ns, err)
-                                                : build_sched<double>(n, plans, odd, A, b, c, rho, ws, st, &ns, err);
-    if (bs != FD_OK) return bs;
-    if (g_cache.size() >= kBatchCache) {
-      auto it = std::min_element(g_cache.begin(), g_cache.end(),
-                                 [](const BatchSched& x, const BatchSched& y) { return x.last_use < y.last_use; });
-      free_sched(*it);
-      g_cache.erase(it);
+    if (s.key == key) {
+      s.last_use = ++g_clock;
+      *out = &s;
+      return FD_OK;
     }
-    g_cache.push_back(std::move(ns));
-    S = &g_cache.back();
+  BatchSched ns;
+  ns.key = std::move(key);
+  for (int i = 0; i < n; ++i) ns.uids.push_back(plans[i]->uid);
+  const fd_status bs = plans[0]->dt == FD_C64 ? build_sched<float>(n, plans, odd, A, b, c, rho, ws, st, &ns, err)
+                                              : build_sched<double>(n, plans, odd, A, b, c, rho, ws, st, &ns, err);
+  if (bs != FD_OK) return bs;
+  if (g_cache.size() >= kBatchCache) {
+    auto it = std::min_element(g_cache.begin(), g_cache.end(),
+                               [](const BatchSched& x, const BatchSched& y) { return x.last_use < y.last_use; });
+    free_sched(*it);
+    g_cache.erase(it);
   }
-  S->last_use = ++g_clock;
-  const hipError_t e = plans[0]->dt == FD_C64 ? launch_batch<float>(*S, n, *plans[0], st)
-                                              : launch_batch<double>(*S, n, *plans[0], st);
-  if (e != hipSuccess) {
-    *err = std::string("kernel launch failed: ") + hipGetErrorString(e);
-    return FD_ERR_HIP;
-  }
+  g_cache.push_back(std::move(ns));
+  *out = &g_cache.back();
+  (*out)->last_use = ++g_clock;
   return FD_OK;
 }
 
+// A batched call captured into a graph: the level launches of the circuits
+// that fill the device, then the persistent sweep's three launches.
+struct BatchGraph {
+  int device = -1;
+  std::vector<uint64_t> key, uids;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+std::vector<BatchGraph> g_graphs;
+hipStream_t g_capture[64] = {};   // private capture stream per device
+bool g_graph_failed = false;      // a capture was refused: batched calls run eagerly
+
+void free_graph(BatchGraph& g) {
+  if (unloading()) return;
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+struct Split {
+  std::vector<int> big, small;
+};
+
+Split split_batch(int n, Plan* const* plans, const fd_batch_tuning& T) {
+  Split sp;
+  for (int i = 0; i < n; ++i)
+    (fills_device(*plans[i], (double)T.fill_waves) || !sweep_takes(*plans[i]) ? sp.big : sp.small).push_back(i);
+  // one wave's LDS holds the largest PN table, A/b and unit rows of all
+  // members together: while they do not fit, the member with the most unit
+  // rows leaves the sweep
+  for (;;) {
+    WaveParts mx;
+    int worst = -1;
+    size_t worst_rows = 0;
+    for (size_t k = 0; k < sp.small.size(); ++k) {
+      const WaveParts w = wave_parts(*plans[sp.small[k]]);
+      mx.pn = std::max(mx.pn, w.pn);
+      mx.sa = std::max(mx.sa, w.sa);
+      mx.rows = std::max(mx.rows, w.rows);
+      if (worst < 0 || w.rows + w.sa > worst_rows) {
+        worst = (int)k;
+        worst_rows = w.rows + w.sa;
+      }
+    }
+    if (worst < 0 || kTabBytes + align16(mx.pn + mx.sa + mx.rows) <= kMaxLds) break;
+    sp.big.push_back(sp.small[worst]);
+    sp.small.erase(sp.small.begin() + worst);
+  }
+  return sp;
+}
+
+// Enqueues the whole batched call on `st`: the circuits that fill the device
+// (or that the sweep cannot stage) with their own level launches, then the
+// sweep over the others (its schedule `S`, built beforehand).
+hipError_t enqueue_batch(const Split& sp, Plan* const* plans, const bool* odd, const void* const* A,
+                         const void* const* b, const void* const* c, void* const* rho, void* const* ws,
+                         const BatchSched* S, hipStream_t st) {
+  for (int i : sp.big) {
+    const hipError_t e = run_forward(*plans[i], odd[i], A[i], b[i], c[i], rho[i], ws[i], nullptr, st);
+    if (e != hipSuccess) return e;
+  }
+  if (!S) return hipSuccess;
+  const Plan& P0 = *plans[sp.small[0]];
+  return P0.dt == FD_C64 ? launch_batch<float>(*S, (int)sp.small.size(), P0, st)
+                         : launch_batch<double>(*S, (int)sp.small.size(), P0, st);
+}
+
+}  // namespace
+
+fd_status run_forward_batch(int n, Plan* const* plans, const bool* odd, const void* const* A,
+                            const void* const* b, const void* const* c, void* const* rho, void* const* ws,
+                            hipStream_t st, std::string* err) {
+  if (n == 0) return FD_OK;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const fd_batch_tuning T = g_tuning;
+  const Split sp = split_batch(n, plans, T);
+  // the sweep's members, as arrays of their own
+  const size_t m = sp.small.size();
+  std::vector<Plan*> p2(m);
+  std::unique_ptr<bool[]> o2(new bool[m > 0 ? m : 1]);
+  std::vector<const void*> A2(m), b2(m), c2(m);
+  std::vector<void*> r2(m), w2(m);
+  for (size_t k = 0; k < m; ++k) {
+    const int i = sp.small[k];
+    p2[k] = plans[i];
+    o2[k] = odd[i];
+    A2[k] = A[i];
+    b2[k] = b[i];
+    c2[k] = c[i];
+    r2[k] = rho[i];
+    w2[k] = ws[i];
+  }
+  BatchSched* S = nullptr;
+  if (m > 0) {
+    const fd_status s = sweep_sched((int)m, p2.data(), o2.get(), A2.data(), b2.data(), c2.data(), r2.data(),
+                                    w2.data(), T, st, &S, err);
+    if (s != FD_OK) return s;
+  }
+  bool timing = false;
+  for (int i = 0; i < n; ++i) timing = timing || plans[i]->timing.mask != 0;
+  auto fail_hip = [&](hipError_t e) {
+    *err = std::string("kernel launch failed: ") + hipGetErrorString(e);
+    return FD_ERR_HIP;
+  };
+  if (T.use_graph <= 0 || g_graph_failed || timing) {
+    const hipError_t e = enqueue_batch(sp, plans, odd, A, b, c, rho, ws, S, st);
+    return e == hipSuccess ? FD_OK : fail_hip(e);
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::vector<uint64_t> key = batch_key(n, plans, odd, A, b, c, rho, ws, T);
+  for (BatchGraph& g : g_graphs)
+    if (g.key == key) {
+      g.last_use = ++g_clock;
+      const hipError_t e = hipGraphLaunch(g.exec, st);
+      return e == hipSuccess ? FD_OK : fail_hip(e);
+    }
+  hipError_t e;
+  if (dev < 0 || dev >= 64) return fail_hip(hipErrorInvalidDevice);
+  if (!g_capture[dev] && (e = hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking)) != hipSuccess)
+    return fail_hip(e);
+  hipStream_t cs = g_capture[dev];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool captured = false;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    const hipError_t eb = enqueue_batch(sp, plans, odd, A, b, c, rho, ws, S, cs);
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    captured = eb == hipSuccess && ee == hipSuccess && graph &&
+               hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  }
+  (void)hipGetLastError();
+  if (!captured) {
+    // the runtime would not capture (cooperative launches, for one): run
+    // this and later calls eagerly
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    g_graph_failed = true;
+    e = enqueue_batch(sp, plans, odd, A, b, c, rho, ws, S, st);
+    return e == hipSuccess ? FD_OK : fail_hip(e);
+  }
+  if (g_graphs.size() >= kBatchCache) {
+    auto it = std::min_element(g_graphs.begin(), g_graphs.end(),
+                               [](const BatchGraph& x, const BatchGraph& y) { return x.last_use < y.last_use; });
+    free_graph(*it);
+    g_graphs.erase(it);
+  }
+  BatchGraph g;
+  g.device = dev;
+  g.key = std::move(key);
+  for (int i = 0; i < n; ++i) g.uids.push_back(plans[i]->uid);
+  g.graph = graph;
+  g.exec = exec;
+  g.last_use = ++g_clock;
+  g_graphs.push_back(std::move(g));
+  e = hipGraphLaunch(exec, st);
+  return e == hipSuccess ? FD_OK : fail_hip(e);
+}
+
 fd_status batch_set_tuning(const fd_batch_tuning& T) {
-  if (T.min_block_units < 1 || T.min_point_units < 1 || T.items_per_wave < 1)
+  if (T.min_block_units < 1 || T.min_point_units < 1 || T.items_per_wave < 1 || T.fill_waves < 1 ||
+      T.use_graph < 0 || T.use_graph > 1)
     return FD_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(g_mu);
   g_tuning = T;
@@ -511,11 +651,21 @@ fd_status batch_set_tuning(const fd_batch_tuning& T) {
 
 fd_batch_tuning batch_get_tuning() {
   std::lock_guard<std::mutex> lock(g_mu);
-  return g_tuning;
+  fd_batch_tuning t = g_tuning;
+  if (t.use_graph > 0 && g_graph_failed) t.use_graph = -1;
+  return t;
 }
 
 void batch_forget(uint64_t uid) {
   std::lock_guard<std::mutex> lock(g_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    if (std::find(g_graphs[i].uids.begin(), g_graphs[i].uids.end(), uid) != g_graphs[i].uids.end()) {
+      free_graph(g_graphs[i]);
+      g_graphs.erase(g_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
   for (size_t i = 0; i < g_cache.size();) {
     if (std::find(g_cache[i].uids.begin(), g_cache[i].uids.end(), uid) != g_cache[i].uids.end()) {
       free_sched(g_cache[i]);

@@ -45,10 +45,10 @@ _live = weakref.WeakSet()
 class BatchTuning(ctypes.Structure):
     """fd_batch_tuning: scheduling knobs of fock_diag_fwd_batch."""
     _fields_ = [("min_block_units", ctypes.c_int32), ("min_point_units", ctypes.c_int32),
-                ("items_per_wave", ctypes.c_int32)]
+                ("items_per_wave", ctypes.c_int32), ("fill_waves", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.min_block_units, self.min_point_units, self.items_per_wave)
+        return (self.min_block_units, self.min_point_units, self.items_per_wave, self.fill_waves, self.use_graph)
 
 
 class FockDiagError(RuntimeError):
@@ -330,8 +330,9 @@ def fock_diag_fwd_batch(plans, As, bs, cs, rhos, workspaces, stream=None):
                                      _stream(stream)))
 
 
-def fd_batch_set_tuning(min_block_units, min_point_units, items_per_wave):
-    t = BatchTuning(int(min_block_units), int(min_point_units), int(items_per_wave))
+def fd_batch_set_tuning(min_block_units, min_point_units, items_per_wave, fill_waves=2048, use_graph=0):
+    t = BatchTuning(int(min_block_units), int(min_point_units), int(items_per_wave), int(fill_waves),
+                    int(use_graph))
     _check(lib().fd_batch_set_tuning(ctypes.byref(t)))
 
 

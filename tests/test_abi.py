@@ -159,14 +159,18 @@ def test_batch_rejects_bad_arguments_on_the_host():
 
 def test_batch_tuning_round_trip_and_range_checks():
     old = F.fd_batch_get_tuning()
+    assert old == (2, 64, 4, 2048, 0)
     try:
         F.fd_batch_set_tuning(3, 128, 5)
-        assert F.fd_batch_get_tuning() == (3, 128, 5)
-        for bad in [(0, 64, 2), (2, 0, 2), (2, 64, 0), (-4, 64, 2)]:
+        assert F.fd_batch_get_tuning() == (3, 128, 5, 2048, 0)
+        F.fd_batch_set_tuning(3, 128, 5, 512, 1)
+        assert F.fd_batch_get_tuning() == (3, 128, 5, 512, 1)
+        for bad in [(0, 64, 2), (2, 0, 2), (2, 64, 0), (-4, 64, 2), (2, 64, 2, 0), (2, 64, 2, 2048, 2),
+                    (2, 64, 2, 2048, -1)]:
             with pytest.raises(F.FockDiagError) as e:
                 F.fd_batch_set_tuning(*bad)
             assert e.value.status == F.FD_ERR_INVALID_ARG
-        assert F.fd_batch_get_tuning() == (3, 128, 5)
+        assert F.fd_batch_get_tuning() == (3, 128, 5, 512, 1)
     finally:
         F.fd_batch_set_tuning(*old)
 

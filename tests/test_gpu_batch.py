@@ -172,16 +172,74 @@ def test_batch_runner_memory_groups_and_autotune():
     assert len(runner.groups) > 1
     old = F.fd_batch_get_tuning()
     try:
-        best, times = Bt.autotune(runner, candidates=[(2, 64, 4), (1, 64, 1)])
+        best, times = Bt.autotune(runner, candidates=[(2, 64, 4), (1, 64, 1), (2, 64, 4, 1), (2, 64, 4, 2048, 1)])
         assert best in times and F.fd_batch_get_tuning() == best
+        assert (2, 64, 4, 1, 0) in times     # the routing threshold at its minimum
         got = {}
         runner.run(True, callback=lambda k, rho: got.update({i: r.cpu().numpy() for i, r in rho.items()}))
         runner.check_status()
         assert sorted(got) == list(range(len(circs)))
         for i, c in enumerate(circs):
             np.testing.assert_array_equal(got[i], run_single(c))
+        # the staged search, then its cached winner for the same signature
+        best2, times2 = Bt.autotune(runner, use_cache=False)
+        assert len(times2) >= 6 and F.fd_batch_get_tuning() == best2
+        best3, times3 = Bt.autotune(runner)
+        assert best3 == best2 and times3 == {}
     finally:
-        F.fd_batch_set_tuning(*old)
+        F.fd_batch_set_tuning(*old[:4], max(old[4], 0))
+
+
+def test_batch_graph_replay_matches_eager_over_repeated_calls():
+    # the whole batched call (level launches of the largest circuit, the
+    # sweep's prep, sweep and permutation) captured once and replayed; eager
+    # work and synchronisations between the replays; new input values between
+    # calls; every replay equal to the eager call bit for bit
+    rng = np.random.default_rng(352)
+    circs = small_batch(352, 10)
+    circs.append(W._circuit(rng, 5, 0.3, 0.8, lambda g, M: g.uniform(0.8, 0.95, size=M), [9, 8, 7, 6, 6], 0x1F))
+    dt = torch.complex128
+    plans = [ops.get_plan(c.cutoffs, c.detected_mask, dt, "zero") for c in circs]
+    ins = [[torch.as_tensor(x, dtype=dt, device="cuda").reshape(-1 if k == 2 else x.shape).contiguous()
+            for k, x in enumerate((c.A, c.b, np.asarray([c.c])))] for c in circs]
+    ws = [torch.empty(max(p.workspace(False)[0], 256), dtype=torch.uint8, device="cuda") for p in plans]
+    rho = [torch.empty(p.out_shape, dtype=dt, device="cuda") for p in plans]
+    old = F.fd_batch_get_tuning()
+    call = lambda: F.fock_diag_fwd_batch(plans, [x[0] for x in ins], [x[1] for x in ins], [x[2] for x in ins],
+                                         rho, ws)
+    c0 = [x[2].clone() for x in ins]
+    scale = (1.0, 1.25, 0.5)
+
+    def set_inputs(rep):
+        for x, c in zip(ins, c0):
+            x[2].copy_(c * scale[rep])
+
+    try:
+        # fill_waves = 4: the 5-mode circuit runs its own level launches
+        F.fd_batch_set_tuning(2, 64, 4, 4, 0)
+        refs = []
+        for rep in range(3):
+            set_inputs(rep)
+            call()
+            torch.cuda.synchronize()
+            refs.append([r.cpu().numpy() for r in rho])
+        F.fd_batch_set_tuning(2, 64, 4, 4, 1)
+        for rep in range(3):
+            set_inputs(rep)
+            for r in rho:
+                r.zero_()
+            call()
+            _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+            torch.cuda.synchronize()
+            for r, ref in zip(rho, refs[rep]):
+                np.testing.assert_array_equal(r.cpu().numpy(), ref)
+        graph_state = F.fd_batch_get_tuning()[4]
+        print(f"[batch graph] use_graph reads {graph_state}", flush=True)
+        assert graph_state in (1, -1)
+        for c, p in zip(circs, plans):
+            F.fd_device_status(p)
+    finally:
+        F.fd_batch_set_tuning(*old[:4], max(old[4], 0))
 
 
 def test_vjp_batch_matches_single_calls():
