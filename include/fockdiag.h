@@ -211,18 +211,20 @@ fd_status fock_diag_fwd_static(fd_plan p, const void* A, const void* b, const vo
 /* Forward mode (Sec. 2.5, the tangent recurrences summed along one
  * direction): rho and its directional derivative
  *     drho = sum_ij dA_ij d rho / d A_ij + sum_i db_i d rho / d b_i + dc d rho / d c
- * for a plan whose detected_mask covers every mode (Algorithm 1), box or
- * total-cutoff (fd_plan_create_total; rho and drho then in level order).
- * A is used through 1/2 (A + A^T), and so is dA.  Every kept amplitude carries
- * its tangent through the same reads and writes, so the sweep reads and writes
- * twice the forward's bytes.
+ * for any box plan (Algorithm 1, or Algorithm 2 with undetected modes: the
+ * tangent is carried through the undetected-block fill and the block units)
+ * and for total-cutoff plans (fd_plan_create_total; rho and drho then in
+ * level order).  A is used through 1/2 (A + A^T), and so is dA.  Every kept
+ * amplitude carries its tangent through the same reads and writes, so the
+ * sweep reads and writes twice the forward's bytes.
  *   dA, db, dc  device direction (2M x 2M, 2M, 1 complex elements, block order)
  *   rho, drho   device outputs, FD_Q_OUT_ELEMS complex elements each
  *   workspace   256-byte aligned device scratch of at least
  *               fd_plan_jvp_workspace bytes (values, then tangents)
- * Returns FD_ERR_UNSUPPORTED for plans with undetected modes and for plans
- * created with FD_B_ZERO (a non-zero db reaches the odd levels, which that
- * schedule skips).  With fd_plan_use_graphs the sweep is captured once per
+ * Returns FD_ERR_UNSUPPORTED for plans created with FD_B_ZERO (a non-zero db
+ * reaches the odd levels, which that schedule skips) and for undetected
+ * blocks whose values and tangents exceed the LDS staging (the block fill:
+ * 2B elements; the block units: twice the forward's rows).  With fd_plan_use_graphs the sweep is captured once per
  * set of pointers and replayed, as for fock_diag_fwd. */
 fd_status fd_plan_jvp_workspace(fd_plan p, size_t* bytes);
 fd_status fock_diag_jvp(fd_plan p, const void* A, const void* b, const void* c, const void* dA,

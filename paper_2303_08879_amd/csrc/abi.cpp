@@ -345,7 +345,12 @@ fd_status fock_diag_jvp(fd_plan p, const void* A, const void* b, const void* c, 
   fd_status s = check_ptrs(P, {A, b, c, dA, db, dc, rho, drho, workspace});
   if (s != FD_OK) return s;
   if (!aligned(workspace, 256)) return fail(FD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (P.B != 1) return fail(FD_ERR_UNSUPPORTED, "forward mode covers plans whose modes are all detected");
+  if (P.B > 1) {
+    const size_t rows = std::max(fd::fwd_lds_bytes_for(P, fd::chunk_geo(P), true),
+                                 fd::fwd_lds_bytes_for(P, fd::chunk_geo(P, fd::kBT / 2), true));
+    if ((P.MD > 0 && rows > fd::kMaxLds) || fd::ufill_jvp_lds_bytes(P) > fd::kMaxLds)
+      return fail(FD_ERR_UNSUPPORTED, "undetected block too large for the forward mode's LDS staging");
+  }
   if (P.flags == FD_B_ZERO)
     return fail(FD_ERR_UNSUPPORTED, "forward mode needs the odd levels: create the plan with FD_B_AUTO or FD_B_GENERAL");
   if (ws_bytes < 2 * fd::jvp_half_bytes(P)) return fail(FD_ERR_WORKSPACE, "workspace too small");

@@ -52,6 +52,33 @@ __device__ __forceinline__ cx<R> cadd(const cx<R>& a, const cx<R>& b) {
   return cmake<R>(a.x + b.x, a.y + b.y);
 }
 
+// Value and tangent of one amplitude (forward mode, Sec. 2.5): the tangent
+// of an element stored at p lives dT bytes after it.
+template <typename R>
+struct dual {
+  cx<R> v, t;
+};
+template <typename T>
+__device__ __forceinline__ T* tangent_of(T* p, int64_t dT) {
+  using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<Byte*>(p) + dT);
+}
+// acc += a * x for coefficient a and operand x, both with tangents:
+// (a x)' = a' x + a x'
+template <typename R>
+__device__ __forceinline__ void cfma(dual<R>& acc, const dual<R>& a, const dual<R>& x) {
+  cfma(acc.v, a.v, x.v);
+  cfma(acc.t, a.t, x.v);
+  cfma(acc.t, a.v, x.t);
+}
+template <typename R>
+__device__ __forceinline__ dual<R> cscale(const dual<R>& a, R s) {
+  dual<R> r;
+  r.v = cscale(a.v, s);
+  r.t = cscale(a.t, s);
+  return r;
+}
+
 // Element idx of one level's slab of a family through a 32-bit byte offset
 // from the level's base: the memory instruction then takes the base from
 // scalar registers and one 32-bit offset register instead of a 64-bit
@@ -79,6 +106,35 @@ __device__ __forceinline__ void st(cx<double>* p, const cx<double>& a) {
 __device__ __forceinline__ void st(cx<float>* p, const cx<float>& a) {
   *reinterpret_cast<float2*>(p) = make_float2(a.x, a.y);
 }
+
+// Zero, load and store of a sweep element: one complex amplitude, or an
+// amplitude with its tangent (dT bytes further on).
+template <typename E>
+struct ET;
+template <typename R>
+struct ET<cx<R>> {
+  static __device__ __forceinline__ cx<R> zero() { return czero<R>(); }
+  static __device__ __forceinline__ cx<R> load(const cx<R>* p, int64_t) { return ld(p); }
+  static __device__ __forceinline__ void store(cx<R>* p, const cx<R>& v, int64_t) { st(p, v); }
+};
+template <typename R>
+struct ET<dual<R>> {
+  static __device__ __forceinline__ dual<R> zero() {
+    dual<R> r;
+    r.v = r.t = czero<R>();
+    return r;
+  }
+  static __device__ __forceinline__ dual<R> load(const cx<R>* p, int64_t dT) {
+    dual<R> r;
+    r.v = ld(p);
+    r.t = ld(tangent_of(p, dT));
+    return r;
+  }
+  static __device__ __forceinline__ void store(cx<R>* p, const dual<R>& v, int64_t dT) {
+    st(p, v.v);
+    st(tangent_of(p, dT), v.t);
+  }
+};
 
 // Per-launch node-0 pointers of every family at the levels a sweep step
 // touches: rd = level S-1 (reads), wr = level S (writes), plus F0 at S and

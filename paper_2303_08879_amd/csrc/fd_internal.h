@@ -177,6 +177,13 @@ inline size_t ufill_lds_bytes(const Plan& P, bool vjp) {
          (size_t)(P.B + P.wmax + 2) * sizeof(int);
 }
 
+// LDS of the block fill with tangents (forward mode): values and tangents of
+// the block, of A and b between undetected positions, then the tables.
+inline size_t ufill_jvp_lds_bytes(const Plan& P) {
+  return ufill_lds_bytes(P, false) + (size_t)P.B * elem_bytes(P.dt) +
+         (size_t)(kMaxUq * kMaxUq + kMaxUq) * elem_bytes(P.dt);
+}
+
 // level_cap >= 0: every mode with cutoff >= 2 detected, only lattice points
 // with |n| <= level_cap (the levels of a total photon cutoff), F0 returned in
 // level order.
@@ -209,7 +216,7 @@ size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kerne
 // Dynamic LDS of the forward block kernel for one chunk geometry: F0 rows
 // [k0-2, k1), MD bridge pivot blocks of rows [k0-1, k1), A and b, the
 // square-root tables.
-size_t fwd_lds_bytes_for(const Plan& P, const ChunkGeo& G);
+size_t fwd_lds_bytes_for(const Plan& P, const ChunkGeo& G, bool jvp = false);   // jvp: values and tangents
 size_t vjp_lds_bytes_for(const Plan& P, const ChunkGeo& G);   // ... for one chunk geometry
 constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);

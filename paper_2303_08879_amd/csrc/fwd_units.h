@@ -72,30 +72,32 @@ __device__ __forceinline__ void prep_body(const cx<R>* __restrict__ A, const cx<
 // The weights form a chain of dependent steps, so everything a step reads
 // (entry list, A and b between undetected positions, square-root tables) is
 // staged in LDS first and a step never waits on global memory.
-// LDS: ufill_lds_bytes(plan, false).
+// LDS: ufill_lds_bytes(plan, false) (E = cx<R>); the forward mode carries
+// value and tangent (E = dual<R>) through the same steps.
 // ---------------------------------------------------------------------------
-template <typename R, int NQ>
+template <typename R, int NQ, typename E>
 __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __restrict__ Ai,
                                            const cx<R>* __restrict__ bi, cx<R>* G, const int* __restrict__ elist,
-                                           const int* __restrict__ woff, int wmax, cx<R>* g) {
+                                           const int* __restrict__ woff, int wmax, E* g, int64_t dT = 0) {
+  using T = ET<E>;
   constexpr int nq = NQ;   // 2 per undetected mode
   const int npos = P.npos, B = P.B;
   const int lane = threadIdx.x & 63;
-  cx<R>* sA = g + B;   // A between undetected positions, row stride NQ
-  cx<R>* sb = sA + NQ * NQ;
+  E* sA = g + B;   // A between undetected positions, row stride NQ
+  E* sb = sA + NQ * NQ;
   R* sq = reinterpret_cast<R*>(sb + NQ);
   R* isq = sq + (kMaxCut + 4);
   int* el = reinterpret_cast<int*>(isq + (kMaxCut + 4));
   int* wo = el + B;
   for (int t = lane; t < B; t += 64) el[t] = elist[t];
   for (int t = lane; t < wmax + 2; t += 64) wo[t] = woff[t];
-  for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = ld(Ai + (i / nq) * npos + i % nq);
-  if (lane < nq) sb[lane] = ld(bi + lane);
+  for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = T::load(Ai + (i / nq) * npos + i % nq, dT);
+  if (lane < nq) sb[lane] = T::load(bi + lane, dT);
   for (int v = lane; v < kMaxCut + 4; v += 64) {
     sq[v] = sqrt(R(v));
     isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
   }
-  if (lane == 0) g[0] = ld(G);   // c, written by the prep kernel
+  if (lane == 0) g[0] = T::load(G, dT);   // c, written by the prep kernel
   wave_sync();
   for (int w = 1; w <= wmax; ++w) {
     const int t1 = wo[w + 1];
@@ -120,7 +122,7 @@ __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __rest
           kqf = kap[q];
         }
       const int pe = e - usf;
-      cx<R> acc = czero<R>();
+      E acc = T::zero();
       cfma(acc, sb[qf], g[pe]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -132,7 +134,7 @@ __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __rest
     }
     wave_sync();
   }
-  for (int e = lane; e < B; e += 64) st(G + e, g[e]);
+  for (int e = lane; e < B; e += 64) T::store(G + e, g[e], dT);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,10 +263,11 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 // LDS: F0(m) rows [k0-2, k1) and the bridge pivot blocks F1k(K)(m), rows
 // [k0-1, k1), for every bridge K applied at m.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R, typename LP>
-__device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const cx<R>* sA, const cx<R>* sb,
+template <int MD, int NQ, typename R, typename LP, typename E>
+__device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const E* sA, const E* sb,
                                                const R* sq, const R* isq, int S, int r, int c, const ChunkGeo& G,
-                                               cx<R>* lf0, cx<R>* lpk) {
+                                               E* lf0, E* lpk, int64_t dT = 0) {
+  using T = ET<E>;
   constexpr int NPD = 2 * MD;
   constexpr int NPOS = NQ + NPD;
   // Fences between loop iterations for the shapes whose unfenced build needs
@@ -289,7 +292,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
     {
       const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
       const int base = (k0 - 2) * R0;
-      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = ld(at32(L.f0cur, (uint32_t)(r * B + e)));
+      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = T::load(at32(L.f0cur, (uint32_t)(r * B + e)), dT);
     }
     wave_sync();
     // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
@@ -306,19 +309,19 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           rem -= kap[q] * P.ustride[q];
         }
         const int le = e - (k0 - 2) * R0;
-        const cx<R> piv = lf0[le];
-        cx<R> un[NQ];
+        const E piv = lf0[le];
+        E un[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(lf0[le - P.ustride[q]], sq[kap[q]]) : czero<R>();
-        cx<R> x[NPD];
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(lf0[le - P.ustride[q]], sq[kap[q]]) : T::zero();
+        E x[NPD];
 #pragma unroll
         for (int j = 0; j < MD; ++j) {
           if (m[j] > 0) {
-            x[2 * j] = cscale(ld(at32(L.rd[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
-            x[2 * j + 1] = cscale(ld(at32(L.rd[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            x[2 * j] = cscale(T::load(at32(L.rd[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e)), dT), sq[m[j]]);
+            x[2 * j + 1] = cscale(T::load(at32(L.rd[fam_f1k(j)], (uint32_t)(rdn[j] * B + e)), dT), sq[m[j]]);
           } else {
-            x[2 * j] = czero<R>();
-            x[2 * j + 1] = czero<R>();
+            x[2 * j] = T::zero();
+            x[2 * j + 1] = T::zero();
           }
         }
 #pragma unroll
@@ -331,14 +334,14 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
             const bool bridge = side == 0 && j <= K0 && m[j] <= P.CD[j] - 2;
             if (!(ok && own) && !bridge) continue;
             const int row = (NQ + i) * NPOS;
-            cx<R> acc = czero<R>();
+            E acc = T::zero();
             cfma(acc, sb[NQ + i], piv);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
 #pragma unroll
             for (int l = 0; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
             acc = cscale(acc, isq[m[j] + 1]);
-            if (ok && own) st(at32(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)], (uint32_t)(r * B + e)), acc);
+            if (ok && own) T::store(at32(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)], (uint32_t)(r * B + e)), acc, dT);
             if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
           }
         }
@@ -350,7 +353,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
       if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
-      const cx<R>* pv = lpk + (size_t)K * pk1;
+      const E* pv = lpk + (size_t)K * pk1;
       for (int e = k0 * R0 + lane; e < k1 * R0; e += kBT) {
         int kap[NQ];
         int rem = e;
@@ -360,21 +363,21 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           rem -= kap[q] * P.ustride[q];
         }
         const int lp = e - (k0 - 1) * R0;
-        const cx<R> piv = pv[lp];
-        cx<R> un[NQ];
+        const E piv = pv[lp];
+        E un[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : czero<R>();
-        cx<R> x[NPD];
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : T::zero();
+        E x[NPD];
         x[2 * K] = cscale(lf0[e - (k0 - 2) * R0], sq[m[K] + 1]);
-        x[2 * K + 1] = (m[K] > 0) ? cscale(ld(at32(L.rd[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]) : czero<R>();
+        x[2 * K + 1] = (m[K] > 0) ? cscale(T::load(at32(L.rd[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e)), dT), sq[m[K]]) : T::zero();
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
           if (m[j] > 0) {
-            x[2 * j] = cscale(ld(at32(L.rd[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
-            x[2 * j + 1] = cscale(ld(at32(L.rd[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            x[2 * j] = cscale(T::load(at32(L.rd[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e)), dT), sq[m[j]]);
+            x[2 * j + 1] = cscale(T::load(at32(L.rd[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e)), dT), sq[m[j]]);
           } else {
-            x[2 * j] = czero<R>();
-            x[2 * j + 1] = czero<R>();
+            x[2 * j] = T::zero();
+            x[2 * j + 1] = T::zero();
           }
         }
 #pragma unroll
@@ -398,13 +401,13 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           }
           if (!ok) continue;
           const int row = (NQ + i) * NPOS;
-          cx<R> acc = czero<R>();
+          E acc = T::zero();
           cfma(acc, sb[NQ + i], piv);
 #pragma unroll
           for (int q = 0; q < NQ; ++q) cfma(acc, sA[row + q], un[q]);
 #pragma unroll
           for (int l = 2 * K; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
-          st(dst, cscale(acc, scale));
+          T::store(dst, cscale(acc, scale), dT);
         }
         if constexpr (kFence) compiler_fence();
       }

@@ -16,14 +16,15 @@ __global__ void k_prep(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
   prep_body<R>(A, b, c, Ai, bi, ci, f0node0, a, status);
 }
 
-// Step 1 of Algorithm 2: one wavefront, the undetected block in LDS.
-template <typename R, int NQ>
+// Step 1 of Algorithm 2: one wavefront, the undetected block in LDS (with
+// E = dual<R>: values and tangents, the tangents dT bytes after the values).
+template <typename R, int NQ, typename E = cx<R>>
 __global__ __launch_bounds__(64) void k_ufill(DevPlan P, const cx<R>* __restrict__ Ai,
                                               const cx<R>* __restrict__ bi, cx<R>* G,
                                               const int* __restrict__ elist, const int* __restrict__ woff,
-                                              int wmax) {
+                                              int wmax, int64_t dT) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  ufill_body<R, NQ>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<cx<R>*>(smem_raw));
+  ufill_body<R, NQ>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<E*>(smem_raw), dT);
 }
 
 // Algorithm 1 (every mode detected): one thread per lattice point of level S.
@@ -42,28 +43,31 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
 }
 
 // Algorithm 2: one wavefront per (lattice point, chunk of undetected rows).
-template <int MD, int NQ, typename R>
+// E = dual<R> carries every amplitude's tangent along (forward mode), dT
+// bytes after the value.
+template <int MD, int NQ, typename R, typename E>
 __global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
-                                                   const cx<R>* __restrict__ bi, int S, int nwork, ChunkGeo G) {
+                                                   const cx<R>* __restrict__ bi, int S, int nwork, ChunkGeo G,
+                                                   int64_t dT) {
   constexpr int NPOS = NQ + 2 * MD;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R0 = G.R0;
-  cx<R>* lf0 = reinterpret_cast<cx<R>*>(smem_raw);             // (RC + 2) rows
-  cx<R>* lpk = lf0 + (size_t)(G.RC + 2) * R0;                  // MD x (RC + 1) rows
-  cx<R>* sA = lpk + (size_t)MD * (G.RC + 1) * R0;              // A (NPOS x NPOS) then b (NPOS)
-  const cx<R>* sb = sA + NPOS * NPOS;
+  E* lf0 = reinterpret_cast<E*>(smem_raw);             // (RC + 2) rows
+  E* lpk = lf0 + (size_t)(G.RC + 2) * R0;              // MD x (RC + 1) rows
+  E* sA = lpk + (size_t)MD * (G.RC + 1) * R0;          // A (NPOS x NPOS) then b (NPOS)
+  const E* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
   for (int v = threadIdx.x; v < kMaxCut + 4; v += blockDim.x) {
     sq[v] = sqrt(R(v));
     isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
   }
-  for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ld(Ai + i);
+  for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ET<E>::load(Ai + i, dT);
   // one wavefront per workgroup: the unit's first wave_sync orders these
   // LDS writes before their reads
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
-    fwd_block_unit<MD, NQ, R>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk);
+    fwd_block_unit<MD, NQ, R>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk, dT);
   }
 }
 
@@ -101,13 +105,14 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // Rows of the first undetected coordinate per chunk: about `target` own
 // entries (default one wavefront), spread evenly over the rows.
 
-template <int MD, int NQ, typename R>
+template <int MD, int NQ, typename R, typename E = cx<R>>
 static void launch_fwd_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const LevelPtrs<R>& L,
-                               const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G) {
+                               const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G,
+                               int64_t dT = 0) {
   if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R, E>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G);
+  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R, E>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G, dT);
 }
 
 // The undetected-block fill for the plan's number of block coordinates.
@@ -120,7 +125,7 @@ static hipError_t launch_ufill(const Plan& Pl, const DevPlan& P, const cx<R>* Ai
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
-  hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax);
+  hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -524,11 +529,6 @@ hipError_t run_forward(const Plan& Pl, bool odd, const void* A, const void* b, c
 // values, so every kept amplitude gets its tangent in a second workspace of
 // the same layout, dT bytes further on, and one thread carries both.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T* tangent_of(T* p, int64_t dT) {
-  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
-  return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + dT);
-}
 
 template <int MD, typename R>
 __global__ __launch_bounds__(kThreads) void k_fwd_point_jvp(DevPlan P, LevelPtrs<R> L, int64_t dT,
@@ -686,6 +686,18 @@ static hipError_t run_jvp_t(const Plan& Pl, const void* A, const void* b, const 
     if ((e = launch_prep(Pl, A, b, c, Ai, f0, st)) != hipSuccess) return e;
     if ((e = launch_prep(Pl, dA, db, dc, dAi, tf0, st)) != hipSuccess) return e;
   }
+  if (Pl.B > 1) {
+    // step 1 of Algorithm 2 with tangents
+    KTimer kt(Pl, KK_UFILL, st);
+    const size_t shm = ufill_jvp_lds_bytes(Pl);
+    if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
+    auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2, dual<R>> : Pl.nq == 4 ? &k_ufill<R, 4, dual<R>> : &k_ufill<R, 6, dual<R>>;
+    if (shm > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+    hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, f0, Pl.d_elist, Pl.d_woff, Pl.wmax, half);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const size_t tab = 2 * (kMaxCut + 4) * sizeof(R) + (size_t)(Pl.MD + 1) * (Pl.smax + 3) * sizeof(int);
   for (int S = 0; S <= Pl.smax && Pl.MD > 0; ++S) {
     const int nwork = (int)Pl.ncnt[S];
@@ -700,8 +712,40 @@ static hipError_t run_jvp_t(const Plan& Pl, const void* A, const void* b, const 
     }
     L.f0cur = fam_level_ptr<R>(Pl, ws, Lw.f0, 0, S, false);
     L.f0nxt = S < Pl.smax ? fam_level_ptr<R>(Pl, ws, Lw.f0, 0, S + 1, false) : nullptr;
-    const int grid = (nwork + kThreads - 1) / kThreads;
     KTimer kt(Pl, KK_FWD_LEVEL, st);
+    if (Pl.B > 1) {
+      L.node = Pl.d_node + (size_t)Pl.lvl[S] * kNodeStride;
+      ChunkGeo G = chunk_geo(Pl);
+      if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
+      const size_t shm = fwd_lds_bytes_for(Pl, G, true);
+      if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
+      const int grid = nwork * G.nchunks;
+#define FD_LAUNCH_BLOCK_JVP(MDV)                                                                          \
+  case MDV:                                                                                              \
+    if (Pl.nq == 2)                                                                                      \
+      launch_fwd_block_k<MDV, 2, R, dual<R>>(shm, grid, st, P, L, Ai, bi, S, nwork, G, half);            \
+    else if (Pl.nq == 4)                                                                                 \
+      launch_fwd_block_k<MDV, 4, R, dual<R>>(shm, grid, st, P, L, Ai, bi, S, nwork, G, half);            \
+    else                                                                                                 \
+      launch_fwd_block_k<MDV, 6, R, dual<R>>(shm, grid, st, P, L, Ai, bi, S, nwork, G, half);            \
+    break;
+      switch (Pl.MD) {
+        FD_LAUNCH_BLOCK_JVP(1)
+        FD_LAUNCH_BLOCK_JVP(2)
+        FD_LAUNCH_BLOCK_JVP(3)
+        FD_LAUNCH_BLOCK_JVP(4)
+        FD_LAUNCH_BLOCK_JVP(5)
+        FD_LAUNCH_BLOCK_JVP(6)
+        FD_LAUNCH_BLOCK_JVP(7)
+        FD_LAUNCH_BLOCK_JVP(8)
+        default:
+          return hipErrorInvalidValue;
+      }
+#undef FD_LAUNCH_BLOCK_JVP
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      continue;
+    }
+    const int grid = (nwork + kThreads - 1) / kThreads;
 #define FD_LAUNCH_JVP(MDV)                                                                                        \
   case MDV:                                                                                                       \
     hipLaunchKernelGGL((k_fwd_point_jvp<MDV, R>), dim3(grid), dim3(kThreads), tab, st, P, L, half, Ai, bi, dAi,  \

@@ -390,9 +390,9 @@ size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
 }
 
-size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
+size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G, bool jvp) {
   return (((size_t)(G.RC + 2) + (size_t)Pl.MD * (G.RC + 1)) * G.R0 + (size_t)Pl.npos * (Pl.npos + 1)) *
-             elem_bytes(Pl.dt) +
+             elem_bytes(Pl.dt) * (jvp ? 2 : 1) +
          2 * (kMaxCut + 4) * (elem_bytes(Pl.dt) / 2);
 }
 

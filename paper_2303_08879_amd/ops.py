@@ -90,9 +90,8 @@ class FockDiagFunction(torch.autograd.Function):
     """rho = fock_diag(A, b, c); backward = fock_diag_vjp with the saved
     intermediate amplitudes (PyTorch's complex-gradient convention: the
     incoming gradient g yields sum g conj(d rho / d x)); forward-mode AD with
-    dual tensors (torch.autograd.forward_ad) = fock_diag_jvp, for plans
-    whose modes are all detected (rho is holomorphic in A, b, c, so the
-    tangent is sum dx d rho / d x)."""
+    dual tensors (torch.autograd.forward_ad) = fock_diag_jvp (rho is
+    holomorphic in A, b, c, so the tangent is sum dx d rho / d x)."""
 
     @staticmethod
     def forward(ctx, A, b, c, cutoffs, detected_mask, b_mode):

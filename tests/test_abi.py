@@ -226,9 +226,12 @@ def test_density_jvp_host_checks():
     # the b = 0 schedule skips the odd levels a non-zero db reaches
     pz = F.Plan([4, 3], 0b11, torch.complex128, "zero")
     assert L.fock_diag_jvp(pz.handle, *ptrs, 256, 1 << 30, None) == F.FD_ERR_UNSUPPORTED
-    # an undetected mode (Algorithm 2) is not covered
-    pu = F.Plan([4, 3], 0b10, torch.complex128, "general")
-    assert L.fock_diag_jvp(pu.handle, *ptrs, 256, 1 << 30, None) == F.FD_ERR_UNSUPPORTED
+    # undetected blocks whose values and tangents exceed the LDS staging:
+    # two undetected modes at cutoff 9 with five detected modes (the forward
+    # alone fits)
+    pu = F.Plan([9, 9, 3, 3, 3, 3, 3], 0b1111100, torch.complex128, "general")
+    assert L.fock_diag_jvp(pu.handle, *ptrs, 256, 1 << 40, None) == F.FD_ERR_UNSUPPORTED
+    assert "LDS" in F.fd_last_error()
 
 
 def test_exact_reciprocal_digit_split_of_cindex():

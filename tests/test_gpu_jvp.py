@@ -1,7 +1,8 @@
 """GPU parity of the density-matrix forward mode (fock_diag_jvp: rho and its
-derivative along a direction (dA, db, dc), every mode detected) against the
-oracle's tangent recurrences (Sec. 2.5), through the C ABI.  Bar (c128):
-normwise relative error <= 1e-10 for rho and for drho."""
+derivative along a direction (dA, db, dc); every mode detected, or undetected
+modes through the block units) against the oracle's tangent recurrences
+(Sec. 2.5), through the C ABI.  Bar (c128, tests/parity.py): relative error
+<= 1e-10 for rho and for drho, normwise and entry by entry."""
 import numpy as np
 import pytest
 import torch
@@ -30,9 +31,10 @@ def rand_dir(rng, M):
     return dA, db, complex(rng.standard_normal(), rng.standard_normal())
 
 
-def gpu_jvp(A, b, c, dA, db, dc, cut, dtype=torch.complex128, b_mode="general", total=None):
-    print(f"[gpu] jvp cut={cut} total={total} dtype={dtype} b_mode={b_mode}", flush=True)
-    mask = 0 if total is not None else (1 << len(cut)) - 1
+def gpu_jvp(A, b, c, dA, db, dc, cut, dtype=torch.complex128, b_mode="general", total=None, mask=None):
+    print(f"[gpu] jvp cut={cut} total={total} mask={mask} dtype={dtype} b_mode={b_mode}", flush=True)
+    if mask is None:
+        mask = 0 if total is not None else (1 << len(cut)) - 1
     plan = F.Plan(cut, mask, dtype, b_mode, total_cutoff=total)
     T = lambda x: torch.tensor(np.asarray(x), dtype=dtype, device="cuda")
     ws = torch.empty(plan.jvp_workspace(), dtype=torch.uint8, device="cuda")
@@ -61,6 +63,51 @@ def test_jvp_small(M, cut, bz):
         rho, drho = gpu_jvp(A, b, c, dA, db, dc, cut, b_mode=b_mode)
         assert_close(rho, ref, label="gpu_jvp:61")
         assert_close(drho, dref, label="gpu_jvp:62")
+
+
+# Algorithm 2 plans: one, two and three undetected modes (first or not),
+# nothing detected, several row chunks per node
+UNDET = [(2, [5, 4], 0b10), (2, [5, 4], 0b01), (3, [4, 3, 3], 0b110), (3, [3, 4, 3], 0b101),
+         (3, [4, 3, 3], 0b100), (4, [3, 3, 3, 3], 0b1100), (4, [3, 2, 3, 3], 0b1000), (2, [4, 3], 0b00),
+         (3, [12, 3, 3], 0b110), (4, [3, 1, 4, 3], 0b1010)]
+
+
+@pytest.mark.parametrize("M,cut,mask", UNDET)
+@pytest.mark.parametrize("bz", [False, True])
+def test_jvp_undetected_modes(M, cut, mask, bz):
+    rng = np.random.default_rng(600 + 19 * M + sum(cut) + mask + bz)
+    A, b, c = rand_triple(rng, M, bz, scale=0.2)
+    dA, db, dc = rand_dir(rng, M)
+    ref, dref = O.fock_diag_jvp(A, b, c, cut, mask, dA, db, dc)
+    for b_mode in (["general", "auto"] if bz else ["general"]):
+        rho, drho = gpu_jvp(A, b, c, dA, db, dc, cut, b_mode=b_mode, mask=mask)
+        assert rho.shape == ref.shape
+        assert_close(rho, ref, label=f"rho {cut} {bin(mask)}")
+        assert_close(drho, dref, label=f"drho {cut} {bin(mask)}")
+    rho, drho = gpu_jvp(A.astype(np.complex64), b.astype(np.complex64), np.complex64(c), dA.astype(np.complex64),
+                        db.astype(np.complex64), np.complex64(dc), cut, dtype=torch.complex64, mask=mask)
+    err = O.rel_err(drho, dref)
+    print(f"c64 jvp rel_err {cut} {bin(mask)}: rho {O.rel_err(rho, ref):.3e} drho {err:.3e}", flush=True)
+    assert err < 1e-4
+
+
+def test_jvp_config2_full_size_sampled_patterns():
+    # the 4-mode conditional workload at full size (undetected cutoff 30,
+    # detected cutoffs 12, b != 0): rho and drho at sampled patterns n, each
+    # against the oracle's tangent recurrences on the box with detected
+    # cutoffs n + 1 (amplitudes and tangents do not depend on the cutoffs)
+    from paper_2303_08879_amd import workloads as W
+    circ = W.config2()
+    rng = np.random.default_rng(71)
+    dA, db, dc = rand_dir(rng, circ.M)
+    rho, drho = gpu_jvp(circ.A, circ.b, circ.c, dA, db, dc, circ.cutoffs, mask=circ.detected_mask)
+    assert rho.shape == (30, 30, 12, 12, 12)
+    for n in [(0, 0, 0), (1, 1, 1), (5, 0, 0), (0, 7, 0), (0, 0, 11), (2, 1, 1), (1, 0, 3)]:
+        cut = [circ.cutoffs[0]] + [k + 1 for k in n]
+        ref, dref = O.fock_diag_jvp(circ.A, circ.b, circ.c, cut, circ.detected_mask, dA, db, dc)
+        idx = (slice(None), slice(None)) + n
+        assert_close(rho[idx], ref[idx], label=f"config2 rho{n}")
+        assert_close(drho[idx], dref[idx], label=f"config2 drho{n}")
 
 
 def test_jvp_multi_tile_sampled():
