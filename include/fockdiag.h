@@ -76,21 +76,15 @@ enum { FD_B_AUTO = 0u, FD_B_ZERO = 1u, FD_B_GENERAL = 2u };
  * prod over detected cutoffs < 2^31 (<= 2^22 when a mode is undetected: the
  * plan keeps a 96-byte record per detected lattice point), one level of the
  * detected lattice times the undetected block <= 2^28 amplitudes,
- * undetected block B = prod C_u^2 <= 16384, and the LDS staging (160 KiB per
- * workgroup) must hold
- *   forward:  the block fill (B elements and B + sum 2(C_u - 1) + 2 ints) and
- *             (3 + 2 |D|) rows of B / C_u0 elements (C_u0 the first
- *             undetected cutoff), else fd_plan_create returns
- *             FD_ERR_UNSUPPORTED;
- *   reverse:  the block fill (2 B elements) and (2 + 2|U|) such rows plus
- *             the record staging, else fock_diag_vjp returns
- *             FD_ERR_UNSUPPORTED.
- * E.g. in complex128: two undetected modes at cutoff 9, forward with up to
- * 5 detected modes and no reverse sweep (complex64: both); three undetected
- * modes at cutoff 3, forward and reverse with up to 8 detected modes; at
- * cutoff 4, forward with up to 3 detected modes.  Blocks are not streamed
- * from HBM.  Modes with cutoff 1 carry no photons and are dropped
- * internally. */
+ * undetected block B = prod C_u^2 <= 65536.  A node's block rows are staged
+ * in LDS (160 KiB per workgroup) where they fit; otherwise, per kernel, they
+ * stream from HBM (the forward and reverse block units read the rows where
+ * they lie and keep their computed rows in per-workgroup slots of the
+ * workspace, the block fills work on the block in HBM), which
+ * fd_plan_workspace accounts for.  The forward mode (fock_diag_jvp) does not
+ * stream: its LDS rows hold values and tangents, and blocks beyond them give
+ * FD_ERR_UNSUPPORTED there.  Modes with cutoff 1 carry no photons and are
+ * dropped internally. */
 
 typedef struct fd_plan_s* fd_plan;
 

@@ -374,7 +374,7 @@ fd_status fock_diag_vjp(fd_plan p, const void* A, const void* b, const void* c, 
   if (s != FD_OK) return s;
   if (!aligned(workspace, 256) || (saved && !aligned(saved, 256)))
     return fail(FD_ERR_INVALID_ARG, "workspace and saved must be 256-byte aligned");
-  if (P.B > 1 && (fd::vjp_lds_bytes(P) > fd::kMaxLds || fd::ufill_lds_bytes(P, true) > fd::kMaxLds))
+  if (P.B > 1 && (fd::vjp_lds_bytes(P) > fd::kMaxLds || fd::ufill_launch_lds_bytes(P, true) > fd::kMaxLds))
     return fail(FD_ERR_UNSUPPORTED, "undetected block too large for the reverse sweep's LDS staging");
   bool b_zero = false;
   if ((s = decide_b_zero(P, b, stream, &b_zero)) != FD_OK) return s;

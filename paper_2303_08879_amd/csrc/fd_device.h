@@ -172,6 +172,17 @@ __device__ __forceinline__ void wave_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Orders a unit's phases: LDS traffic within the wavefront, or (ST, rows in
+// global memory) a workgroup-scope fence and barrier, which makes one lane's
+// global writes visible to the others (one wavefront per workgroup).
+template <bool ST>
+__device__ __forceinline__ void unit_sync() {
+  if constexpr (ST)
+    __syncthreads();
+  else
+    wave_sync();
+}
+
 // Compiler-only barrier: memory accesses are not moved across it, so the
 // compiler cannot overlap consecutive loop iterations whose live values would
 // otherwise push the register count past an occupancy step.

@@ -39,13 +39,14 @@ namespace fd {
 constexpr int kMaxModes = 16;
 constexpr int kMaxD = 8;                 // detected modes with cutoff >= 2
 constexpr int kMaxUq = 6;                // undetected block coordinates (2 per U mode, at most 3 modes)
-constexpr int kMaxBlock = 16384;         // entries per node (prod_U C_u^2); the LDS staging limits it further
+constexpr int kMaxBlock = 65536;         // entries per node (prod_U C_u^2)
 constexpr int kMaxCut = 64;
 constexpr int kMaxPos = kMaxUq + 2 * kMaxD;   // positions of the active index
 constexpr int kMaxFam = 1 + 3 * kMaxD + kMaxD * (kMaxD - 1);
 constexpr int kMaxSmax = kMaxD * (kMaxCut - 1);
 constexpr int kPnMax = (kMaxD + 1) * (kMaxSmax + 3);
 constexpr int kPartialSlots = 4096;      // deterministic VJP partial accumulators
+constexpr int kStreamSlots = 1024;       // workgroups of a block kernel whose rows stream from HBM
 constexpr int kThreads = 256;
 constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
@@ -161,6 +162,9 @@ struct Plan {
   // reverse-sweep checkpoint interval in levels (0: the saved buffer keeps
   // every level of every family)
   int ckpt = 0;
+  // blocks whose rows do not fit the LDS staging stream them from HBM, per
+  // kernel: forward block units, block fill, reverse block units, reverse fill
+  bool st_fwd = false, st_ufill = false, st_vjp = false, st_ufill_vjp = false;
   bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
 };
 
@@ -175,6 +179,13 @@ inline size_t ufill_lds_bytes(const Plan& P, bool vjp) {
   const size_t eb = elem_bytes(P.dt);
   return (vjp ? 2 : 1) * (size_t)P.B * eb + (size_t)(kMaxUq * kMaxUq + kMaxUq) * eb + 2 * (kMaxCut + 4) * (eb / 2) +
          (size_t)(P.B + P.wmax + 2) * sizeof(int);
+}
+// ... as launched: a streamed fill keeps only A, b and the square-root
+// tables in LDS.
+inline size_t ufill_launch_lds_bytes(const Plan& P, bool vjp) {
+  const size_t eb = elem_bytes(P.dt);
+  if (vjp ? P.st_ufill_vjp : P.st_ufill) return (size_t)(kMaxUq * kMaxUq + kMaxUq) * eb + 2 * (kMaxCut + 4) * (eb / 2);
+  return ufill_lds_bytes(P, vjp);
 }
 
 // LDS of the block fill with tangents (forward mode): values and tangents of
@@ -205,18 +216,26 @@ struct VjpLayout {
   size_t g0 = 0;                     // drho in level-major node order
   std::vector<size_t> gfam;          // cotangent rings per family (F0 too)
   size_t partial = 0;                // kPartialSlots x (npos x (npos+1)) complex (double)
-  size_t priv = 0;                   // block plans: kPartialSlots x vjp_private_entries (per workgroup)
+  size_t priv = 0;                   // block plans: kPartialSlots (streamed: kStreamSlots) x vjp_private_entries
+  size_t ublk = 0;                   // streamed reverse fill: the block's cotangents (B entries)
   size_t total = 0;
 };
 // Entries of one workgroup's private slot of the block reverse kernel: the
 // pivot cotangent blocks (MD rows sets), their b-terms and the own F0
-// cotangent rows, each read only by the lane that wrote it.
+// cotangent rows, each read only by the lane that wrote it; streamed rows add
+// the undetected-neighbour terms (NQ x (RC + 2) rows).
 size_t vjp_private_entries(const Plan& P);
 size_t vjp_lds_bytes(const Plan& P);   // dynamic LDS of the block reverse kernel (largest geometry used)
 // Dynamic LDS of the forward block kernel for one chunk geometry: F0 rows
 // [k0-2, k1), MD bridge pivot blocks of rows [k0-1, k1), A and b, the
 // square-root tables.
 size_t fwd_lds_bytes_for(const Plan& P, const ChunkGeo& G, bool jvp = false);   // jvp: values and tangents
+// ... with the rows streamed from HBM (A, b and the tables only)
+size_t fwd_stream_lds_bytes(const Plan& P);
+// Entries of one workgroup's slot for the streamed forward block kernel: the
+// bridge pivot blocks, MD x (RC + 1) rows.
+size_t fwd_stream_entries(const Plan& P);
+size_t prep_core_bytes(const Plan& P);   // A_int, b_int, c (the stream slots follow in prep_bytes)
 size_t vjp_lds_bytes_for(const Plan& P, const ChunkGeo& G);   // ... for one chunk geometry
 constexpr size_t kMaxLds = 160 * 1024;
 VjpLayout vjp_layout(const Plan& P, bool odd, size_t base);

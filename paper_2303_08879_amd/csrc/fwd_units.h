@@ -75,30 +75,47 @@ __device__ __forceinline__ void prep_body(const cx<R>* __restrict__ A, const cx<
 // LDS: ufill_lds_bytes(plan, false) (E = cx<R>); the forward mode carries
 // value and tangent (E = dual<R>) through the same steps.
 // ---------------------------------------------------------------------------
-template <typename R, int NQ, typename E>
+template <typename R, int NQ, typename E, bool ST = false>
 __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __restrict__ Ai,
                                            const cx<R>* __restrict__ bi, cx<R>* G, const int* __restrict__ elist,
                                            const int* __restrict__ woff, int wmax, E* g, int64_t dT = 0) {
   using T = ET<E>;
+  static_assert(!ST || std::is_same<E, cx<R>>::value, "the streamed fill carries values only");
   constexpr int nq = NQ;   // 2 per undetected mode
   const int npos = P.npos, B = P.B;
   const int lane = threadIdx.x & 63;
-  E* sA = g + B;   // A between undetected positions, row stride NQ
+  // the block: in LDS, or (ST) the node-0 block itself in HBM
+  E* blk;
+  E* sA;   // A between undetected positions, row stride NQ
+  if constexpr (ST) {
+    blk = reinterpret_cast<E*>(G);
+    sA = g;
+  } else {
+    blk = g;
+    sA = g + B;
+  }
   E* sb = sA + NQ * NQ;
   R* sq = reinterpret_cast<R*>(sb + NQ);
   R* isq = sq + (kMaxCut + 4);
-  int* el = reinterpret_cast<int*>(isq + (kMaxCut + 4));
-  int* wo = el + B;
-  for (int t = lane; t < B; t += 64) el[t] = elist[t];
-  for (int t = lane; t < wmax + 2; t += 64) wo[t] = woff[t];
+  const int* el = elist;
+  const int* wo = woff;
+  if constexpr (!ST) {
+    int* lel = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+    int* lwo = lel + B;
+    for (int t = lane; t < B; t += 64) lel[t] = elist[t];
+    for (int t = lane; t < wmax + 2; t += 64) lwo[t] = woff[t];
+    el = lel;
+    wo = lwo;
+  }
   for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = T::load(Ai + (i / nq) * npos + i % nq, dT);
   if (lane < nq) sb[lane] = T::load(bi + lane, dT);
   for (int v = lane; v < kMaxCut + 4; v += 64) {
     sq[v] = sqrt(R(v));
     isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
   }
-  if (lane == 0) g[0] = T::load(G, dT);   // c, written by the prep kernel
-  wave_sync();
+  if constexpr (!ST)
+    if (lane == 0) blk[0] = T::load(G, dT);   // c, written by the prep kernel
+  unit_sync<ST>();
   for (int w = 1; w <= wmax; ++w) {
     const int t1 = wo[w + 1];
     for (int t = wo[w] + lane; t < t1; t += 64) {
@@ -123,18 +140,19 @@ __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __rest
         }
       const int pe = e - usf;
       E acc = T::zero();
-      cfma(acc, sb[qf], g[pe]);
+      cfma(acc, sb[qf], blk[pe]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q >= nq) continue;
         const int pq = kap[q] - (q == qf ? 1 : 0);
-        if (pq > 0) cfma(acc, sA[qf * NQ + q], cscale(g[pe - P.ustride[q]], sq[pq]));
+        if (pq > 0) cfma(acc, sA[qf * NQ + q], cscale(blk[pe - P.ustride[q]], sq[pq]));
       }
-      g[e] = cscale(acc, isq[kqf]);
+      blk[e] = cscale(acc, isq[kqf]);
     }
-    wave_sync();
+    unit_sync<ST>();
   }
-  for (int e = lane; e < B; e += 64) T::store(G + e, g[e], dT);
+  if constexpr (!ST)
+    for (int e = lane; e < B; e += 64) T::store(G + e, blk[e], dT);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,9 +279,12 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 // The pivot's undetected neighbours reach one row back, so a chunk computes
 // the pivot rows it needs one row above its own (recomputed, not stored).
 // LDS: F0(m) rows [k0-2, k1) and the bridge pivot blocks F1k(K)(m), rows
-// [k0-1, k1), for every bridge K applied at m.
+// [k0-1, k1), for every bridge K applied at m.  ST (blocks whose rows do not
+// fit the LDS): F0(m) is read from HBM where it lies and lpk is the
+// workgroup's slot in global memory; workgroup-scope fences order its
+// writes before other lanes read them.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R, typename LP, typename E>
+template <int MD, int NQ, typename R, typename LP, typename E, bool ST = false>
 __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const E* sA, const E* sb,
                                                const R* sq, const R* isq, int S, int r, int c, const ChunkGeo& G,
                                                E* lf0, E* lpk, int64_t dT = 0) {
@@ -287,14 +308,20 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
     for (int d = MD - 1; d >= 0; --d)
       if (m[d] > 0) K0 = d;
     if (m[0] > P.CD[0] - 2) return;   // no pivot at this point (uniform)
-    const size_t rB = (size_t)r * B;
-    // F0(m), rows [k0-2, k1)
-    {
+    // F0(m), rows [k0-2, k1): entry e of the node's block
+    const int f0base = (k0 - 2) * R0;
+    const cx<R>* f0g = at32(L.f0cur, (uint32_t)(r * B));
+    auto F0 = [&](int e) -> E {
+      if constexpr (ST)
+        return T::load(at32(f0g, (uint32_t)e), dT);
+      else
+        return lf0[e - f0base];
+    };
+    if constexpr (!ST) {
       const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
-      const int base = (k0 - 2) * R0;
-      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - base] = T::load(at32(L.f0cur, (uint32_t)(r * B + e)), dT);
+      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - f0base] = T::load(at32(f0g, (uint32_t)e), dT);
     }
-    wave_sync();
+    unit_sync<ST>();
     // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
     // the halo row only keeps the bridge pivot blocks
     {
@@ -308,11 +335,10 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
           kap[q] = ucoord(P, rem, q);
           rem -= kap[q] * P.ustride[q];
         }
-        const int le = e - (k0 - 2) * R0;
-        const E piv = lf0[le];
+        const E piv = F0(e);
         E un[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(lf0[le - P.ustride[q]], sq[kap[q]]) : T::zero();
+        for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(F0(e - P.ustride[q]), sq[kap[q]]) : T::zero();
         E x[NPD];
 #pragma unroll
         for (int j = 0; j < MD; ++j) {
@@ -348,7 +374,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
         if constexpr (kFence) compiler_fence();
       }
     }
-    wave_sync();
+    unit_sync<ST>();
     // bridges d(m) + 1_ket(K), own rows
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
@@ -368,7 +394,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
         for (int q = 0; q < NQ; ++q) un[q] = kap[q] > 0 ? cscale(pv[lp - P.ustride[q]], sq[kap[q]]) : T::zero();
         E x[NPD];
-        x[2 * K] = cscale(lf0[e - (k0 - 2) * R0], sq[m[K] + 1]);
+        x[2 * K] = cscale(F0(e), sq[m[K] + 1]);
         x[2 * K + 1] = (m[K] > 0) ? cscale(T::load(at32(L.rd[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e)), dT), sq[m[K]]) : T::zero();
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
@@ -413,7 +439,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
       }
       if constexpr (kFence) compiler_fence();
     }
-    wave_sync();
+    unit_sync<ST>();
   }
 }
 

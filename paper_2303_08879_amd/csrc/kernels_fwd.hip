@@ -18,13 +18,13 @@ __global__ void k_prep(const cx<R>* __restrict__ A, const cx<R>* __restrict__ b,
 
 // Step 1 of Algorithm 2: one wavefront, the undetected block in LDS (with
 // E = dual<R>: values and tangents, the tangents dT bytes after the values).
-template <typename R, int NQ, typename E = cx<R>>
+template <typename R, int NQ, typename E = cx<R>, bool ST = false>
 __global__ __launch_bounds__(64) void k_ufill(DevPlan P, const cx<R>* __restrict__ Ai,
                                               const cx<R>* __restrict__ bi, cx<R>* G,
                                               const int* __restrict__ elist, const int* __restrict__ woff,
                                               int wmax, int64_t dT) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  ufill_body<R, NQ>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<E*>(smem_raw), dT);
+  ufill_body<R, NQ, E, ST>(P, Ai, bi, G, elist, woff, wmax, reinterpret_cast<E*>(smem_raw), dT);
 }
 
 // Algorithm 1 (every mode detected): one thread per lattice point of level S.
@@ -44,17 +44,21 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
 
 // Algorithm 2: one wavefront per (lattice point, chunk of undetected rows).
 // E = dual<R> carries every amplitude's tangent along (forward mode), dT
-// bytes after the value.
-template <int MD, int NQ, typename R, typename E>
+// bytes after the value.  ST: the rows stream from HBM (blocks whose rows do
+// not fit the LDS); the bridge pivot blocks then go to the workgroup's slot
+// of `slots` (slot_len entries each).
+template <int MD, int NQ, typename R, typename E, bool ST>
 __global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
                                                    const cx<R>* __restrict__ bi, int S, int nwork, ChunkGeo G,
-                                                   int64_t dT) {
+                                                   int64_t dT, cx<R>* slots, int64_t slot_len) {
+  static_assert(!ST || std::is_same<E, cx<R>>::value, "streamed rows carry values only");
   constexpr int NPOS = NQ + 2 * MD;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int R0 = G.R0;
-  E* lf0 = reinterpret_cast<E*>(smem_raw);             // (RC + 2) rows
-  E* lpk = lf0 + (size_t)(G.RC + 2) * R0;              // MD x (RC + 1) rows
-  E* sA = lpk + (size_t)MD * (G.RC + 1) * R0;          // A (NPOS x NPOS) then b (NPOS)
+  E* lf0 = reinterpret_cast<E*>(smem_raw);                                  // (RC + 2) rows
+  E* lpk = ST ? reinterpret_cast<E*>(slots + (size_t)blockIdx.x * slot_len)  // MD x (RC + 1) rows
+              : lf0 + (size_t)(G.RC + 2) * R0;
+  E* sA = ST ? lf0 : lpk + (size_t)MD * (G.RC + 1) * R0;                   // A (NPOS x NPOS) then b (NPOS)
   const E* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, co
   // LDS writes before their reads
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
-    fwd_block_unit<MD, NQ, R>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk, dT);
+    fwd_block_unit<MD, NQ, R, LevelPtrs<R>, E, ST>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk, dT);
   }
 }
 
@@ -105,23 +109,29 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // Rows of the first undetected coordinate per chunk: about `target` own
 // entries (default one wavefront), spread evenly over the rows.
 
-template <int MD, int NQ, typename R, typename E = cx<R>>
+template <int MD, int NQ, typename R, typename E = cx<R>, bool ST = false>
 static void launch_fwd_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const LevelPtrs<R>& L,
                                const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G,
-                               int64_t dT = 0) {
+                               int64_t dT = 0, cx<R>* slots = nullptr, int64_t slot_len = 0) {
   if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R, E>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R, E, ST>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R, E>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G, dT);
+  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R, E, ST>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G, dT,
+                     slots, slot_len);
 }
 
 // The undetected-block fill for the plan's number of block coordinates.
 template <typename R>
 static hipError_t launch_ufill(const Plan& Pl, const DevPlan& P, const cx<R>* Ai, const cx<R>* bi, cx<R>* f0,
                                hipStream_t st) {
-  const size_t shm = ufill_lds_bytes(Pl, false);
-  if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected at plan creation
-  auto* kfn = Pl.nq == 2 ? &k_ufill<R, 2> : Pl.nq == 4 ? &k_ufill<R, 4> : &k_ufill<R, 6>;
+  const size_t shm = ufill_launch_lds_bytes(Pl, false);
+  if (shm > kMaxLds) return hipErrorInvalidConfiguration;
+  auto* kfn = Pl.st_ufill ? (Pl.nq == 2   ? &k_ufill<R, 2, cx<R>, true>
+                             : Pl.nq == 4 ? &k_ufill<R, 4, cx<R>, true>
+                                          : &k_ufill<R, 6, cx<R>, true>)
+                          : (Pl.nq == 2   ? &k_ufill<R, 2>
+                             : Pl.nq == 4 ? &k_ufill<R, 4>
+                                          : &k_ufill<R, 6>);
   if (shm > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
@@ -169,17 +179,29 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
     // whole-wavefront chunks (halving them costs 30-40 % there)
     ChunkGeo G = chunk_geo(Pl);
     if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
-    const size_t shm = fwd_lds_bytes_for(Pl, G);
-    if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected at plan creation
-    const int grid = nwork * G.nchunks;
-#define FD_LAUNCH_BLOCK(MDV)                                                                     \
-  case MDV:                                                                                      \
-    if (Pl.nq == 2)                                                                              \
-      launch_fwd_block_k<MDV, 2, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
-    else if (Pl.nq == 4)                                                                         \
-      launch_fwd_block_k<MDV, 4, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
-    else                                                                                         \
-      launch_fwd_block_k<MDV, 6, R>(shm, grid, st, P, L, A, b, S, nwork, G);                     \
+    const bool stm = Pl.st_fwd;
+    const size_t shm = stm ? fwd_stream_lds_bytes(Pl) : fwd_lds_bytes_for(Pl, G);
+    if (shm > kMaxLds) return hipErrorInvalidConfiguration;
+    // streamed rows: at most kStreamSlots workgroups, each with its slot after
+    // the prep block
+    const int grid = stm ? (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kStreamSlots) : nwork * G.nchunks;
+    cx<R>* slots = stm ? reinterpret_cast<cx<R>*>(reinterpret_cast<char*>(const_cast<cx<R>*>(A)) + prep_core_bytes(Pl))
+                       : nullptr;
+    const int64_t slen = (int64_t)fwd_stream_entries(Pl);
+#define FD_LAUNCH_BLOCK_NQ(MDV, NQV)                                                                     \
+  if (stm)                                                                                               \
+    launch_fwd_block_k<MDV, NQV, R, cx<R>, true>(shm, grid, st, P, L, A, b, S, nwork, G, 0, slots, slen); \
+  else                                                                                                   \
+    launch_fwd_block_k<MDV, NQV, R>(shm, grid, st, P, L, A, b, S, nwork, G);
+#define FD_LAUNCH_BLOCK(MDV)        \
+  case MDV:                         \
+    if (Pl.nq == 2) {               \
+      FD_LAUNCH_BLOCK_NQ(MDV, 2)    \
+    } else if (Pl.nq == 4) {        \
+      FD_LAUNCH_BLOCK_NQ(MDV, 4)    \
+    } else {                        \
+      FD_LAUNCH_BLOCK_NQ(MDV, 6)    \
+    }                               \
     break;
     switch (MD) {
       FD_LAUNCH_BLOCK(1)
@@ -194,6 +216,7 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
         return hipErrorInvalidValue;
     }
 #undef FD_LAUNCH_BLOCK
+#undef FD_LAUNCH_BLOCK_NQ
   }
   return hipGetLastError();
 }

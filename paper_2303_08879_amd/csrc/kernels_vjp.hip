@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 // time in its own LDS region and each lane accumulates fixed (i, l) pairs in
 // registers for the whole kernel; no workgroup barrier is involved.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R, int NB>
+template <int MD, int NQ, typename R, int NB, bool ST>
 __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         ChunkGeo G, double2* __restrict__ partial) {
@@ -425,15 +425,20 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int B = P.B, R0 = G.R0, RC = G.RC;
   const int nrow1 = (RC + 1) * R0, nrow2 = (RC + 2) * R0;
-  cx<R>* lfw = reinterpret_cast<cx<R>*>(smem_raw);   // forward pivot rows [k0-1, k1)
-  cx<R>* qv = lfw + nrow1;                           // NQ x rows [k0, k1+2)
-  cx<R>* rec = qv + (size_t)NQ * nrow2;              // waves x RS x (NPD + NR)
   // entries each lane reads back only itself (same entry-to-lane map in every
   // loop of a unit): the workgroup's private slot in global memory, which
   // leaves the LDS to the shared rows and raises the wavefronts per CU
   cx<R>* gpk = V.priv + (size_t)blockIdx.x * V.priv_stride;   // MD x rows [k0, k1+1)
   cx<R>* gbv = gpk + (size_t)MD * nrow1;                       // rows [k0, k1+1)
   cx<R>* g0a = gbv + nrow1;                                    // own rows
+  // the forward pivot rows [k0-1, k1) and the undetected-neighbour terms of
+  // NQ x rows [k0, k1+2): in LDS, or (ST, blocks whose rows do not fit) the
+  // pivot rows read from HBM where they lie and the terms in the private
+  // slot after the own rows (the __syncthreads between phases are
+  // workgroup-scope fences)
+  cx<R>* lfw = reinterpret_cast<cx<R>*>(smem_raw);
+  cx<R>* qv = ST ? g0a + (size_t)RC * R0 : lfw + nrow1;
+  cx<R>* rec = ST ? lfw : qv + (size_t)NQ * nrow2;   // waves x RS x (NPD + NR)
   cx<R>* sA = rec + (size_t)(kBT / 64) * RS * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
@@ -461,15 +466,23 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
     for (int d = MD - 1; d >= 0; --d)
       if (m[d] > 0) K0 = d;
     const size_t rB = (size_t)r * B;
+    // forward pivot row entry e of the current phase's pivot block
+    const cx<R>* fsrc = nullptr;
+    auto LF = [&](int e) -> cx<R> {
+      if constexpr (ST)
+        return ld(at32(fsrc, (uint32_t)e));
+      else
+        return lfw[e - (k0 - 1) * R0];
+    };
     for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) g0a[e - e_own0] = ld(at32(V.d0cur, (uint32_t)(r * B + e)));
 
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
       if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
-      {
-        const cx<R>* f = V.fcur[fam_f1k(K)] + rB;
+      fsrc = V.fcur[fam_f1k(K)] + rB;
+      if constexpr (!ST) {
         const int e0 = max(0, k0 - 1) * R0;
-        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(f + e);
+        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(fsrc + e);
       }
       __syncthreads();
       const int eq1 = min(G.C0, k1 + 2) * R0, eb1 = min(G.C0, k1 + 1) * R0;
@@ -534,15 +547,14 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
 #pragma unroll
             for (int l = 0; l < NR; ++l) setx(l, czero<R>());
             if (rec_ok) {
-              const int lf = e - (k0 - 1) * R0;
               int rem = e;
 #pragma unroll
               for (int q = 0; q < NQ; ++q) {
                 const int kq = ucoord(P, rem, q);
                 rem -= kq * P.ustride[q];
-                if (kq > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kq]));
+                if (kq > 0) setx(q, cscale(LF(e - P.ustride[q]), sq[kq]));
               }
-              setx(NPOS, lfw[lf]);
+              setx(NPOS, LF(e));
               setx(NQ + 2 * K, cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]));
               if (m[K] > 0)
                 setx(NQ + 2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]));
@@ -581,10 +593,10 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
     }
 
     if (m[0] <= P.CD[0] - 2) {
-      {
-        const cx<R>* f = V.fcur[0] + rB;
+      fsrc = V.fcur[0] + rB;
+      if constexpr (!ST) {
         const int e0 = max(0, k0 - 1) * R0;
-        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(f + e);
+        for (int e = e0 + threadIdx.x; e < e_own1; e += blockDim.x) lfw[e - (k0 - 1) * R0] = ld(fsrc + e);
       }
       __syncthreads();
       const int eq1 = min(G.C0, k1 + 1) * R0;
@@ -641,15 +653,14 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
 #pragma unroll
             for (int l = 0; l < NR; ++l) setx(l, czero<R>());
             if (rec_ok) {
-              const int lf = e - (k0 - 1) * R0;
               int rem = e;
 #pragma unroll
               for (int q = 0; q < NQ; ++q) {
                 const int kq = ucoord(P, rem, q);
                 rem -= kq * P.ustride[q];
-                if (kq > 0) setx(q, cscale(lfw[lf - P.ustride[q]], sq[kq]));
+                if (kq > 0) setx(q, cscale(LF(e - P.ustride[q]), sq[kq]));
               }
-              setx(NPOS, lfw[lf]);
+              setx(NPOS, LF(e));
 #pragma unroll
               for (int j = 0; j < MD; ++j) {
                 if (m[j] > 0) {
@@ -707,38 +718,55 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
 // first (incoming cotangents included), so the steps never wait on global
 // memory.  LDS: ufill_lds_bytes(plan, true).
 // ---------------------------------------------------------------------------
-template <typename R, int NQ>
+template <typename R, int NQ, bool ST = false>
 __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __restrict__ Ai,
                                                   const cx<R>* __restrict__ bi, const cx<R>* __restrict__ G,
                                                   const cx<R>* __restrict__ gin, const int* __restrict__ elist,
                                                   const int* __restrict__ woff, int wmax, double2* slot,
-                                                  cx<R>* cbar) {
+                                                  cx<R>* cbar, cx<R>* gbuf) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int nq = NQ;   // 2 per undetected mode
   const int npos = P.npos, B = P.B;
   const int NR = npos + 1;
   const int lane = threadIdx.x;
+  // forward values and cotangents of the block: in LDS, or (ST) read from
+  // HBM where the forward left them and accumulated in `gbuf` (B entries of
+  // the workspace)
   cx<R>* Gl = reinterpret_cast<cx<R>*>(smem_raw);
-  cx<R>* gf = Gl + B;
-  cx<R>* sA = gf + B;   // A between undetected positions, row stride NQ
+  cx<R>* gf = ST ? gbuf : Gl + B;
+  cx<R>* sA = ST ? Gl : gf + B;   // A between undetected positions, row stride NQ
   cx<R>* sb = sA + NQ * NQ;
   R* sq = reinterpret_cast<R*>(sb + NQ);
   R* isq = sq + (kMaxCut + 4);
-  int* el = reinterpret_cast<int*>(isq + (kMaxCut + 4));
-  int* wo = el + B;
-  for (int e = lane; e < B; e += 64) {
-    Gl[e] = ld(G + e);
-    gf[e] = ld(gin + e);
-    el[e] = elist[e];
+  const int* el = elist;
+  const int* wo = woff;
+  auto GL = [&](int i) -> cx<R> {
+    if constexpr (ST)
+      return ld(G + i);
+    else
+      return Gl[i];
+  };
+  if constexpr (ST) {
+    for (int e = lane; e < B; e += 64) st(gf + e, ld(gin + e));
+  } else {
+    int* lel = reinterpret_cast<int*>(isq + (kMaxCut + 4));
+    int* lwo = lel + B;
+    for (int e = lane; e < B; e += 64) {
+      Gl[e] = ld(G + e);
+      gf[e] = ld(gin + e);
+      lel[e] = elist[e];
+    }
+    for (int t = lane; t < wmax + 2; t += 64) lwo[t] = woff[t];
+    el = lel;
+    wo = lwo;
   }
-  for (int t = lane; t < wmax + 2; t += 64) wo[t] = woff[t];
   for (int i = lane; i < nq * nq; i += 64) sA[(i / nq) * NQ + i % nq] = ld(Ai + (i / nq) * npos + i % nq);
   if (lane < nq) sb[lane] = ld(bi + lane);
   for (int v = lane; v < kMaxCut + 4; v += 64) {
     sq[v] = sqrt(R(v));
     isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
   }
-  wave_sync();
+  unit_sync<ST>();
   cx<double> ab[NQ][NQ + 1];
 #pragma unroll
   for (int a = 0; a < NQ; ++a)
@@ -792,7 +820,7 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
         const int qf = first0;
         const int pe = e - usf;
         const cx<R> h = cscale(acc, isq[xf]);
-        const cx<R> gp = Gl[pe];
+        const cx<R> gp = GL(pe);
 #pragma unroll
         for (int a = 0; a < NQ; ++a) {
           if (a != qf) continue;
@@ -803,14 +831,14 @@ __global__ __launch_bounds__(64) void k_ufill_vjp(DevPlan P, const cx<R>* __rest
             if (q2 >= nq) continue;
             const int pq2 = x[q2] - (q2 == qf ? 1 : 0);
             if (pq2 <= 0) continue;
-            const cx<R> g2 = cscale(Gl[pe - P.ustride[q2]], sq[pq2]);
+            const cx<R> g2 = cscale(GL(pe - P.ustride[q2]), sq[pq2]);
             ab[a][q2].x += (double)g2.x * h.x + (double)g2.y * h.y;
             ab[a][q2].y += (double)g2.x * h.y - (double)g2.y * h.x;
           }
         }
       }
     }
-    wave_sync();
+    unit_sync<ST>();
   }
   // butterfly sums over the wavefront (fixed order), lane 0 adds to the slot
 #pragma unroll
@@ -916,15 +944,15 @@ static cx<R>* gptr(const Plan& Pl, char* base, size_t off, int g, int S) {
   return reinterpret_cast<cx<R>*>(base + off + (size_t)(S & 1) * Pl.maxN[g] * Pl.B * sizeof(cx<R>));
 }
 
-template <int MD, int NQ, typename R>
+template <int MD, int NQ, typename R, bool ST>
 static void launch_vjp_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const VjpPtrs<R>& Vp,
                                const cx<R>* Ai, const cx<R>* bi, int S, int nwork, const ChunkGeo& G,
                                double2* partial) {
   if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MD, NQ, R, kBlockBatch>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MD, NQ, R, kBlockBatch, ST>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_vjp_block<MD, NQ, R, kBlockBatch>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S, nwork,
-                     G, partial);
+  hipLaunchKernelGGL((k_vjp_block<MD, NQ, R, kBlockBatch, ST>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,
+                     nwork, G, partial);
 }
 
 template <typename R>
@@ -1097,15 +1125,23 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
       const size_t shm = vjp_lds_bytes_for(Pl, G);
       if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
-      const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks, kPartialSlots - 1);
-#define FD_VJP_BLOCK(MDV)                                                                         \
-  case MDV:                                                                                       \
-    if (Pl.nq == 2)                                                                               \
-      launch_vjp_block_k<MDV, 2, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
-    else if (Pl.nq == 4)                                                                          \
-      launch_vjp_block_k<MDV, 4, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
-    else                                                                                          \
-      launch_vjp_block_k<MDV, 6, R>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);          \
+      // streamed rows: private slots for at most kStreamSlots workgroups
+      const int grid = (int)std::min<int64_t>((int64_t)nwork * G.nchunks,
+                                              Pl.st_vjp ? kStreamSlots : kPartialSlots - 1);
+#define FD_VJP_BLOCK_NQ(MDV, NQV)                                                                  \
+  if (Pl.st_vjp)                                                                                   \
+    launch_vjp_block_k<MDV, NQV, R, true>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);     \
+  else                                                                                             \
+    launch_vjp_block_k<MDV, NQV, R, false>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
+#define FD_VJP_BLOCK(MDV)        \
+  case MDV:                      \
+    if (Pl.nq == 2) {            \
+      FD_VJP_BLOCK_NQ(MDV, 2)    \
+    } else if (Pl.nq == 4) {     \
+      FD_VJP_BLOCK_NQ(MDV, 4)    \
+    } else {                     \
+      FD_VJP_BLOCK_NQ(MDV, 6)    \
+    }                            \
     break;
       switch (MD) {
         FD_VJP_BLOCK(1)
@@ -1120,6 +1156,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
           return hipErrorInvalidValue;
       }
 #undef FD_VJP_BLOCK
+#undef FD_VJP_BLOCK_NQ
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -1129,14 +1166,22 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
   if (Pl.B > 1) {
     const cx<R>* G0blk = reinterpret_cast<const cx<R>*>(sv + f0off);
     KTimer kt(Pl, KK_UFILL_VJP, st);
-    const size_t shm = ufill_lds_bytes(Pl, true);
-    if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
-    auto* kfn = Pl.nq == 2 ? &k_ufill_vjp<R, 2> : Pl.nq == 4 ? &k_ufill_vjp<R, 4> : &k_ufill_vjp<R, 6>;
+    const size_t shm = ufill_launch_lds_bytes(Pl, true);
+    if (shm > kMaxLds) return hipErrorInvalidConfiguration;
+    // streamed: the block's cotangents accumulate in the workspace
+    cx<R>* gbuf = Pl.st_ufill_vjp ? reinterpret_cast<cx<R>*>(ws + V.ublk) : nullptr;
+    if (Pl.st_ufill_vjp && V.ublk == 0) return hipErrorInvalidValue;
+    auto* kfn = Pl.st_ufill_vjp ? (Pl.nq == 2   ? &k_ufill_vjp<R, 2, true>
+                                   : Pl.nq == 4 ? &k_ufill_vjp<R, 4, true>
+                                                : &k_ufill_vjp<R, 6, true>)
+                                : (Pl.nq == 2   ? &k_ufill_vjp<R, 2, false>
+                                   : Pl.nq == 4 ? &k_ufill_vjp<R, 4, false>
+                                                : &k_ufill_vjp<R, 6, false>);
     if (shm > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)shm);
     hipLaunchKernelGGL(kfn, dim3(1), dim3(64), shm, st, P, Ai, bi, G0blk, gseed, Pl.d_elist, Pl.d_woff, Pl.wmax,
-                       partial + (size_t)(kPartialSlots - 1) * PP, cb);
+                       partial + (size_t)(kPartialSlots - 1) * PP, cb, gbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cbar_src = cb;
   }

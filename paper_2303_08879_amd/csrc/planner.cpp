@@ -111,7 +111,7 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     B *= P->udims[q];
   }
   if (B > kMaxBlock) {
-    *err = "undetected block prod C_u^2 exceeds 16384";
+    *err = "undetected block prod C_u^2 exceeds 65536";
     return FD_ERR_UNSUPPORTED;
   }
   P->B = (int)B;
@@ -300,13 +300,14 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     std::vector<int> pos(P->woff.begin(), P->woff.end() - 1);
     for (int e = 0; e < P->B; ++e) P->elist[pos[wt[e]]++] = e;
   }
-  // the forward block kernel and the block fill hold their rows in LDS
+  // the block kernels and the block fills hold their rows in LDS where they
+  // fit, else stream them from HBM
   if (P->B > 1) {
     const size_t rows = std::max(fwd_lds_bytes_for(*P, chunk_geo(*P)), fwd_lds_bytes_for(*P, chunk_geo(*P, kBT / 2)));
-    if ((P->MD > 0 && rows > kMaxLds) || ufill_lds_bytes(*P, false) > kMaxLds) {
-      *err = "undetected block too large for the forward sweep's LDS staging";
-      return FD_ERR_UNSUPPORTED;
-    }
+    P->st_fwd = P->MD > 0 && rows > kMaxLds;
+    P->st_ufill = ufill_lds_bytes(*P, false) > kMaxLds;
+    P->st_vjp = P->MD > 0 && vjp_lds_bytes(*P) > kMaxLds;
+    P->st_ufill_vjp = ufill_lds_bytes(*P, true) > kMaxLds;
   }
   P->targets = -1;
   P->terms = -1;
@@ -338,9 +339,23 @@ DevPlan make_devplan(const Plan& P, bool odd) {
   return d;
 }
 
-size_t prep_bytes(const Plan& P) {
+size_t prep_core_bytes(const Plan& P) {
   size_t n = (size_t)P.npos * P.npos + P.npos + 1;
   return align256(n * elem_bytes(P.dt));
+}
+
+// The prep block of every workspace; a plan whose forward block rows stream
+// from HBM keeps its workgroups' bridge pivot slots right after it.
+size_t prep_bytes(const Plan& P) {
+  size_t n = prep_core_bytes(P);
+  if (P.st_fwd) n += align256((size_t)kStreamSlots * fwd_stream_entries(P) * elem_bytes(P.dt));
+  return n;
+}
+
+size_t fwd_stream_entries(const Plan& P) {
+  if (P.B == 1 || P.MD == 0) return 0;
+  const ChunkGeo G = chunk_geo(P);   // the taller of the two chunk geometries
+  return (size_t)P.MD * (G.RC + 1) * G.R0;
 }
 
 FwdLayout fwd_layout(const Plan& P, bool odd, bool store_all, size_t base) {
@@ -385,9 +400,13 @@ ChunkGeo chunk_geo(const Plan& Pl, int target) {
 size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
   const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
-  const size_t ents = (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0 +
-                      (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
+  const size_t rows = Pl.st_vjp ? 0 : (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0;
+  const size_t ents = rows + (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
+}
+
+size_t fwd_stream_lds_bytes(const Plan& Pl) {
+  return (size_t)Pl.npos * (Pl.npos + 1) * elem_bytes(Pl.dt) + 2 * (kMaxCut + 4) * (elem_bytes(Pl.dt) / 2);
 }
 
 size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G, bool jvp) {
@@ -500,7 +519,11 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
   off = align256(off + (size_t)kPartialSlots * P.npos * (P.npos + 1) * 16);
   if (P.B > 1 && P.MD > 0) {
     L.priv = off;
-    off = align256(off + (size_t)kPartialSlots * vjp_private_entries(P) * eb);
+    off = align256(off + (size_t)(P.st_vjp ? kStreamSlots : kPartialSlots) * vjp_private_entries(P) * eb);
+  }
+  if (P.st_ufill_vjp) {
+    L.ublk = off;
+    off = align256(off + (size_t)P.B * eb);
   }
   L.total = off;
   return L;
@@ -509,7 +532,8 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
 size_t vjp_private_entries(const Plan& P) {
   if (P.B == 1 || P.MD == 0) return 0;
   const ChunkGeo G = chunk_geo(P);   // the larger of the two chunk heights the launcher uses
-  return (size_t)(P.MD + 1) * (G.RC + 1) * G.R0 + (size_t)G.RC * G.R0;
+  return (size_t)(P.MD + 1) * (G.RC + 1) * G.R0 + (size_t)G.RC * G.R0 +
+         (P.st_vjp ? (size_t)P.nq * (G.RC + 2) * G.R0 : 0);
 }
 
 

@@ -44,23 +44,20 @@ def test_plan_create_rejects_bad_arguments():
     four_u = (ctypes.c_int * 4)(3, 3, 3, 3)
     assert L.fd_plan_create(4, four_u, 0, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
     assert "undetected" in F.fd_last_error()
-    # two undetected modes at cutoff 12: a block of 20736 entries
-    big2 = (ctypes.c_int * 3)(12, 12, 3)
+    # two undetected modes at cutoff 17: a block of 83521 entries
+    big2 = (ctypes.c_int * 3)(17, 17, 3)
     assert L.fd_plan_create(3, big2, 0b100, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
-    assert "16384" in F.fd_last_error()
-    # three at cutoff 5: 15625 entries, whose fill does not fit the LDS
-    big3 = (ctypes.c_int * 4)(5, 5, 5, 2)
-    assert L.fd_plan_create(4, big3, 0b1000, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
-    assert "LDS" in F.fd_last_error()
+    assert "65536" in F.fd_last_error()
 
 
 @pytest.mark.parametrize("cut,mask,dtype", [
     ((3, 3, 3), 0, 0), ((4, 4, 4, 3), 0b1000, 0), ((3, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3), 0b11111111000, 0),
-    ((9, 9, 3), 0b100, 0), ((9, 9, 3, 3, 3, 3, 3), 0b1111100, 0), ((9, 9, 3, 3, 3, 3, 3, 3), 0b11111100, 1)])
+    ((9, 9, 3), 0b100, 0), ((9, 9, 3, 3, 3, 3, 3), 0b1111100, 0), ((9, 9, 3, 3, 3, 3, 3, 3), 0b11111100, 1),
+    ((9, 9, 3, 3, 3, 3, 3, 3), 0b11111100, 0), ((12, 12, 3), 0b100, 0), ((5, 5, 5, 2), 0b1000, 0),
+    ((16, 16, 2), 0b100, 1)])
 def test_plan_create_three_undetected_modes_and_large_blocks(cut, mask, dtype):
-    # blocks up to what the LDS staging holds: three undetected modes, and two
-    # at cutoff 9 (6561 entries) with up to five detected modes in complex128
-    # (six in complex64, whose rows take half the bytes)
+    # three undetected modes, and blocks of up to 65536 entries: rows that do
+    # not fit the LDS staging stream from HBM
     L = F.lib()
     h = ctypes.c_void_p()
     arr = (ctypes.c_int * len(cut))(*cut)
@@ -68,14 +65,20 @@ def test_plan_create_three_undetected_modes_and_large_blocks(cut, mask, dtype):
     assert L.fd_plan_destroy(h) == F.FD_OK
 
 
-def test_plan_create_rejects_rows_beyond_lds():
-    # two undetected modes at cutoff 9 with six detected modes: 15 rows of
-    # 729 complex128 entries exceed 160 KiB
-    L = F.lib()
-    h = ctypes.c_void_p()
-    cut = (ctypes.c_int * 8)(9, 9, 3, 3, 3, 3, 3, 3)
-    assert L.fd_plan_create(8, cut, 0b11111100, 0, 0, ctypes.byref(h)) == F.FD_ERR_UNSUPPORTED
-    assert "LDS" in F.fd_last_error()
+def test_streamed_rows_workspace_sizes():
+    # a plan whose forward rows stream keeps one bridge-pivot slot per
+    # streaming workgroup (1024) after the prep block, in every workspace that
+    # holds a prep block: two undetected modes at cutoff 12 with two detected
+    # modes (MD = 2, R0 = 1728, RC = 1: 1024 x 2 x 2 x 1728 entries)
+    import torch
+    big = F.Plan([12, 12, 2, 2], 0b1100, torch.complex128, "general")
+    eb, B, nodes = 16, 12 ** 4, 4
+    al = lambda x: (x + 255) // 256 * 256
+    slots = al(1024 * 2 * 2 * 1728 * eb)
+    fwd, _ = big.workspace(False)
+    assert fwd >= slots + al(nodes * B * eb)
+    vjp, saved = big.workspace(True)
+    assert vjp >= slots and saved >= nodes * B * eb
 
 
 def test_calls_reject_null_plan_and_pointers():

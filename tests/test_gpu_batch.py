@@ -105,12 +105,12 @@ def test_batch_wide_and_degenerate_members():
 
 def test_batch_with_three_undetected_modes_and_large_blocks():
     # members the persistent sweep does not stage (six block coordinates; a
-    # 6561-entry block) run their own level launches inside the batched call,
-    # beside sweep members
+    # 6561-entry block; a 20736-entry block whose rows stream from HBM) run
+    # their own level launches inside the batched call, beside sweep members
     rng = np.random.default_rng(322)
     mk = lambda M, cut, mask: W._circuit(rng, M, 0.3, 0.8, lambda g, MM: g.uniform(0.8, 0.95, size=MM), cut, mask)
     circs = [mk(4, [3, 2, 3, 3], 0b1000), mk(3, [9, 9, 3], 0b100), mk(3, [4, 3, 3], 0b110), mk(4, [3, 3, 3, 3], 0xF),
-             mk(5, [2, 3, 2, 3, 3], 0b11000)]
+             mk(5, [2, 3, 2, 3, 3], 0b11000), mk(4, [12, 12, 2, 2], 0b1100)]
     outs = run_batch(circs)
     for c, out in zip(circs, outs):
         np.testing.assert_array_equal(out, run_single(c))

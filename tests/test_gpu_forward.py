@@ -91,6 +91,28 @@ THREE_U = [
 ]
 
 
+# blocks whose rows do not fit the LDS staging stream from HBM: two
+# undetected modes at cutoff 12 (20736 entries; the fill streams, and with two
+# detected modes the block units too) and 16 (65536 entries), three at cutoff 5
+STREAMED = [(3, [12, 12, 3], 0b100, False), (4, [12, 12, 2, 2], 0b1100, False), (4, [12, 12, 2, 2], 0b1100, True),
+            (4, [5, 5, 5, 2], 0b1000, False), (3, [16, 16, 2], 0b100, False)]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", STREAMED)
+def test_streamed_block_rows(M, cut, mask, bz):
+    rng = np.random.default_rng(3500 + M * 41 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.15)
+    ref = O.fock_diag(A, b, c, cut, mask)
+    for b_mode in (["auto", "zero"] if bz else ["general"]):
+        out = gpu(A, b, c, cut, mask, b_mode=b_mode)
+        assert out.shape == ref.shape
+        assert_close(out, ref, label=f"{cut} {bin(mask)} {b_mode}")
+    out = gpu(A.astype(np.complex64), b.astype(np.complex64), np.complex64(c), cut, mask, dtype=torch.complex64)
+    err = O.rel_err(out, ref)
+    print(f"c64 rel_err {cut} {bin(mask)} = {err:.3e}", flush=True)
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("M,cut,mask,bz", THREE_U)
 def test_three_undetected_modes_and_large_blocks(M, cut, mask, bz):
     rng = np.random.default_rng(3000 + M * 41 + sum(cut) + mask)

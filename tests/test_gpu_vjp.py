@@ -111,18 +111,33 @@ def test_vjp_three_undetected_modes(M, cut, mask, bz):
         check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref, label=f"{cut} {bin(mask)} b=0")
 
 
-def test_vjp_block_beyond_lds_is_rejected_and_complex64_runs():
-    # two undetected modes at cutoff 9: the reverse fill holds 2 x 6561
-    # entries, too many complex128 values for the LDS (FD_ERR_UNSUPPORTED
-    # before any device work); complex64 values fit
+STREAMED = [(3, [9, 9, 3], 0b100, False), (3, [12, 12, 3], 0b100, False), (4, [12, 12, 2, 2], 0b1100, False),
+            (3, [16, 16, 2], 0b100, False),
+            (4, [12, 12, 2, 2], 0b1100, True), (4, [5, 5, 5, 2], 0b1000, False)]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", STREAMED)
+def test_vjp_streamed_block_rows(M, cut, mask, bz):
+    # blocks whose rows or fill do not fit the LDS staging: the reverse block
+    # units read the forward pivot rows from HBM and keep the neighbour terms
+    # in their private slots; the reverse fill accumulates in the workspace
+    rng = np.random.default_rng(4500 + M * 43 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.15)
+    shape = O.fock_diag(A, b, c, cut, mask).shape
+    g = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    check(gpu_vjp(A, b, c, cut, mask, g), ref, label=f"{cut} {bin(mask)}")
+    check(gpu_vjp(A, b, c, cut, mask, g, use_saved=False), ref, label=f"{cut} {bin(mask)} recompute")
+    if bz:
+        check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref, label=f"{cut} {bin(mask)} b=0")
+
+
+def test_vjp_block_complex64_two_undetected_at_cutoff_9():
     rng = np.random.default_rng(45)
     cut, mask = [9, 9, 3], 0b100
     A, b, c = rand_triple(rng, 3, False, scale=0.2)
     shape = O.fock_diag(A, b, c, cut, mask).shape
     g = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
-    with pytest.raises(F.FockDiagError) as ei:
-        gpu_vjp(A, b, c, cut, mask, g)
-    assert ei.value.status == F.FD_ERR_UNSUPPORTED
     ref = O.fock_diag_vjp(A, b, c, cut, mask, g)
     got = gpu_vjp(A.astype(np.complex64), b.astype(np.complex64), np.complex64(c), cut, mask, g,
                   dtype=torch.complex64)
