@@ -52,7 +52,7 @@ constexpr int kBT = 64;                  // threads of the block (Algorithm 2) k
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
 constexpr int kPointBatch = 32;          // Abar records per LDS staging batch, point reverse kernel
 constexpr int kBlockBatch = 32;          // the same, block reverse kernel
-constexpr int kVjpSlots = 1024;          // reduction slots of the state-vector cotangents
+constexpr int kVjpSlots = 16384;         // reduction slots of the state-vector cotangents
 
 enum FamType { F_F0 = 0, F_F1K, F_F1B, F_F2, F_1010, F_1001 };
 

@@ -138,83 +138,79 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
 // order, the workgroup folds its threads in a fixed tree into its slot, and
 // the final kernel adds the slots in order (bitwise reproducible).
 // ---------------------------------------------------------------------------
-constexpr int kVjpGroup = 16;
+constexpr int kVjpTerms = kMaxD + kMaxD * (kMaxD + 1) / 2 + 1;   // bbar, Abar (i <= l), c
 
+// The terms; mode i of term t has C-order stride si[t] and cutoff ci[t] (the
+// same for l), with their reciprocals for the exact double-reciprocal digit
+// split.
 struct StateVjpTerms {
-  int n;                    // terms in this launch (<= kVjpGroup)
-  int col[kVjpGroup];       // output column of each term
-  int kind[kVjpGroup];      // 0: bbar_i, 1: Abar_il (i < l), 2: Abar_ii, 3: sum g conj(psi)
-  int i[kVjpGroup], l[kVjpGroup];
+  int n;                    // terms (ncol)
+  int col[kVjpTerms];       // output column of each term
+  int kind[kVjpTerms];      // 0: bbar_i, 1: Abar_il (i < l), 2: Abar_ii, 3: sum g conj(psi)
+  int si[kVjpTerms], ci[kVjpTerms], sl[kVjpTerms], cl[kVjpTerms];
+  double inv_si[kVjpTerms], inv_ci[kVjpTerms], inv_sl[kVjpTerms], inv_cl[kVjpTerms];
 };
 
+// Digit (x / stride) mod C of a C-order index x < 2^31: (x + 1/2) / stride
+// lies at least 1 / (2 stride) from an integer and the rounded product is off
+// by less than (x / stride) 2^-51, so truncation is exact (and so for the mod).
+__device__ __forceinline__ int cdigit(int x, int stride, int c, double inv_stride, double inv_c) {
+  const int q = (int)((x + 0.5) * inv_stride);
+  return q - c * (int)((q + 0.5) * inv_c);
+}
+
+// One workgroup per (chunk of `len` consecutive indices, term): the term is
+// uniform, so each lane keeps one accumulator, the g and shifted psi reads
+// of a wavefront are consecutive addresses, and the term's workgroups of one
+// chunk run together (term fastest in the grid) and share the chunk's g in
+// L2.  Each lane sums its indices in order, the workgroup folds its lanes in
+// a fixed tree into slot (chunk, column); the final kernel adds the slots of
+// a column in order (bitwise reproducible).
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_state_vjp_terms(DevPlan P, const cx<R>* __restrict__ psi,
-                                                              const cx<R>* __restrict__ g, int total, StateVjpTerms T,
-                                                              int ncol, double2* __restrict__ slots) {
+__global__ __launch_bounds__(kThreads) void k_state_vjp_terms(const cx<R>* __restrict__ psi,
+                                                              const cx<R>* __restrict__ g, int total, int len,
+                                                              StateVjpTerms T, double2* __restrict__ slots) {
   __shared__ double2 red[kThreads];
-  const int MD = P.MD;
-  int stride[kMaxD];
-  {
-    int s = 1;
-    for (int d = MD - 1; d >= 0; --d) {
-      stride[d] = s;
-      s *= P.CD[d];
-    }
-  }
-  double ax[kVjpGroup], ay[kVjpGroup];
-#pragma unroll
-  for (int t = 0; t < kVjpGroup; ++t) ax[t] = ay[t] = 0.0;
-  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
-    // digits of x (last mode fastest), exact double-reciprocal split
-    int k[kMaxD];
-    int rem = x;
-    for (int d = MD - 1; d >= 0; --d) {
-      const int q = (int)((rem + 0.5) * P.cinv[d]);
-      k[d] = rem - q * P.CD[d];
-      rem = q;
-    }
-    const cx<R> gv = ld(g + x);
-#pragma unroll
-    for (int t = 0; t < kVjpGroup; ++t) {
-      if (t >= T.n) break;
-      const int kind = T.kind[t], i = T.i[t], l = T.l[t];
-      double w = 0.0;
-      int y = x;
+  __shared__ double sq[kMaxCut + 1];   // sqrt(0..64)
+  for (int v = threadIdx.x; v <= kMaxCut; v += blockDim.x) sq[v] = sqrt((double)v);
+  __syncthreads();
+  const int term = (int)(blockIdx.x % (unsigned)T.n), chunk = (int)(blockIdx.x / (unsigned)T.n);
+  const int kind = T.kind[term];
+  const int si = T.si[term], ci = T.ci[term], sl = T.sl[term], cl = T.cl[term];
+  const double isi = T.inv_si[term], ici = T.inv_ci[term], isl = T.inv_sl[term], icl = T.inv_cl[term];
+  const int shift = kind == 0 ? si : kind == 1 ? si + sl : kind == 2 ? 2 * si : 0;
+  const int x0 = chunk * len, x1 = min(total, x0 + len);
+  double ax = 0.0, ay = 0.0;
+  for (int x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+    double w = 1.0;
+    if (kind != 3) {
+      const int ki = cdigit(x, si, ci, isi, ici);
       if (kind == 0) {
-        if (k[i] < 1) continue;
-        w = sqrt((double)k[i]);
-        y = x - stride[i];
+        w = sq[ki];
       } else if (kind == 1) {
-        if (k[i] < 1 || k[l] < 1) continue;
-        w = 0.5 * sqrt((double)k[i] * (double)k[l]);
-        y = x - stride[i] - stride[l];
-      } else if (kind == 2) {
-        if (k[i] < 2) continue;
-        w = 0.5 * sqrt((double)k[i] * (double)(k[i] - 1));
-        y = x - 2 * stride[i];
+        w = 0.5 * sq[ki] * sq[cdigit(x, sl, cl, isl, icl)];
       } else {
-        w = 1.0;
+        w = ki >= 2 ? 0.5 * sq[ki] * sq[ki - 1] : 0.0;
       }
-      const cx<R> pv = ld(psi + y);
+    }
+    if (w != 0.0) {   // else the shifted amplitude is outside the box
+      const cx<R> gv = ld(g + x), pv = ld(psi + (x - shift));
       // g * conj(w psi_y)
       const double px = w * (double)pv.x, py = w * (double)pv.y;
-      ax[t] += (double)gv.x * px + (double)gv.y * py;
-      ay[t] += (double)gv.y * px - (double)gv.x * py;
+      ax += (double)gv.x * px + (double)gv.y * py;
+      ay += (double)gv.y * px - (double)gv.x * py;
     }
   }
-  for (int t = 0; t < T.n; ++t) {
-    red[threadIdx.x] = make_double2(ax[t], ay[t]);
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        red[threadIdx.x].x += red[threadIdx.x + w].x;
-        red[threadIdx.x].y += red[threadIdx.x + w].y;
-      }
-      __syncthreads();
+  red[threadIdx.x] = make_double2(ax, ay);
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
     }
-    if (threadIdx.x == 0) slots[(size_t)blockIdx.x * ncol + T.col[t]] = red[0];
     __syncthreads();
   }
+  if (threadIdx.x == 0) slots[(size_t)chunk * T.n + T.col[term]] = red[0];
 }
 
 // One workgroup per caller entry of dA (M x M), db (M), dc: the slots of its
@@ -290,7 +286,9 @@ __global__ __launch_bounds__(kThreads) void k_state_jvp(DevPlan P, StateModes sm
                                                         int total, cx<R>* __restrict__ dpsi) {
   __shared__ double2 sS[kMaxD * kMaxD];
   __shared__ double2 sB[kMaxD];
+  __shared__ double sq[kMaxCut + 1];   // sqrt(0..64)
   const int MD = P.MD;
+  for (int v = threadIdx.x; v <= kMaxCut; v += blockDim.x) sq[v] = sqrt((double)v);
   for (int e = threadIdx.x; e < MD * MD; e += blockDim.x) {
     const int i = e / MD, l = e % MD;
     const cx<R> a = ld(tA + (size_t)sm.mode[i] * M + sm.mode[l]);
@@ -327,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_state_jvp(DevPlan P, StateModes sm
     for (int i = 0; i < MD; ++i) {
       if (k[i] < 1) continue;
       const cx<R> p1 = ld(psi + x - stride[i]);
-      const double w = sqrt((double)k[i]);
+      const double w = sq[k[i]];
       const double2 t = sB[i];
       ax += w * (t.x * p1.x - t.y * p1.y);
       ay += w * (t.x * p1.y + t.y * p1.x);
@@ -335,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_state_jvp(DevPlan P, StateModes sm
         const int kl = k[l] - (l == i ? 1 : 0);
         if (kl < 1) continue;
         const cx<R> p2 = ld(psi + x - stride[i] - stride[l]);
-        const double w2 = 0.5 * sqrt((double)k[i] * (double)kl);
+        const double w2 = 0.5 * sq[k[i]] * sq[kl];
         const double2 S = sS[i * MD + l];
         ax += w2 * (S.x * p2.x - S.y * p2.y);
         ay += w2 * (S.x * p2.y + S.y * p2.x);
@@ -373,43 +371,48 @@ static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi
                                   void* dc, void* ws, hipStream_t st) {
   const int MD = Pl.MD, ncol = MD + MD * (MD + 1) / 2 + 1;
   const int total = (int)Pl.nodes_total;
-  const DevPlan P = make_devplan(Pl, true);
   double2* slots = static_cast<double2*>(ws);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + kThreads - 1) / kThreads, kVjpSlots));
+  // chunks of whole wavefront multiples, at most kVjpSlots of them
+  int len = 16 * kThreads;
+  while ((int64_t)(total + len - 1) / len > kVjpSlots) len *= 2;
+  const int nchunks = std::max(1, (total + len - 1) / len);
   // the terms: bbar_i (col i), Abar_il for i <= l (col MD + upper-triangle index), sum g conj(psi) (last col)
-  std::vector<StateVjpTerms> launches;
-  StateVjpTerms cur;
-  std::memset(&cur, 0, sizeof(cur));
+  StateVjpTerms T;
+  std::memset(&T, 0, sizeof(T));
+  std::vector<int> cstride(MD > 0 ? MD : 1, 1);
+  for (int d = MD - 2; d >= 0; --d) cstride[d] = cstride[d + 1] * Pl.CD[d + 1];
   auto add = [&](int col, int kind, int i, int l) {
-    cur.col[cur.n] = col;
-    cur.kind[cur.n] = kind;
-    cur.i[cur.n] = i;
-    cur.l[cur.n] = l;
-    if (++cur.n == kVjpGroup) {
-      launches.push_back(cur);
-      std::memset(&cur, 0, sizeof(cur));
+    const int n = T.n++;
+    T.col[n] = col;
+    T.kind[n] = kind;
+    if (kind != 3) {
+      T.si[n] = cstride[i];
+      T.ci[n] = Pl.CD[i];
+      T.sl[n] = cstride[l];
+      T.cl[n] = Pl.CD[l];
+      T.inv_si[n] = 1.0 / cstride[i];
+      T.inv_ci[n] = 1.0 / Pl.CD[i];
+      T.inv_sl[n] = 1.0 / cstride[l];
+      T.inv_cl[n] = 1.0 / Pl.CD[l];
     }
   };
   for (int i = 0; i < MD; ++i) add(i, 0, i, i);
   for (int a = 0; a < MD; ++a)
     for (int bb = a; bb < MD; ++bb) add(MD + a * MD - a * (a - 1) / 2 + (bb - a), a == bb ? 2 : 1, a, bb);
   add(ncol - 1, 3, 0, 0);
-  if (cur.n) launches.push_back(cur);
   {
     KTimer kt(Pl, KK_VJP_LEVEL, st);
-    for (const StateVjpTerms& T : launches) {
-      hipLaunchKernelGGL((k_state_vjp_terms<R>), dim3(grid), dim3(kThreads), 0, st, P,
-                         static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(g), total, T, ncol, slots);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL((k_state_vjp_terms<R>), dim3((unsigned)(nchunks * T.n)), dim3(kThreads), 0, st,
+                       static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(g), total, len, T, slots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   StateVjpMap m;
   std::memset(&m, 0, sizeof(m));
   m.M = Pl.M;
   m.MD = MD;
   m.ncol = ncol;
-  m.nslots = grid;
+  m.nslots = nchunks;
   for (int d = 0; d < MD; ++d) m.mode[d] = Pl.dmodes[d];
   KTimer kt(Pl, KK_VJP_FINAL, st);
   hipLaunchKernelGGL((k_state_vjp_final<R>), dim3(Pl.M * Pl.M + Pl.M + 1), dim3(kThreads), 0, st, m, slots,
