@@ -250,6 +250,23 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
     for (int K = 0; K < MD; ++K) {
       const bool valid = live && K <= K0 && m[K] <= P.CD[K] - 2;
       if (!__syncthreads_or(valid)) continue;
+      // the record's read values, loaded by every lane with the cotangents
+      // (one memory round trip for both, and for both record batches)
+      cx<R> xr[NCOL];
+#pragma unroll
+      for (int l = 0; l < NCOL; ++l) xr[l] = czero<R>();
+      if (valid) {
+        xr[2 * K] = cscale(G0, sq[m[K] + 1]);
+        if (m[K] > 0) xr[2 * K + 1] = cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]);
+#pragma unroll
+        for (int j = K + 1; j < MD; ++j) {
+          if (m[j] > 0) {
+            xr[2 * j] = cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
+            xr[2 * j + 1] = cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
+          }
+        }
+        if (ODD) xr[NP] = ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r));
+      }
       cx<R> h[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) h[i] = czero<R>();
@@ -294,21 +311,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         if (__ballot(valid && grp) == 0ull) continue;   // uniform over the wave
         if (grp) {
           const int col = lane - q * NB;
-          auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * RS + col] = v; };
 #pragma unroll
-          for (int l = 0; l < NCOL; ++l) stx(l, czero<R>());
-          if (valid) {
-            stx(2 * K, cscale(G0, sq[m[K] + 1]));
-            if (m[K] > 0) stx(2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]));
-#pragma unroll
-            for (int j = K + 1; j < MD; ++j) {
-              if (m[j] > 0) {
-                stx(2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
-                stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]));
-              }
-            }
-            if (ODD) stx(NP, ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r)));
-          }
+          for (int l = 0; l < NCOL; ++l) recw[(NP + l) * RS + col] = xr[l];
 #pragma unroll
           for (int i = 0; i < NP; ++i) recw[i * RS + col] = h[i];
         }
@@ -321,6 +325,19 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
     if (ODD) {
       const bool valid = live && m[0] <= P.CD[0] - 2;
       if (__syncthreads_or(valid)) {
+        cx<R> xr[NCOL];
+#pragma unroll
+        for (int l = 0; l < NCOL; ++l) xr[l] = czero<R>();
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < MD; ++j) {
+            if (m[j] > 0) {
+              xr[2 * j] = cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]);
+              xr[2 * j + 1] = cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]);
+            }
+          }
+          xr[NP] = G0;
+        }
         cx<R> h[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) h[i] = czero<R>();
@@ -355,19 +372,8 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
           if (__ballot(valid && grp) == 0ull) continue;
           if (grp) {
             const int col = lane - q * NB;
-            auto stx = [&](int l, const cx<R>& v) { recw[(NP + l) * RS + col] = v; };
 #pragma unroll
-            for (int l = 0; l < NCOL; ++l) stx(l, czero<R>());
-            if (valid) {
-#pragma unroll
-              for (int j = 0; j < MD; ++j) {
-                if (m[j] > 0) {
-                  stx(2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]));
-                  stx(2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]));
-                }
-              }
-              stx(NP, G0);
-            }
+            for (int l = 0; l < NCOL; ++l) recw[(NP + l) * RS + col] = xr[l];
 #pragma unroll
             for (int i = 0; i < NP; ++i) recw[i * RS + col] = h[i];
           }
@@ -490,6 +496,32 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
+        // the record's read values, loaded by every lane with the cotangents
+        // (one memory round trip for both, and for both record batches)
+        const bool rec_ok = live && own;
+        cx<R> xr[NR];
+#pragma unroll
+        for (int l = 0; l < NR; ++l) xr[l] = czero<R>();
+        if (rec_ok) {
+          int rem = e;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int kq = ucoord(P, rem, q);
+            rem -= kq * P.ustride[q];
+            if (kq > 0) xr[q] = cscale(LF(e - P.ustride[q]), sq[kq]);
+          }
+          xr[NPOS] = LF(e);
+          xr[NQ + 2 * K] = cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]);
+          if (m[K] > 0)
+            xr[NQ + 2 * K + 1] = cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]);
+#pragma unroll
+          for (int j = K + 1; j < MD; ++j) {
+            if (m[j] > 0) {
+              xr[NQ + 2 * j] = cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+              xr[NQ + 2 * j + 1] = cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            }
+          }
+        }
         cx<R> h[NPD];
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
@@ -536,36 +568,14 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
           }
         }
         // Abar records of the own entries, NB lanes at a time
-        const bool rec_ok = live && own;
 #pragma unroll 1
         for (int qb = 0; qb < 64 / NB; ++qb) {
           const bool grp = (lane / NB) == qb;
           if (__ballot(rec_ok && grp) == 0ull) continue;   // uniform over the wave
           if (grp) {
             const int col = lane - qb * NB;
-            auto setx = [&](int l, const cx<R>& v) { recw[(NPD + l) * RS + col] = v; };
 #pragma unroll
-            for (int l = 0; l < NR; ++l) setx(l, czero<R>());
-            if (rec_ok) {
-              int rem = e;
-#pragma unroll
-              for (int q = 0; q < NQ; ++q) {
-                const int kq = ucoord(P, rem, q);
-                rem -= kq * P.ustride[q];
-                if (kq > 0) setx(q, cscale(LF(e - P.ustride[q]), sq[kq]));
-              }
-              setx(NPOS, LF(e));
-              setx(NQ + 2 * K, cscale(ld(at32(V.fcur[0], (uint32_t)(r * B + e))), sq[m[K] + 1]));
-              if (m[K] > 0)
-                setx(NQ + 2 * K + 1, cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)(rdn[K] * B + e))), sq[m[K]]));
-#pragma unroll
-              for (int j = K + 1; j < MD; ++j) {
-                if (m[j] > 0) {
-                  setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                  setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                }
-              }
-            }
+            for (int l = 0; l < NR; ++l) recw[(NPD + l) * RS + col] = xr[l];
 #pragma unroll
             for (int i = 0; i < NPD; ++i) recw[i * RS + col] = rec_ok ? h[i] : czero<R>();
           }
@@ -603,6 +613,28 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
       for (int base = e_own0; base < eq1; base += blockDim.x) {
         const int e = base + threadIdx.x;
         const bool live = e < eq1, own = e < e_own1;
+        // the record's read values, loaded with the cotangents
+        const bool rec_ok = live && own;
+        cx<R> xr[NR];
+#pragma unroll
+        for (int l = 0; l < NR; ++l) xr[l] = czero<R>();
+        if (rec_ok) {
+          int rem = e;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int kq = ucoord(P, rem, q);
+            rem -= kq * P.ustride[q];
+            if (kq > 0) xr[q] = cscale(LF(e - P.ustride[q]), sq[kq]);
+          }
+          xr[NPOS] = LF(e);
+#pragma unroll
+          for (int j = 0; j < MD; ++j) {
+            if (m[j] > 0) {
+              xr[NQ + 2 * j] = cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+              xr[NQ + 2 * j + 1] = cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]);
+            }
+          }
+        }
         cx<R> h[NPD];
 #pragma unroll
         for (int i = 0; i < NPD; ++i) h[i] = czero<R>();
@@ -642,33 +674,14 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
           }
         }
         // Abar records of the own entries, NB lanes at a time
-        const bool rec_ok = live && own;
 #pragma unroll 1
         for (int qb = 0; qb < 64 / NB; ++qb) {
           const bool grp = (lane / NB) == qb;
           if (__ballot(rec_ok && grp) == 0ull) continue;   // uniform over the wave
           if (grp) {
             const int col = lane - qb * NB;
-            auto setx = [&](int l, const cx<R>& v) { recw[(NPD + l) * RS + col] = v; };
 #pragma unroll
-            for (int l = 0; l < NR; ++l) setx(l, czero<R>());
-            if (rec_ok) {
-              int rem = e;
-#pragma unroll
-              for (int q = 0; q < NQ; ++q) {
-                const int kq = ucoord(P, rem, q);
-                rem -= kq * P.ustride[q];
-                if (kq > 0) setx(q, cscale(LF(e - P.ustride[q]), sq[kq]));
-              }
-              setx(NPOS, LF(e));
-#pragma unroll
-              for (int j = 0; j < MD; ++j) {
-                if (m[j] > 0) {
-                  setx(NQ + 2 * j, cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                  setx(NQ + 2 * j + 1, cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)(rdn[j] * B + e))), sq[m[j]]));
-                }
-              }
-            }
+            for (int l = 0; l < NR; ++l) recw[(NPD + l) * RS + col] = xr[l];
 #pragma unroll
             for (int i = 0; i < NPD; ++i) recw[i * RS + col] = rec_ok ? h[i] : czero<R>();
           }
