@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
       const bool valid = live && K <= K0 && m[K] <= P.CD[K] - 2;
-      if (!__syncthreads_or(valid)) continue;
+      if (__ballot(valid) == 0ull) continue;   // uniform over the wave (each wave stages its own records)
       // the record's read values, loaded by every lane with the cotangents
       // (one memory round trip for both, and for both record batches)
       cx<R> xr[NCOL];
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 
     if (ODD) {
       const bool valid = live && m[0] <= P.CD[0] - 2;
-      if (__syncthreads_or(valid)) {
+      if (__ballot(valid) != 0ull) {
         cx<R> xr[NCOL];
 #pragma unroll
         for (int l = 0; l < NCOL; ++l) xr[l] = czero<R>();
