@@ -272,6 +272,34 @@ def cpu_baseline(circ, s128, s64, corner):
     return res
 
 
+def cpu_selective(circ, s128, s64):
+    """The selective CPU oracle (the paper's pivot schedules run as printed,
+    plain C, every host thread) on the largest corner of the workload whose
+    patterns it reaches in a few seconds: forward only (it has no reverse
+    mode), with the GPU's complex128 and complex64 results compared on every
+    output of the corner, entry by entry."""
+    import os
+    from oracle import selective as S
+    M = circ.M
+    det = [(circ.detected_mask >> j) & 1 for j in range(M)]
+    corner = [min(circ.cutoffs[j], 5 if M >= 8 else 6) if det[j] else circ.cutoffs[j] for j in range(M)]
+    nU = M - sum(det)
+    sl = (slice(None),) * (2 * nU) + tuple(slice(0, corner[j]) for j in range(M) if det[j])
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref, piv = S.fock_diag_selective(circ.A, circ.b, circ.c, corner, circ.detected_mask, nthreads=threads)
+    dt = time.perf_counter() - t0
+    import torch
+    ref_t = torch.from_numpy(ref).to(s128.rho.device)
+    e128 = errors_vs(s128.rho[sl], ref_t)
+    res = dict(value=ref.size / dt, unit="Fock amplitudes/s (forward only)", cores=threads, kind="oracle",
+               sample=f"every detection pattern with n < {corner} ({ref.size} outputs, {piv} pivots)",
+               seconds=dt, gpu_c128_vs_oracle=e128)
+    if s64 is not None:
+        res["gpu_c64_vs_oracle"] = errors_vs(s64.rho[sl], ref_t)
+    return res
+
+
 def batched_leg(reps=1):
     """The uneven batch (256 circuits, M 3..6, cutoffs 8..16, 0 or 1 undetected
     mode with cutoff 20..40, b = 0, complex128): batched persistent launches
@@ -717,6 +745,7 @@ def main():
         per = first["seconds"] / size(corners[0])
         pick = max((cn for cn in corners if per * size(cn) <= 25.0), key=size, default=corners[0])
         line["cpu_baseline"] = first if pick is corners[0] else cpu_baseline(circ, s128, s64, pick)
+        line["cpu_selective_oracle"] = cpu_selective(circ, s128, s64)
         s64.release()
         progress("cpu_baseline", t_start)
         del np
