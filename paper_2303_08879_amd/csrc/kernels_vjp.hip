@@ -404,18 +404,22 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 2 reverse step.  One workgroup per (lattice point, chunk of rows
-// of the first undetected coordinate), as in the forward.  The undetected
-// neighbour terms make the cotangent of a pivot entry pull from the entry one
-// row below, so a chunk recomputes the target cotangents of two rows past its
-// own (bridge pivots: the rows its diagonal pivot needs; diagonal pivot: one
-// row), without storing them.
-// Abar records are folded per wavefront: each wave stages WREC records at a
-// time in its own LDS region and each lane accumulates fixed (i, l) pairs in
-// registers for the whole kernel; no workgroup barrier is involved.
+// Algorithm 2 reverse step.  One workgroup of WV wavefronts per (lattice
+// point, chunk of rows of the first undetected coordinate), the chunk about
+// 64 entries per wavefront.  The undetected neighbour terms make the
+// cotangent of a pivot entry pull from the entry one row below, so a chunk
+// recomputes the target cotangents of two rows past its own (bridge pivots:
+// the rows its diagonal pivot needs; diagonal pivot: one row), without
+// storing them; two wavefronts per chunk halve that recomputation against
+// one-wavefront chunks while keeping a pass over a chunk one wavefront step
+// long (5-mode conditional reverse sweep -4 %, the 6-mode gradient circuit's
+// -10 %; four wavefronts lose on the 5-mode workload).
+// Abar records are folded per wavefront: each wave stages NB records at a
+// time in its own LDS region and reduces them on the matrix cores into its
+// own accumulators; the waves' tables are added in wave order at the end.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R, int NB, bool ST>
-__global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
+template <int MD, int NQ, typename R, int NB, bool ST, int WV>
+__global__ __launch_bounds__(64 * WV) void k_vjp_block(DevPlan P, VjpPtrs<R> V, const cx<R>* __restrict__ Ai,
                                                         const cx<R>* __restrict__ bi, int S, int nwork,
                                                         ChunkGeo G, double2* __restrict__ partial) {
   constexpr int NPD = 2 * MD;
@@ -445,7 +449,7 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
   cx<R>* lfw = reinterpret_cast<cx<R>*>(smem_raw);
   cx<R>* qv = ST ? g0a + (size_t)RC * R0 : lfw + nrow1;
   cx<R>* rec = ST ? lfw : qv + (size_t)NQ * nrow2;   // waves x RS x (NPD + NR)
-  cx<R>* sA = rec + (size_t)(kBT / 64) * RS * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
+  cx<R>* sA = rec + (size_t)WV * RS * (NPD + NR);   // A (NPOS x NPOS) then b (NPOS)
   const cx<R>* sb = sA + NPOS * NPOS;
   R* sq = reinterpret_cast<R*>(sA + NPOS * NPOS + NPOS);
   R* isq = sq + (kMaxCut + 4);
@@ -707,17 +711,22 @@ __global__ __launch_bounds__(kBT) void k_vjp_block(DevPlan P, VjpPtrs<R> V, cons
     for (int e = e_own0 + threadIdx.x; e < e_own1; e += blockDim.x) st(at32(V.gcur[0], (uint32_t)(r * B + e)), g0a[e - e_own0]);
     __syncthreads();
   }
-  // fold the wave's pair table into this block's slot (one wavefront per block)
+  // fold the waves' pair tables (in wave order) into this block's slot
   cx<double>* red = reinterpret_cast<cx<double>*>(smem_raw);
   __syncthreads();
-  mfma_acc_store<NPD, NR, NR>(acc, red);
+  mfma_acc_store<NPD, NR, NR>(acc, red + (size_t)(threadIdx.x >> 6) * NPAIR);
   __syncthreads();
   double2* slot = partial + (size_t)blockIdx.x * (NPOS * NR);
   for (int p = threadIdx.x; p < NPAIR; p += blockDim.x) {
     const int i = p / NR, l = p - (p / NR) * NR;
     const int q = (NQ + i) * NR + l;
+    double sx = 0.0, sy = 0.0;
+    for (int wv = 0; wv < WV; ++wv) {
+      sx += red[(size_t)wv * NPAIR + p].x;
+      sy += red[(size_t)wv * NPAIR + p].y;
+    }
     const double2 v = slot[q];
-    slot[q] = make_double2(v.x + red[p].x, v.y + red[p].y);
+    slot[q] = make_double2(v.x + sx, v.y + sy);
   }
 }
 
@@ -957,15 +966,21 @@ static cx<R>* gptr(const Plan& Pl, char* base, size_t off, int g, int S) {
   return reinterpret_cast<cx<R>*>(base + off + (size_t)(S & 1) * Pl.maxN[g] * Pl.B * sizeof(cx<R>));
 }
 
+template <int MD, int NQ, typename R, bool ST, int WV>
+static void launch_vjp_block_w(size_t shm, int grid, hipStream_t st, const DevPlan& P, const VjpPtrs<R>& Vp,
+                               const cx<R>* Ai, const cx<R>* bi, int S, int nwork, const ChunkGeo& G,
+                               double2* partial) {
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MD, NQ, R, kBlockBatch, ST, WV>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_vjp_block<MD, NQ, R, kBlockBatch, ST, WV>), dim3(grid), dim3(64 * WV), shm, st, P, Vp, Ai,
+                     bi, S, nwork, G, partial);
+}
 template <int MD, int NQ, typename R, bool ST>
 static void launch_vjp_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const VjpPtrs<R>& Vp,
                                const cx<R>* Ai, const cx<R>* bi, int S, int nwork, const ChunkGeo& G,
                                double2* partial) {
-  if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vjp_block<MD, NQ, R, kBlockBatch, ST>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_vjp_block<MD, NQ, R, kBlockBatch, ST>), dim3(grid), dim3(kBT), shm, st, P, Vp, Ai, bi, S,
-                     nwork, G, partial);
+  launch_vjp_block_w<MD, NQ, R, ST, kVjpWaves>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
 }
 
 template <typename R>
@@ -1134,8 +1149,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
 #undef FD_VJP_POINT
     } else {
       // as in the forward sweep: half-size row chunks on levels with few units
-      ChunkGeo G = chunk_geo(Pl);
-      if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
+      const ChunkGeo G = vjp_geo(Pl, nwork);
       const size_t shm = vjp_lds_bytes_for(Pl, G);
       if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
       // streamed rows: private slots for at most kStreamSlots workgroups

@@ -3,6 +3,7 @@
 // the undetected block of Algorithm 2).  Host-only: no device call here
 // except in ensure_device(), which uploads the tables on first use.
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <cstring>
 
@@ -399,10 +400,21 @@ ChunkGeo chunk_geo(const Plan& Pl, int target) {
 // square-root tables.
 size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
-  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1;
+  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1, WV = kVjpWaves;
   const size_t rows = Pl.st_vjp ? 0 : (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0;
-  const size_t ents = rows + (size_t)(kBT / 64) * (kBlockBatch + 1) * (NPD + NR);
-  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)NPD * NR * 16) + 2 * (kMaxCut + 4) * rb;
+  const size_t ents = rows + (size_t)WV * (kBlockBatch + 1) * (NPD + NR);
+  return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)WV * NPD * NR * 16) +
+         2 * (kMaxCut + 4) * rb;
+}
+
+// Chunk geometry of a reverse level with nwork lattice points: about 64
+// entries per wavefront of the workgroup; half-height chunks on levels with
+// few units.
+ChunkGeo vjp_geo(const Plan& Pl, int64_t nwork) {
+  const int t = 64 * kVjpWaves;
+  ChunkGeo G = chunk_geo(Pl, t);
+  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, t / 2);
+  return G;
 }
 
 size_t fwd_stream_lds_bytes(const Plan& Pl) {
@@ -416,7 +428,8 @@ size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G, bool jvp) {
 }
 
 size_t vjp_lds_bytes(const Plan& Pl) {
-  return std::max(vjp_lds_bytes_for(Pl, chunk_geo(Pl)), vjp_lds_bytes_for(Pl, chunk_geo(Pl, kBT / 2)));
+  const int t = 64 * kVjpWaves;
+  return std::max(vjp_lds_bytes_for(Pl, chunk_geo(Pl, t)), vjp_lds_bytes_for(Pl, chunk_geo(Pl, t / 2)));
 }
 
 size_t jvp_half_bytes(const Plan& Pl) { return (fwd_layout(Pl, true, false, 0).total + 255) / 256 * 256; }
@@ -531,7 +544,7 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
 
 size_t vjp_private_entries(const Plan& P) {
   if (P.B == 1 || P.MD == 0) return 0;
-  const ChunkGeo G = chunk_geo(P);   // the larger of the two chunk heights the launcher uses
+  const ChunkGeo G = chunk_geo(P, 64 * kVjpWaves);   // the taller of the two chunk heights the launcher uses
   return (size_t)(P.MD + 1) * (G.RC + 1) * G.R0 + (size_t)G.RC * G.R0 +
          (P.st_vjp ? (size_t)P.nq * (G.RC + 2) * G.R0 : 0);
 }
