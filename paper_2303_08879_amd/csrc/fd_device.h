@@ -172,12 +172,13 @@ __device__ __forceinline__ void wave_sync() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Orders a unit's phases: LDS traffic within the wavefront, or (ST, rows in
-// global memory) a workgroup-scope fence and barrier, which makes one lane's
-// global writes visible to the others (one wavefront per workgroup).
-template <bool ST>
+// Orders a unit's phases: LDS traffic within the wavefront, or (WG: rows in
+// global memory, or a unit shared by several wavefronts) a workgroup-scope
+// fence and barrier, which makes one lane's writes visible to every lane of
+// the workgroup.
+template <bool WG>
 __device__ __forceinline__ void unit_sync() {
-  if constexpr (ST)
+  if constexpr (WG)
     __syncthreads();
   else
     wave_sync();

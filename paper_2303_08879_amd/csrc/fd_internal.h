@@ -50,6 +50,8 @@ constexpr int kStreamSlots = 1024;       // workgroups of a block kernel whose r
 constexpr int kThreads = 256;
 constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
 constexpr int kVjpWaves = 2;             // wavefronts per workgroup of the block reverse kernel
+constexpr int kFwdWaves = 4;             // wavefronts per workgroup of the block forward kernel
+constexpr int kFwdChunk = 384;           // own entries of one of its (lattice point, row chunk) units
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
 constexpr int kPointBatch = 32;          // Abar records per LDS staging batch, point reverse kernel
 constexpr int kBlockBatch = 32;          // the same, block reverse kernel
@@ -341,7 +343,8 @@ hipError_t launch_fwd_level(const Plan& P, bool odd, int S, const void* const* r
 // a non-null src (one launch).
 hipError_t launch_copy_fams(const Plan& P, const void* const* src, void* const* dst, const int64_t* n, hipStream_t st);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
-ChunkGeo vjp_geo(const Plan& P, int64_t nwork);     // its chunks on a level of nwork lattice points
+ChunkGeo fwd_geo(const Plan& P, int64_t nwork);     // forward chunks on a level of nwork lattice points
+ChunkGeo vjp_geo(const Plan& P, int64_t nwork);     // reverse chunks on a level of nwork lattice points
 constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
 // LDS tile of the permutations between rho's C order and node order:
 // consecutive lattice points x consecutive undetected-block entries

@@ -23,7 +23,7 @@
 
 namespace fd {
 
-static_assert(kBT == 64, "block units assume one wavefront per (node, chunk)");
+static_assert(kBT == 64, "kBT is one wavefront");
 
 // ---------------------------------------------------------------------------
 // prep: caller's triple (block order) -> interleaved internal positions,
@@ -275,7 +275,8 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 // ---------------------------------------------------------------------------
 // Algorithm 2 (undetected modes present).  A node's block of B entries is
 // split into chunks of whole rows of the first undetected coordinate (rows of
-// R0 = B / C0 entries); one wavefront handles one (lattice point, chunk).
+// R0 = B / C0 entries); the WV wavefronts of one workgroup handle one
+// (lattice point, chunk); the batched sweep gives each unit one wavefront.
 // The pivot's undetected neighbours reach one row back, so a chunk computes
 // the pivot rows it needs one row above its own (recomputed, not stored).
 // LDS: F0(m) rows [k0-2, k1) and the bridge pivot blocks F1k(K)(m), rows
@@ -284,7 +285,7 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 // workgroup's slot in global memory; workgroup-scope fences order its
 // writes before other lanes read them.
 // ---------------------------------------------------------------------------
-template <int MD, int NQ, typename R, typename LP, typename E, bool ST = false>
+template <int MD, int NQ, typename R, typename LP, typename E, bool ST = false, int WV = 1>
 __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, const E* sA, const E* sb,
                                                const R* sq, const R* isq, int S, int r, int c, const ChunkGeo& G,
                                                E* lf0, E* lpk, int64_t dT = 0) {
@@ -297,7 +298,10 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
   // overlap of iterations is worth more than a fourth wave.
   constexpr bool kFence = MD >= 4 || (MD >= 3 && NQ >= 4);
   const int B = P.B, R0 = G.R0;
-  const int lane = threadIdx.x & 63;
+  // WV wavefronts share the unit (the lanes of the whole workgroup)
+  constexpr int NT = kBT * WV;
+  constexpr bool kBar = ST || WV > 1;
+  const int lane = WV == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int pk1 = (G.RC + 1) * R0;   // entries of one pivot block in LDS
   {
     const int k0 = c * G.RC, k1 = min(G.C0, k0 + G.RC);
@@ -319,14 +323,14 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
     };
     if constexpr (!ST) {
       const int e0 = max(0, k0 - 2) * R0, e1 = k1 * R0;
-      for (int e = e0 + lane; e < e1; e += kBT) lf0[e - f0base] = T::load(at32(f0g, (uint32_t)e), dT);
+      for (int e = e0 + lane; e < e1; e += NT) lf0[e - f0base] = T::load(at32(f0g, (uint32_t)e), dT);
     }
-    unit_sync<ST>();
+    unit_sync<kBar>();
     // diagonal pivot, rows [k0-1, k1): own rows store every type-1 target,
     // the halo row only keeps the bridge pivot blocks
     {
       const int e0 = max(0, k0 - 1) * R0, e1 = k1 * R0;
-      for (int e = e0 + lane; e < e1; e += kBT) {
+      for (int e = e0 + lane; e < e1; e += NT) {
         const bool own = e >= k0 * R0;
         int kap[NQ];
         int rem = e;
@@ -374,13 +378,13 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
         if constexpr (kFence) compiler_fence();
       }
     }
-    unit_sync<ST>();
+    unit_sync<kBar>();
     // bridges d(m) + 1_ket(K), own rows
 #pragma unroll
     for (int K = 0; K < MD; ++K) {
       if (K > K0 || m[K] > P.CD[K] - 2) continue;   // uniform
       const E* pv = lpk + (size_t)K * pk1;
-      for (int e = k0 * R0 + lane; e < k1 * R0; e += kBT) {
+      for (int e = k0 * R0 + lane; e < k1 * R0; e += NT) {
         int kap[NQ];
         int rem = e;
 #pragma unroll
@@ -439,7 +443,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
       }
       if constexpr (kFence) compiler_fence();
     }
-    unit_sync<ST>();
+    unit_sync<kBar>();
   }
 }
 

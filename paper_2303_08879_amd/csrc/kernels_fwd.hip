@@ -42,13 +42,17 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
   fwd_point_unit<MD, ODD, R>(P, L, Ai, bi, spn, sq, isq, S, r);
 }
 
-// Algorithm 2: one wavefront per (lattice point, chunk of undetected rows).
+// Algorithm 2: one workgroup of WV wavefronts per (lattice point, chunk of
+// undetected rows).  Chunks of about 96 entries per wavefront over four
+// wavefronts leave fewer rows to the halo than one-wavefront chunks (the
+// 5-mode conditional forward sweep 2.29 -> 1.77 ms, the 4-mode one 0.45 ->
+// 0.39 ms, the 6-mode gradient circuit 4.61 -> 4.32 ms).
 // E = dual<R> carries every amplitude's tangent along (forward mode), dT
 // bytes after the value.  ST: the rows stream from HBM (blocks whose rows do
 // not fit the LDS); the bridge pivot blocks then go to the workgroup's slot
 // of `slots` (slot_len entries each).
-template <int MD, int NQ, typename R, typename E, bool ST>
-__global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
+template <int MD, int NQ, typename R, typename E, bool ST, int WV>
+__global__ __launch_bounds__(kBT * WV) void k_fwd_block(DevPlan P, LevelPtrs<R> L, const cx<R>* __restrict__ Ai,
                                                    const cx<R>* __restrict__ bi, int S, int nwork, ChunkGeo G,
                                                    int64_t dT, cx<R>* slots, int64_t slot_len) {
   static_assert(!ST || std::is_same<E, cx<R>>::value, "streamed rows carry values only");
@@ -67,11 +71,11 @@ __global__ __launch_bounds__(kBT) void k_fwd_block(DevPlan P, LevelPtrs<R> L, co
     isq[v] = v ? R(1) / sqrt(R(v)) : R(0);
   }
   for (int i = threadIdx.x; i < NPOS * NPOS + NPOS; i += blockDim.x) sA[i] = ET<E>::load(Ai + i, dT);
-  // one wavefront per workgroup: the unit's first wave_sync orders these
-  // LDS writes before their reads
+  // the unit's first unit_sync orders these LDS writes before their reads
   for (int w = blockIdx.x; w < nwork * G.nchunks; w += gridDim.x) {
     const int r = w / G.nchunks, c = w - r * G.nchunks;
-    fwd_block_unit<MD, NQ, R, LevelPtrs<R>, E, ST>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk, dT);
+    fwd_block_unit<MD, NQ, R, LevelPtrs<R>, E, ST, WV>(P, L, sA, sb, sq, isq, S, r, c, G, lf0, lpk, dT);
+    if constexpr (WV > 1) __syncthreads();   // the next unit overwrites the rows
   }
 }
 
@@ -106,18 +110,26 @@ __global__ __launch_bounds__(kThreads) void k_out_perm(DevPlan P, const cx<R>* _
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-// Rows of the first undetected coordinate per chunk: about `target` own
-// entries (default one wavefront), spread evenly over the rows.
-
+template <int MD, int NQ, typename R, typename E, bool ST, int WV>
+static void launch_fwd_block_w(size_t shm, int grid, hipStream_t st, const DevPlan& P, const LevelPtrs<R>& L,
+                               const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G, int64_t dT,
+                               cx<R>* slots, int64_t slot_len) {
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R, E, ST, WV>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R, E, ST, WV>), dim3(grid), dim3(kBT * WV), shm, st, P, L, A, b, S, nwork,
+                     G, dT, slots, slot_len);
+}
 template <int MD, int NQ, typename R, typename E = cx<R>, bool ST = false>
 static void launch_fwd_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const LevelPtrs<R>& L,
                                const cx<R>* A, const cx<R>* b, int S, int nwork, const ChunkGeo& G,
                                int64_t dT = 0, cx<R>* slots = nullptr, int64_t slot_len = 0) {
-  if (shm > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fwd_block<MD, NQ, R, E, ST>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL((k_fwd_block<MD, NQ, R, E, ST>), dim3(grid), dim3(kBT), shm, st, P, L, A, b, S, nwork, G, dT,
-                     slots, slot_len);
+  // values with rows in LDS: kFwdWaves wavefronts per unit; the streamed
+  // rows and the forward mode: one
+  if constexpr (std::is_same<E, cx<R>>::value && !ST)
+    launch_fwd_block_w<MD, NQ, R, E, ST, kFwdWaves>(shm, grid, st, P, L, A, b, S, nwork, G, dT, slots, slot_len);
+  else
+    launch_fwd_block_w<MD, NQ, R, E, ST, 1>(shm, grid, st, P, L, A, b, S, nwork, G, dT, slots, slot_len);
 }
 
 // The undetected-block fill for the plan's number of block coordinates.
@@ -175,11 +187,10 @@ static hipError_t launch_fwd_level_t(const Plan& Pl, const DevPlan& P, bool odd,
 #undef FD_LAUNCH_POINT
   } else {
     // a level with few units is latency-bound: halve the chunks to put more
-    // wavefronts in flight (config-2-sized levels: -7 %); a large level keeps
-    // whole-wavefront chunks (halving them costs 30-40 % there)
-    ChunkGeo G = chunk_geo(Pl);
-    if ((int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
+    // wavefronts in flight; a large level keeps the full height
     const bool stm = Pl.st_fwd;
+    ChunkGeo G = stm ? chunk_geo(Pl) : fwd_geo(Pl, nwork);
+    if (stm && (int64_t)nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
     const size_t shm = stm ? fwd_stream_lds_bytes(Pl) : fwd_lds_bytes_for(Pl, G);
     if (shm > kMaxLds) return hipErrorInvalidConfiguration;
     // streamed rows: at most kStreamSlots workgroups, each with its slot after

@@ -382,7 +382,8 @@ FwdLayout fwd_layout(const Plan& P, bool odd, bool store_all, size_t base) {
 }
 
 // Chunks of whole rows of the first undetected coordinate, about `target`
-// entries each (one wavefront per (lattice point, chunk) unit).
+// entries each, spread evenly over the rows (one (lattice point, chunk) unit
+// per workgroup of the block kernels).
 ChunkGeo chunk_geo(const Plan& Pl, int target) {
   ChunkGeo G;
   G.C0 = Pl.udims[0];
@@ -395,8 +396,8 @@ ChunkGeo chunk_geo(const Plan& Pl, int target) {
 }
 
 // Dynamic LDS of the block reverse kernel for a chunk geometry: the forward
-// pivot rows, the undetected-neighbour terms, one wavefront's record staging
-// batch and A, b (or the pair table of the final fold, if larger), then the
+// pivot rows, the undetected-neighbour terms, each wavefront's record
+// staging batch and A, b (or the pair table of the final fold, if larger), then the
 // square-root tables.
 size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
@@ -405,6 +406,20 @@ size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t ents = rows + (size_t)WV * (kBlockBatch + 1) * (NPD + NR);
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)WV * NPD * NR * 16) +
          2 * (kMaxCut + 4) * rb;
+}
+
+// Chunk geometry of a forward level with nwork lattice points (its units
+// span kFwdWaves wavefronts): about kFwdChunk own entries, half-height chunks
+// on levels with few units, and the one-wavefront heights where the taller
+// chunk's rows do not fit the LDS (those fit whenever the plan's rows are not
+// streamed).
+ChunkGeo fwd_geo(const Plan& Pl, int64_t nwork) {
+  ChunkGeo G = chunk_geo(Pl, kFwdChunk);
+  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kFwdChunk / 2);
+  if (fwd_lds_bytes_for(Pl, G) <= kMaxLds) return G;
+  G = chunk_geo(Pl, kBT);
+  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
+  return G;
 }
 
 // Chunk geometry of a reverse level with nwork lattice points: about 64

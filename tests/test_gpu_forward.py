@@ -80,6 +80,22 @@ def test_fenced_block_shapes(M, cut, mask, bz):
         assert_close(out, ref, label=str(b_mode))
 
 
+# one undetected mode at cutoff 23-40: several row chunks of several rows
+# per node, the last one ragged; one chunk's unit spans several wavefronts
+TALL = [(3, [25, 3, 3], 0b110, True), (3, [25, 3, 3], 0b110, False), (4, [23, 3, 2, 3], 0b1110, False),
+        (2, [40, 4], 0b10, False)]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", TALL)
+def test_tall_row_chunks(M, cut, mask, bz):
+    rng = np.random.default_rng(2700 + M * 31 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.15)
+    ref = O.fock_diag(A, b, c, cut, mask)
+    for b_mode in (["auto", "zero"] if bz else ["general"]):
+        out = gpu(A, b, c, cut, mask, b_mode=b_mode)
+        assert_close(out, ref, label=f"{cut} {bin(mask)} {b_mode}")
+
+
 # three undetected modes (six block coordinates), with zero to four detected
 # modes; blocks of several row chunks; two undetected modes at cutoff 9 (6561
 # entries per node, more than one LDS tile per row chunk)

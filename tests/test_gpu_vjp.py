@@ -111,6 +111,26 @@ def test_vjp_three_undetected_modes(M, cut, mask, bz):
         check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref, label=f"{cut} {bin(mask)} b=0")
 
 
+# one undetected mode at cutoff 23-40: several row chunks of several rows
+# per node, the last one ragged (rows of the first block coordinate split
+# unevenly); the units of one chunk span several wavefronts
+TALL = [(3, [25, 3, 3], 0b110, True), (3, [25, 3, 3], 0b110, False), (4, [23, 3, 2, 3], 0b1110, False),
+        (2, [40, 4], 0b10, False)]
+
+
+@pytest.mark.parametrize("M,cut,mask,bz", TALL)
+def test_vjp_tall_row_chunks(M, cut, mask, bz):
+    rng = np.random.default_rng(4700 + M * 43 + sum(cut) + mask)
+    A, b, c = rand_triple(rng, M, bz, scale=0.15)
+    shape = O.fock_diag(A, b, c, cut, mask).shape
+    g = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    ref = O.fock_diag_vjp(A, b, c, cut, mask, g)
+    check(gpu_vjp(A, b, c, cut, mask, g), ref, label=f"{cut} {bin(mask)}")
+    check(gpu_vjp(A, b, c, cut, mask, g, use_saved=False), ref, label=f"{cut} {bin(mask)} recompute")
+    if bz:
+        check(gpu_vjp(A, b, c, cut, mask, g, b_mode="zero"), ref, label=f"{cut} {bin(mask)} b=0")
+
+
 STREAMED = [(3, [9, 9, 3], 0b100, False), (3, [12, 12, 3], 0b100, False), (4, [12, 12, 2, 2], 0b1100, False),
             (3, [16, 16, 2], 0b100, False),
             (4, [12, 12, 2, 2], 0b1100, True), (4, [5, 5, 5, 2], 0b1000, False)]
