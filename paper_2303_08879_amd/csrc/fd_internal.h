@@ -49,7 +49,8 @@ constexpr int kPartialSlots = 4096;      // deterministic VJP partial accumulato
 constexpr int kStreamSlots = 1024;       // workgroups of a block kernel whose rows stream from HBM
 constexpr int kThreads = 256;
 constexpr int kBT = 64;                  // threads of the block (Algorithm 2) kernels: one wavefront
-constexpr int kVjpWaves = 2;             // wavefronts per workgroup of the block reverse kernel
+constexpr int kVjpWaves = 4;             // wavefronts per workgroup of the block reverse kernel,
+constexpr int kVjpWavesLds = 2;          // or this many where four wavefronts' staging does not fit the LDS
 constexpr int kFwdWaves = 4;             // wavefronts per workgroup of the block forward kernel
 constexpr int kFwdChunk = 384;           // own entries of one of its (lattice point, row chunk) units
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
@@ -168,6 +169,9 @@ struct Plan {
   // blocks whose rows do not fit the LDS staging stream them from HBM, per
   // kernel: forward block units, block fill, reverse block units, reverse fill
   bool st_fwd = false, st_ufill = false, st_vjp = false, st_ufill_vjp = false;
+  // wavefronts per workgroup of the block reverse kernel (kVjpWaves, or
+  // kVjpWavesLds where the rows and staging of kVjpWaves do not fit the LDS)
+  int vjp_waves = kVjpWavesLds;
   bool odd_for(bool b_zero) const { return !b_zero || MU > 0; }
 };
 
@@ -344,6 +348,10 @@ hipError_t launch_fwd_level(const Plan& P, bool odd, int S, const void* const* r
 hipError_t launch_copy_fams(const Plan& P, const void* const* src, void* const* dst, const int64_t* n, hipStream_t st);
 ChunkGeo chunk_geo(const Plan& P, int target = kBT);   // forward block kernels
 ChunkGeo fwd_geo(const Plan& P, int64_t nwork);     // forward chunks on a level of nwork lattice points
+struct VjpChunking {
+  int target, small, small_units;
+};
+VjpChunking vjp_chunking(const Plan& P);
 ChunkGeo vjp_geo(const Plan& P, int64_t nwork);     // reverse chunks on a level of nwork lattice points
 constexpr int kSmallLevelUnits = 4096;   // below: the forward level halves its row chunks
 // LDS tile of the permutations between rho's C order and node order:

@@ -405,15 +405,15 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
 
 // ---------------------------------------------------------------------------
 // Algorithm 2 reverse step.  One workgroup of WV wavefronts per (lattice
-// point, chunk of rows of the first undetected coordinate), the chunk about
-// 64 entries per wavefront.  The undetected neighbour terms make the
-// cotangent of a pivot entry pull from the entry one row below, so a chunk
-// recomputes the target cotangents of two rows past its own (bridge pivots:
-// the rows its diagonal pivot needs; diagonal pivot: one row), without
-// storing them; two wavefronts per chunk halve that recomputation against
-// one-wavefront chunks while keeping a pass over a chunk one wavefront step
-// long (5-mode conditional reverse sweep -4 %, the 6-mode gradient circuit's
-// -10 %; four wavefronts lose on the 5-mode workload).
+// point, chunk of rows of the first undetected coordinate).  The undetected
+// neighbour terms make the cotangent of a pivot entry pull from the entry one
+// row below, so a chunk recomputes the target cotangents of two rows past its
+// own (bridge pivots: the rows its diagonal pivot needs; diagonal pivot: one
+// row), without storing them.  Four wavefronts with chunks of about 128
+// entries each (48 on levels with few units) make that recomputation a small
+// part of a chunk; plans whose four-wavefront staging does not fit the LDS,
+// and streamed rows, run two wavefronts with 64-entry chunks (the chunk
+// heights are set by the planner).
 // Abar records are folded per wavefront: each wave stages NB records at a
 // time in its own LDS region and reduces them on the matrix cores into its
 // own accumulators; the waves' tables are added in wave order at the end.
@@ -977,10 +977,13 @@ static void launch_vjp_block_w(size_t shm, int grid, hipStream_t st, const DevPl
                      bi, S, nwork, G, partial);
 }
 template <int MD, int NQ, typename R, bool ST>
-static void launch_vjp_block_k(size_t shm, int grid, hipStream_t st, const DevPlan& P, const VjpPtrs<R>& Vp,
-                               const cx<R>* Ai, const cx<R>* bi, int S, int nwork, const ChunkGeo& G,
-                               double2* partial) {
-  launch_vjp_block_w<MD, NQ, R, ST, kVjpWaves>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
+static void launch_vjp_block_k(int waves, size_t shm, int grid, hipStream_t st, const DevPlan& P,
+                               const VjpPtrs<R>& Vp, const cx<R>* Ai, const cx<R>* bi, int S, int nwork,
+                               const ChunkGeo& G, double2* partial) {
+  if (!ST && waves == kVjpWaves)
+    launch_vjp_block_w<MD, NQ, R, ST, kVjpWaves>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
+  else
+    launch_vjp_block_w<MD, NQ, R, ST, kVjpWavesLds>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
 }
 
 template <typename R>
@@ -1148,7 +1151,7 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
       }
 #undef FD_VJP_POINT
     } else {
-      // as in the forward sweep: half-size row chunks on levels with few units
+      // as in the forward sweep: shorter row chunks on levels with few units
       const ChunkGeo G = vjp_geo(Pl, nwork);
       const size_t shm = vjp_lds_bytes_for(Pl, G);
       if (shm > kMaxLds) return hipErrorInvalidConfiguration;   // rejected before the sweep
@@ -1157,9 +1160,9 @@ static hipError_t run_vjp_t(const Plan& Pl, bool odd, const void* A, const void*
                                               Pl.st_vjp ? kStreamSlots : kPartialSlots - 1);
 #define FD_VJP_BLOCK_NQ(MDV, NQV)                                                                  \
   if (Pl.st_vjp)                                                                                   \
-    launch_vjp_block_k<MDV, NQV, R, true>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);     \
+    launch_vjp_block_k<MDV, NQV, R, true>(Pl.vjp_waves, shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial); \
   else                                                                                             \
-    launch_vjp_block_k<MDV, NQV, R, false>(shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
+    launch_vjp_block_k<MDV, NQV, R, false>(Pl.vjp_waves, shm, grid, st, P, Vp, Ai, bi, S, nwork, G, partial);
 #define FD_VJP_BLOCK(MDV)        \
   case MDV:                      \
     if (Pl.nq == 2) {            \

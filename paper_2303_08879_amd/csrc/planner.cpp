@@ -307,6 +307,8 @@ fd_status build_plan(int M, const int* cutoffs, uint32_t mask, fd_dtype dt, uint
     const size_t rows = std::max(fwd_lds_bytes_for(*P, chunk_geo(*P)), fwd_lds_bytes_for(*P, chunk_geo(*P, kBT / 2)));
     P->st_fwd = P->MD > 0 && rows > kMaxLds;
     P->st_ufill = ufill_lds_bytes(*P, false) > kMaxLds;
+    P->vjp_waves = kVjpWaves;
+    if (vjp_lds_bytes(*P) > kMaxLds) P->vjp_waves = kVjpWavesLds;
     P->st_vjp = P->MD > 0 && vjp_lds_bytes(*P) > kMaxLds;
     P->st_ufill_vjp = ufill_lds_bytes(*P, true) > kMaxLds;
   }
@@ -401,7 +403,7 @@ ChunkGeo chunk_geo(const Plan& Pl, int target) {
 // square-root tables.
 size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
   const size_t eb = elem_bytes(Pl.dt), rb = eb / 2;
-  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1, WV = kVjpWaves;
+  const int MD = Pl.MD, NPD = 2 * MD, NR = Pl.npos + 1, WV = Pl.vjp_waves;
   const size_t rows = Pl.st_vjp ? 0 : (size_t)(G.RC + 1) * G.R0 + (size_t)Pl.nq * (G.RC + 2) * G.R0;
   const size_t ents = rows + (size_t)WV * (kBlockBatch + 1) * (NPD + NR);
   return std::max((ents + (size_t)Pl.npos * (Pl.npos + 1)) * eb, (size_t)WV * NPD * NR * 16) +
@@ -422,13 +424,21 @@ ChunkGeo fwd_geo(const Plan& Pl, int64_t nwork) {
   return G;
 }
 
-// Chunk geometry of a reverse level with nwork lattice points: about 64
-// entries per wavefront of the workgroup; half-height chunks on levels with
-// few units.
+// Row chunks of the reverse block kernel: own entries per unit on large
+// levels, on levels with fewer than `small_units` units, and that threshold.
+// Four wavefronts take 128 entries each (48 on small levels): a chunk's two
+// halo rows then cost less of its time (5-mode conditional reverse 6.2 -> 5.7
+// ms, 6-mode gradient circuit 12.9 -> 10.4 ms); two wavefronts keep 64 (32).
+VjpChunking vjp_chunking(const Plan& Pl) {
+  if (Pl.vjp_waves == kVjpWaves) return {128 * kVjpWaves, 48 * kVjpWaves, 1024};
+  return {64 * Pl.vjp_waves, 32 * Pl.vjp_waves, kSmallLevelUnits};
+}
+
+// Chunk geometry of a reverse level with nwork lattice points.
 ChunkGeo vjp_geo(const Plan& Pl, int64_t nwork) {
-  const int t = 64 * kVjpWaves;
-  ChunkGeo G = chunk_geo(Pl, t);
-  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, t / 2);
+  const VjpChunking t = vjp_chunking(Pl);
+  ChunkGeo G = chunk_geo(Pl, t.target);
+  if (nwork * G.nchunks < t.small_units) G = chunk_geo(Pl, t.small);
   return G;
 }
 
@@ -443,8 +453,8 @@ size_t fwd_lds_bytes_for(const Plan& Pl, const ChunkGeo& G, bool jvp) {
 }
 
 size_t vjp_lds_bytes(const Plan& Pl) {
-  const int t = 64 * kVjpWaves;
-  return std::max(vjp_lds_bytes_for(Pl, chunk_geo(Pl, t)), vjp_lds_bytes_for(Pl, chunk_geo(Pl, t / 2)));
+  const VjpChunking t = vjp_chunking(Pl);
+  return std::max(vjp_lds_bytes_for(Pl, chunk_geo(Pl, t.target)), vjp_lds_bytes_for(Pl, chunk_geo(Pl, t.small)));
 }
 
 size_t jvp_half_bytes(const Plan& Pl) { return (fwd_layout(Pl, true, false, 0).total + 255) / 256 * 256; }
@@ -559,7 +569,7 @@ VjpLayout vjp_layout(const Plan& P, bool odd, size_t base) {
 
 size_t vjp_private_entries(const Plan& P) {
   if (P.B == 1 || P.MD == 0) return 0;
-  const ChunkGeo G = chunk_geo(P, 64 * kVjpWaves);   // the taller of the two chunk heights the launcher uses
+  const ChunkGeo G = chunk_geo(P, vjp_chunking(P).target);   // the taller of the launcher's two chunk heights
   return (size_t)(P.MD + 1) * (G.RC + 1) * G.R0 + (size_t)G.RC * G.R0 +
          (P.st_vjp ? (size_t)P.nq * (G.RC + 2) * G.R0 : 0);
 }
