@@ -52,7 +52,8 @@ constexpr int kBT = 64;                  // threads of the block (Algorithm 2) k
 constexpr int kVjpWaves = 4;             // wavefronts per workgroup of the block reverse kernel,
 constexpr int kVjpWavesLds = 2;          // or this many where four wavefronts' staging does not fit the LDS
 constexpr int kFwdWaves = 4;             // wavefronts per workgroup of the block forward kernel
-constexpr int kFwdChunk = 384;           // own entries of one of its (lattice point, row chunk) units
+constexpr int kFwdChunk = 448;           // own entries of one of its (lattice point, row chunk) units,
+constexpr int kFwdChunkSmall = 192;      // on levels with fewer than kSmallLevelUnits units
 constexpr int kNodeStride = 3 * kMaxD;   // ints per node record: m, rank(m - 1_j), rank(m + 1_j)
 constexpr int kPointBatch = 32;          // Abar records per LDS staging batch, point reverse kernel
 constexpr int kBlockBatch = 32;          // the same, block reverse kernel

@@ -43,10 +43,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_point(DevPlan P, LevelPtrs<R> 
 }
 
 // Algorithm 2: one workgroup of WV wavefronts per (lattice point, chunk of
-// undetected rows).  Chunks of about 96 entries per wavefront over four
+// undetected rows).  Chunks of about 112 entries per wavefront over four
 // wavefronts leave fewer rows to the halo than one-wavefront chunks (the
-// 5-mode conditional forward sweep 2.29 -> 1.77 ms, the 4-mode one 0.45 ->
-// 0.39 ms, the 6-mode gradient circuit 4.61 -> 4.32 ms).
+// 5-mode conditional forward sweep 2.29 -> 1.78 ms, the 4-mode one 0.45 ->
+// 0.40 ms, the 6-mode gradient circuit 4.61 -> 3.75 ms).
 // E = dual<R> carries every amplitude's tangent along (forward mode), dT
 // bytes after the value.  ST: the rows stream from HBM (blocks whose rows do
 // not fit the LDS); the bridge pivot blocks then go to the workgroup's slot

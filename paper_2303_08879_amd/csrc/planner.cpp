@@ -411,13 +411,13 @@ size_t vjp_lds_bytes_for(const Plan& Pl, const ChunkGeo& G) {
 }
 
 // Chunk geometry of a forward level with nwork lattice points (its units
-// span kFwdWaves wavefronts): about kFwdChunk own entries, half-height chunks
-// on levels with few units, and the one-wavefront heights where the taller
+// span kFwdWaves wavefronts): about kFwdChunk own entries, kFwdChunkSmall on
+// levels with few units, and the one-wavefront heights where the taller
 // chunk's rows do not fit the LDS (those fit whenever the plan's rows are not
 // streamed).
 ChunkGeo fwd_geo(const Plan& Pl, int64_t nwork) {
   ChunkGeo G = chunk_geo(Pl, kFwdChunk);
-  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kFwdChunk / 2);
+  if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kFwdChunkSmall);
   if (fwd_lds_bytes_for(Pl, G) <= kMaxLds) return G;
   G = chunk_geo(Pl, kBT);
   if (nwork * G.nchunks < kSmallLevelUnits) G = chunk_geo(Pl, kBT / 2);
