@@ -55,8 +55,8 @@ def workload(name):
 # Sources each level kernel is compiled from: a counter summary applies to a
 # kernel only while these hash to the value recorded with it.
 KERNEL_SOURCES = {
-    "k_vjp_point": ["kernels_vjp.hip", "fd_device.h"],
-    "k_vjp_block": ["kernels_vjp.hip", "fd_device.h"],
+    "k_vjp_point": ["kernels_vjp.hip", "vjp_common.h", "fd_device.h"],
+    "k_vjp_block": ["kernels_vjp_block.hip", "vjp_common.h", "fd_device.h"],
     "k_fwd_point": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
     "k_fwd_block": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
     "k_state_level": ["kernels_state.hip", "fd_device.h"],

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfockdiag.so")
-SOURCES = ["planner.cpp", "abi.cpp", "kernels_fwd.hip", "kernels_vjp.hip", "kernels_batch.hip", "kernels_state.hip",
+SOURCES = ["planner.cpp", "abi.cpp", "kernels_fwd.hip", "kernels_vjp.hip", "kernels_vjp_block.hip", "kernels_batch.hip", "kernels_state.hip",
            "kernels_batch_md6.hip", "kernels_batch_md8.hip", "scratch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
