@@ -29,23 +29,28 @@ struct VjpPtrs {
 // runs NB / 4 FP64 MFMA 16x16x4 steps of four records: lane t feeds value
 // t % 16 of record k0 + t / 16 to both operands (one 16-byte LDS read each)
 // and keeps D[4 j + t / 16][16 c + t % 16], j = 0..3, of column tile c in its
-// accumulators (the gfx950 output layout, checked on the device).  Real part
-// Hr Xr + Hi Xi, imaginary part Hi Xr - Hr Xi.  The hardware fixes the order
-// of accumulation, so the sums are reproducible.  At most 16 rows of H
-// (NPD) and 32 columns of X (NCOL).
+// accumulators (the gfx950 output layout, checked on the device).  The
+// complex products take three real products (Karatsuba's method):
+// P1 = Hr Xr, P2 = Hi Xi, P3 = (Hr + Hi)(Xr - Xi), each summed in its own
+// accumulator; the real part is P1 + P2 and the imaginary part (Hi Xr -
+// Hr Xi) is P3 - P1 + P2.  Three MFMAs per step instead of four, and three
+// independent accumulation chains of one MFMA per step instead of two of
+// two.  The hardware fixes the order of accumulation, so the sums are
+// reproducible.  At most 16 rows of H (NPD) and 32 columns of X (NCOL).
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
 template <int NT>
 struct MfmaAcc {
-  mfma_d4 re[NT], im[NT];
+  mfma_d4 p1[NT], p2[NT], p3[NT];
 };
 
 template <int NT>
 __device__ __forceinline__ void mfma_acc_zero(MfmaAcc<NT>& a) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    a.re[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-    a.im[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    a.p1[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    a.p2[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    a.p3[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
   }
 }
 
@@ -60,16 +65,15 @@ __device__ __forceinline__ void wave_accum_mfma(const cx<R>* recw, MfmaAcc<(NCOL
   for (int k0 = 0; k0 < NB; k0 += 4) {
     const int rc = k0 + kq;
     const cx<R> h = row < NPD ? recw[row * RS + rc] : czero<R>();
-    const double hx = (double)h.x, hy = (double)h.y;
+    const double hx = (double)h.x, hy = (double)h.y, hs = hx + hy;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = 16 * t + row;
       const cx<R> x = col < NCOL ? recw[(NPD + col) * RS + rc] : czero<R>();
       const double xx = (double)x.x, xy = (double)x.y;
-      acc.re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hx, xx, acc.re[t], 0, 0, 0);
-      acc.im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hy, xx, acc.im[t], 0, 0, 0);
-      acc.re[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hy, xy, acc.re[t], 0, 0, 0);
-      acc.im[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-hx, xy, acc.im[t], 0, 0, 0);
+      acc.p1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hx, xx, acc.p1[t], 0, 0, 0);
+      acc.p2[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hy, xy, acc.p2[t], 0, 0, 0);
+      acc.p3[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hs, xx - xy, acc.p3[t], 0, 0, 0);
     }
   }
 }
@@ -87,7 +91,10 @@ __device__ __forceinline__ void mfma_acc_store(const MfmaAcc<(NCOL + 15) / 16>& 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int i = 4 * j + kq;
-      if (i < NPD && l < NCOL) red[i * NR + l] = cmake<double>(acc.re[t][j], acc.im[t][j]);
+      if (i < NPD && l < NCOL) {
+        const double p1 = acc.p1[t][j], p2 = acc.p2[t][j];
+        red[i * NR + l] = cmake<double>(p1 + p2, (acc.p3[t][j] - p1) + p2);
+      }
     }
   }
 }
