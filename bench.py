@@ -60,6 +60,8 @@ KERNEL_SOURCES = {
     "k_fwd_point": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
     "k_fwd_block": ["kernels_fwd.hip", "fwd_units.h", "fd_device.h"],
     "k_state_level": ["kernels_state.hip", "fd_device.h"],
+    "k_state_jvp": ["kernels_state.hip", "fd_device.h"],
+    "k_state_vjp": ["kernels_state.hip", "fd_device.h"],
 }
 
 
@@ -517,6 +519,24 @@ def state_leg(steps=20):
         F.fock_state_jvp(plan, c, psi, tA, tb, tc, dpsi)
     torch.cuda.synchronize()
     sec_j = time.perf_counter() - t3
+    # the derivative kernels alone, HIP events around each launch
+    F.fd_state_plan_timing(plan, (1 << F.FD_K_FWD_LEVEL) | (1 << F.FD_K_VJP_LEVEL))
+    for _ in range(steps):
+        F.fock_state_vjp(plan, c, psi, g, dA, db, dc, vws)
+        F.fock_state_jvp(plan, c, psi, tA, tb, tc, dpsi)
+    torch.cuda.synchronize()
+    nv, ms_v = F.fd_state_plan_kernel_times(plan, F.FD_K_VJP_LEVEL)
+    nj, ms_j = F.fd_state_plan_kernel_times(plan, F.FD_K_FWD_LEVEL)
+    F.fd_state_plan_timing(plan, 0)
+
+    def deriv_roofline(kernel, n, ms, amps):
+        # 32 B per amplitude: two complex128 streams (psi and the cotangent
+        # read, or psi read and the tangent written), each entry once
+        us = 1e3 * ms / max(n, 1)
+        gbs = 32.0 * amps / (us * 1e-6) / 1e9
+        return {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "avg_launch_us": round(us, 3),
+                "algorithmic_bytes_per_launch": 32 * amps, "traffic": measured_traffic("state8", kernel)}
     N = level_counts(ci.cutoffs)
     smax = len(N) - 1
     alg = sum(16 * (N[S] + N[S - 1] + N[S - 2]) for S in range(2, smax + 1, 2))
@@ -538,12 +558,16 @@ def state_leg(steps=20):
                           "traffic": measured_traffic("state8", "k_state_level")},
                 norm2=float((psi.abs() ** 2).sum()),
                 vjp={"ms_per_call": 1e3 * sec_v / steps,
-                     "note": "the 45 cotangent dot products (8 of b, 36 of the symmetric A, 1 of c) over the box",
+                     "note": "the 45 cotangent dot products (8 of b, 36 of the symmetric A, 1 of c) over the box, "
+                             "one tiled pass plus the final slot sums",
                      "algorithmic_GBs": round(32 * amps * steps / sec_v / 1e9, 1),
-                     "algorithmic_bytes": "32 B per amplitude: the cotangent and psi read once"},
+                     "algorithmic_bytes": "32 B per amplitude: the cotangent and psi read once",
+                     "roofline": deriv_roofline("k_state_vjp", nv, ms_v, amps)},
                 jvp={"ms_per_call": 1e3 * sec_j / steps, "launches": 1,
-                     "note": "one pass: reads psi (and its shifted neighbours), writes the tangent: 32 B per amplitude",
-                     "algorithmic_GBs": round(32 * amps * steps / sec_j / 1e9, 1)})
+                     "note": "one tiled pass: reads psi (and its shifted neighbours), writes the tangent: "
+                             "32 B per amplitude",
+                     "algorithmic_GBs": round(32 * amps * steps / sec_j / 1e9, 1),
+                     "roofline": deriv_roofline("k_state_jvp", nj, ms_j, amps)})
 
 
 def total_leg(steps=20, N=16, eps=0.05):

@@ -126,30 +126,69 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
 }
 
 // ---------------------------------------------------------------------------
-// Reverse mode.  The local gradients of Sec. 2.5 (the solutions of its
-// tangent recurrences for b and A) have closed forms in the amplitudes:
+// Derivatives.  The local gradients of Sec. 2.5 (the solutions of its tangent
+// recurrences for b and A) have closed forms in the amplitudes:
 //   d psi_k / d b_i   = sqrt(k_i) psi_{k - 1_i},
 //   d psi_k / d A_il  = 1/2 sqrt(k_i (k_l - [i = l])) psi_{k - 1_i - 1_l},
 //   d psi_k / d c     = psi_k / c,
-// and every shifted amplitude lies inside the box, so the cotangents
-//   bbar_i = sum_k g_k conj(d psi_k / d b_i)   (g = dL/dpsi^*, Eqs. dL_dB, dL_dA)
-// are weighted dot products of g with shifted copies of psi.  One launch
-// accumulates up to kVjpGroup of them; each thread sums its indices in
-// order, the workgroup folds its threads in a fixed tree into its slot, and
-// the final kernel adds the slots in order (bitwise reproducible).
+// and every shifted amplitude lies inside the box.  Reverse mode: the
+// cotangents bbar_i = sum_k g_k conj(d psi_k / d b_i) (g = dL/dpsi^*, Eqs.
+// dL_dB, dL_dA) are weighted dot products of g with shifted copies of psi.
+// Forward mode: the tangent along (dA, db, dc) is
+//   dpsi_k = (dc / c) psi_k + sum_i db_i sqrt(k_i) psi_{k-1_i}
+//          + sum_{i <= l} S_il w_il(k) psi_{k-1_i-1_l},
+// S_il = dA_il + dA_li (i < l), dA_ii (i = l), w_il the weight above: the
+// directional derivative for the symmetric part of dA, as A enters through
+// (A + A^T)/2.
+//
+// Both kernels walk psi (C order, last kept mode fastest) by tiles: the
+// trailing modes sp..MD-1 span a tile of T = prod_{d >= sp} C_d entries (at
+// most the kernel's tile size) and the leading modes number the tiles, so entry x is
+// entry x mod T of tile x / T.  A shifted amplitude of a tile-t entry lies in
+// tile t (every mode of the shift trailing), in tile t - 1_i (one leading
+// mode i) or in tile t - 1_i - 1_l (two leading modes).  A workgroup stages
+// tile t in LDS and serves the terms of the first kind from it, then stages
+// tile t - 1_i for each leading i with k_i >= 1 and serves the terms whose
+// leading part is 1_i, reading the one amplitude of each two-leading-mode
+// term straight from memory.  Each psi entry is so read 1 + (leading modes)
+// + (leading pairs) times instead of once per term, and the tile order keeps
+// those re-reads in cache: workgroup v runs on XCD v mod 8 and visits tile
+// (v mod 8) * ntiles/8 + v / 8, so every XCD walks one contiguous range of
+// tiles in order and finds tiles t - 1_i of the faster leading modes in its
+// own L2.
 // ---------------------------------------------------------------------------
-constexpr int kVjpTerms = kMaxD + kMaxD * (kMaxD + 1) / 2 + 1;   // bbar, Abar (i <= l), c
+// Tile geometry of each kernel (entries per tile, entries per lane, lanes per
+// workgroup): the forward mode stages 64 KB tiles in sixteen-wavefront
+// workgroups, the reverse mode 8 KB tiles in one-wavefront workgroups (the faster of the two shapes for each on the 8-mode cutoff-8
+// state).
+constexpr int kJvpTile = 4096, kJvpEPT = 4, kJvpThreads = kJvpTile / kJvpEPT;
+constexpr int kVjpTile = 512, kVjpEPT = 8, kVjpThreads = kVjpTile / kVjpEPT;
+constexpr int kVjpCols = kMaxD + kMaxD * (kMaxD + 1) / 2 + 1;   // bbar, Abar (i <= l), c
 
-// The terms; mode i of term t has C-order stride si[t] and cutoff ci[t] (the
-// same for l), with their reciprocals for the exact double-reciprocal digit
-// split.
-struct StateVjpTerms {
-  int n;                    // terms (ncol)
-  int col[kVjpTerms];       // output column of each term
-  int kind[kVjpTerms];      // 0: bbar_i, 1: Abar_il (i < l), 2: Abar_ii, 3: sum g conj(psi)
-  int si[kVjpTerms], ci[kVjpTerms], sl[kVjpTerms], cl[kVjpTerms];
-  double inv_si[kVjpTerms], inv_ci[kVjpTerms], inv_sl[kVjpTerms], inv_cl[kVjpTerms];
+struct StateTiles {
+  int MD, sp, T, ntiles;
+  int C[kMaxD], stride[kMaxD];   // kept cutoffs, C-order strides
+  double inv_stride[kMaxD], inv_c[kMaxD];
 };
+
+static StateTiles state_tiles(const Plan& Pl, int max_tile) {
+  StateTiles G;
+  std::memset(&G, 0, sizeof(G));
+  G.MD = Pl.MD;
+  int64_t s = 1;
+  for (int d = Pl.MD - 1; d >= 0; --d) {
+    G.C[d] = Pl.CD[d];
+    G.stride[d] = (int)s;
+    G.inv_stride[d] = 1.0 / (double)s;
+    G.inv_c[d] = 1.0 / (double)Pl.CD[d];
+    s *= Pl.CD[d];
+  }
+  G.sp = Pl.MD;
+  G.T = 1;
+  while (G.sp > 0 && G.T * Pl.CD[G.sp - 1] <= max_tile) G.T *= Pl.CD[--G.sp];
+  G.ntiles = (int)(s / G.T);
+  return G;
+}
 
 // Digit (x / stride) mod C of a C-order index x < 2^31: (x + 1/2) / stride
 // lies at least 1 / (2 stride) from an integer and the rounded product is off
@@ -159,58 +198,345 @@ __device__ __forceinline__ int cdigit(int x, int stride, int c, double inv_strid
   return q - c * (int)((q + 0.5) * inv_c);
 }
 
-// One workgroup per (chunk of `len` consecutive indices, term): the term is
-// uniform, so each lane keeps one accumulator, the g and shifted psi reads
-// of a wavefront are consecutive addresses, and the term's workgroups of one
-// chunk run together (term fastest in the grid) and share the chunk's g in
-// L2.  Each lane sums its indices in order, the workgroup folds its lanes in
-// a fixed tree into slot (chunk, column); the final kernel adds the slots of
-// a column in order (bitwise reproducible).
+// The tile of visit v (see above); in order when the tiles do not split into
+// eight equal ranges.
+__device__ __forceinline__ int state_tile_of(int ntiles, int v) {
+  return (ntiles & 7) ? v : (v & 7) * (ntiles >> 3) + (v >> 3);
+}
+
+// Loads tile entries [src, src + T) of this lane (entry f = lane + e * lanes)
+// into registers, every load issued before the first is waited on.
+template <int NT, int EPT, typename R>
+__device__ __forceinline__ void load_lane_entries(cx<R> (&v)[EPT], const cx<R>* __restrict__ src, int T) {
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int f = threadIdx.x + e * NT;
+    v[e] = f < T ? ld(src + f) : czero<R>();
+  }
+}
+
+// Stages tile entries [src, src + T) in LDS (loads first, then the writes).
+template <int NT, int EPT, typename R>
+__device__ __forceinline__ void stage_tile(cx<R>* buf, const cx<R>* __restrict__ src, int T) {
+  cx<R> v[EPT];
+  load_lane_entries<NT, EPT>(v, src, T);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int f = threadIdx.x + e * NT;
+    if (f < T) buf[f] = v[e];
+  }
+}
+
+// acc += (w s) p for a double coefficient s and an amplitude p.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_state_vjp_terms(const cx<R>* __restrict__ psi,
-                                                              const cx<R>* __restrict__ g, int total, int len,
-                                                              StateVjpTerms T, double2* __restrict__ slots) {
-  __shared__ double2 red[kThreads];
-  __shared__ double sq[kMaxCut + 1];   // sqrt(0..64)
-  for (int v = threadIdx.x; v <= kMaxCut; v += blockDim.x) sq[v] = sqrt((double)v);
+__device__ __forceinline__ void cmac_w(double& ax, double& ay, double w, double2 s, const cx<R>& p) {
+  const double sx = w * s.x, sy = w * s.y;
+  ax += sx * (double)p.x - sy * (double)p.y;
+  ay += sx * (double)p.y + sy * (double)p.x;
+}
+
+template <typename R>
+size_t state_jvp_lds_bytes() {
+  return (size_t)kJvpTile * sizeof(cx<R>) + (kMaxD * kMaxD + kMaxD) * sizeof(double2) +
+         (kMaxCut + 1) * sizeof(double) + kMaxD * sizeof(int);
+}
+
+// Forward mode: one workgroup per tile, kJvpEPT entries per lane, the
+// tangent accumulated in registers over the tile's phases; the modes are a
+// template argument, so the term loops unroll with the strides in scalar
+// registers.
+template <int MD, typename R>
+__global__ __launch_bounds__(kJvpThreads) void k_state_jvp(
+    StateTiles G, StateModes sm, int M, const cx<R>* __restrict__ psi, const cx<R>* __restrict__ c,
+    const cx<R>* __restrict__ tA, const cx<R>* __restrict__ tb, const cx<R>* __restrict__ tc,
+    cx<R>* __restrict__ dpsi) {
+  constexpr int MDA = MD > 0 ? MD : 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+  double2* sS = reinterpret_cast<double2*>(smem_raw + (size_t)kJvpTile * sizeof(cx<R>));   // kMaxD x kMaxD
+  double2* sB = sS + kMaxD * kMaxD;
+  double* sq = reinterpret_cast<double*>(sB + kMaxD);   // sqrt(0..kMaxCut)
+  int* ks = reinterpret_cast<int*>(sq + kMaxCut + 1);  // leading digits of the tile
+  const int sp = G.sp, T = G.T;
+  for (int v = threadIdx.x; v <= kMaxCut; v += kJvpThreads) sq[v] = sqrt((double)v);
+  for (int e = threadIdx.x; e < MD * MD; e += kJvpThreads) {
+    const int i = e / MD, l = e % MD;
+    const cx<R> a = ld(tA + (size_t)sm.mode[i] * M + sm.mode[l]);
+    const cx<R> t = ld(tA + (size_t)sm.mode[l] * M + sm.mode[i]);
+    sS[i * kMaxD + l] = i == l ? make_double2(a.x, a.y) : make_double2((double)a.x + t.x, (double)a.y + t.y);
+  }
+  for (int i = threadIdx.x; i < MD; i += kJvpThreads) {
+    const cx<R> v = ld(tb + sm.mode[i]);
+    sB[i] = make_double2(v.x, v.y);
+  }
+  const int x0 = state_tile_of(G.ntiles, blockIdx.x) * T;
+  for (int d = threadIdx.x; d < sp; d += kJvpThreads)
+    ks[d] = cdigit(x0, G.stride[d], G.C[d], G.inv_stride[d], G.inv_c[d]);
+  stage_tile<kJvpThreads, kJvpEPT>(buf, psi + x0, T);
   __syncthreads();
-  const int term = (int)(blockIdx.x % (unsigned)T.n), chunk = (int)(blockIdx.x / (unsigned)T.n);
-  const int kind = T.kind[term];
-  const int si = T.si[term], ci = T.ci[term], sl = T.sl[term], cl = T.cl[term];
-  const double isi = T.inv_si[term], ici = T.inv_ci[term], isl = T.inv_sl[term], icl = T.inv_cl[term];
-  const int shift = kind == 0 ? si : kind == 1 ? si + sl : kind == 2 ? 2 * si : 0;
-  const int x0 = chunk * len, x1 = min(total, x0 + len);
-  double ax = 0.0, ay = 0.0;
-  for (int x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-    double w = 1.0;
-    if (kind != 3) {
-      const int ki = cdigit(x, si, ci, isi, ici);
-      if (kind == 0) {
-        w = sq[ki];
-      } else if (kind == 1) {
-        w = 0.5 * sq[ki] * sq[cdigit(x, sl, cl, isl, icl)];
-      } else {
-        w = ki >= 2 ? 0.5 * sq[ki] * sq[ki - 1] : 0.0;
+  // dc / c
+  const cx<R> cv = ld(c), dv = ld(tc);
+  const double n2 = (double)cv.x * cv.x + (double)cv.y * cv.y;
+  const double2 r = make_double2(((double)dv.x * cv.x + (double)dv.y * cv.y) / n2,
+                                 ((double)dv.y * cv.x - (double)dv.x * cv.y) / n2);
+  double ax[kJvpEPT], ay[kJvpEPT];
+  // terms inside tile t: dc/c, db_i and the pairs of trailing modes
+#pragma unroll
+  for (int e = 0; e < kJvpEPT; ++e) {
+    const int f = threadIdx.x + e * kJvpThreads;
+    ax[e] = 0.0;
+    ay[e] = 0.0;
+    if (f >= T) continue;
+    int k[MDA];
+#pragma unroll
+    for (int d = 0; d < MD; ++d) k[d] = d >= sp ? cdigit(f, G.stride[d], G.C[d], G.inv_stride[d], G.inv_c[d]) : 0;
+    double x = 0.0, y = 0.0;
+    cmac_w(x, y, 1.0, r, buf[f]);
+#pragma unroll
+    for (int i = 0; i < MD; ++i) {
+      if (i < sp || k[i] < 1) continue;
+      const int fi = f - G.stride[i];
+      const double wi = sq[k[i]];
+      cmac_w(x, y, wi, sB[i], buf[fi]);
+#pragma unroll
+      for (int l = i; l < MD; ++l) {
+        const int kl = k[l] - (l == i ? 1 : 0);
+        if (kl < 1) continue;
+        cmac_w(x, y, 0.5 * wi * sq[kl], sS[i * kMaxD + l], buf[fi - G.stride[l]]);
       }
     }
-    if (w != 0.0) {   // else the shifted amplitude is outside the box
-      const cx<R> gv = ld(g + x), pv = ld(psi + (x - shift));
-      // g * conj(w psi_y)
-      const double px = w * (double)pv.x, py = w * (double)pv.y;
-      ax += (double)gv.x * px + (double)gv.y * py;
-      ay += (double)gv.y * px - (double)gv.x * py;
+    ax[e] = x;
+    ay[e] = y;
+  }
+  // terms whose leading part is 1_i: tile t - 1_i (uniform over the workgroup)
+#pragma unroll
+  for (int i = 0; i < MD; ++i) {
+    if (i >= sp) continue;
+    const int ki = ks[i];
+    if (ki < 1) continue;
+    const int xs = x0 - G.stride[i];
+    __syncthreads();
+    stage_tile<kJvpThreads, kJvpEPT>(buf, psi + xs, T);
+    __syncthreads();
+    const double wi = sq[ki];
+#pragma unroll
+    for (int e = 0; e < kJvpEPT; ++e) {
+      const int f = threadIdx.x + e * kJvpThreads;
+      if (f >= T) continue;
+      int k[MDA];
+#pragma unroll
+      for (int d = 0; d < MD; ++d) k[d] = d >= sp ? cdigit(f, G.stride[d], G.C[d], G.inv_stride[d], G.inv_c[d]) : 0;
+      double x = ax[e], y = ay[e];
+      cmac_w(x, y, wi, sB[i], buf[f]);
+#pragma unroll
+      for (int l = i + 1; l < MD; ++l) {
+        if (l < sp || k[l] < 1) continue;
+        cmac_w(x, y, 0.5 * wi * sq[k[l]], sS[i * kMaxD + l], buf[f - G.stride[l]]);
+      }
+      ax[e] = x;
+      ay[e] = y;
+    }
+    // two leading modes: one amplitude per entry from memory
+#pragma unroll
+    for (int l = i; l < MD; ++l) {
+      if (l >= sp) continue;
+      const int kl = ks[l] - (l == i ? 1 : 0);
+      if (kl < 1) continue;
+      cx<R> p[kJvpEPT];
+      load_lane_entries<kJvpThreads, kJvpEPT>(p, psi + (xs - G.stride[l]), T);
+      const double w = 0.5 * wi * sq[kl];
+      const double2 sc = sS[i * kMaxD + l];
+#pragma unroll
+      for (int e = 0; e < kJvpEPT; ++e) cmac_w(ax[e], ay[e], w, sc, p[e]);
     }
   }
-  red[threadIdx.x] = make_double2(ax, ay);
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[threadIdx.x].x += red[threadIdx.x + w].x;
-      red[threadIdx.x].y += red[threadIdx.x + w].y;
+#pragma unroll
+  for (int e = 0; e < kJvpEPT; ++e) {
+    const int f = threadIdx.x + e * kJvpThreads;
+    if (f < T) st(dpsi + x0 + f, cmake<R>((R)ax[e], (R)ay[e]));
+  }
+}
+
+// Column of each cotangent: bbar_i (i), Abar_il for i <= l (MD + the upper
+// triangle row by row), sum g conj(psi) (last).
+__host__ __device__ __forceinline__ int vjp_col_pair(int MD, int i, int l) { return MD + i * MD - i * (i - 1) / 2 + (l - i); }
+
+template <typename R>
+size_t state_vjp_lds_bytes() {
+  return (size_t)kVjpTile * sizeof(cx<R>) + (size_t)(kVjpThreads / 64) * kVjpCols * sizeof(double2) +
+         (kMaxCut + 1) * sizeof(double) + 2 * kMaxD * sizeof(int);
+}
+
+// Adds the wavefront's sum of (sx, sy) to *dst (a fixed butterfly, lane 0
+// writes: bitwise reproducible).
+__device__ __forceinline__ void wave_sum_into(double2* dst, double sx, double sy) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o);
+    sy += __shfl_xor(sy, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    dst->x += sx;
+    dst->y += sy;
+  }
+  // one term at a time: the scheduler keeps the next term's LDS reads behind
+  // this one (interleaving them only raises the register count)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// sum over e of g_e conj(w_e p_e)
+template <typename R>
+__device__ __forceinline__ void dot_acc(double& sx, double& sy, double w, double gx, double gy, const cx<R>& p) {
+  const double px = w * (double)p.x, py = w * (double)p.y;
+  sx += gx * px + gy * py;
+  sy += gy * px - gx * py;
+}
+
+// Reverse mode: workgroup w visits tiles w, w + grid, ... (grid a multiple of
+// 8, so every visit of a workgroup stays on its XCD's range), each lane
+// holding the cotangent of its kVjpEPT entries; per term the lanes sum
+// their entries in order, each wavefront folds its lanes into its own LDS
+// row, and at the end the workgroup adds its wavefront rows in order into
+// slot (workgroup, column); the final kernel adds the slots of a column in
+// order (bitwise reproducible).  Terms are walked by runtime loops over the
+// modes, one term at a time (unrolled over the modes, the per-entry weights
+// of every mode stay live and the register count grows with the modes).
+template <typename R>
+__global__ __launch_bounds__(kVjpThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_state_vjp(StateTiles G, const cx<R>* psi,
+                                                             const cx<R>* __restrict__ g, double2* __restrict__ slots) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+  double2* red = reinterpret_cast<double2*>(smem_raw + (size_t)kVjpTile * sizeof(cx<R>));   // waves x kVjpCols
+  double* sq = reinterpret_cast<double*>(red + (kVjpThreads / 64) * kVjpCols);
+  int* ks = reinterpret_cast<int*>(sq + kMaxCut + 1);   // leading digits of the tile
+  int* sst = ks + kMaxD;                                  // C-order strides
+  const int MD = G.MD, sp = G.sp, T = G.T;
+  const int ncol = MD + MD * (MD + 1) / 2 + 1;
+  for (int v = threadIdx.x; v <= kMaxCut; v += kVjpThreads) sq[v] = sqrt((double)v);
+  for (int p = threadIdx.x; p < (kVjpThreads / 64) * kVjpCols; p += kVjpThreads) red[p] = make_double2(0.0, 0.0);
+  if (threadIdx.x < kMaxD) sst[threadIdx.x] = G.stride[threadIdx.x];
+  double2* wred = red + (threadIdx.x >> 6) * kVjpCols;
+  // trailing digits of this lane's tile entries (the same in every tile), 6
+  // bits per mode; an entry beyond the tile gets digit 0 everywhere, which
+  // zeroes every shifted term
+  uint64_t kp[kVjpEPT];
+#pragma unroll
+  for (int e = 0; e < kVjpEPT; ++e) {
+    const int f = threadIdx.x + e * kVjpThreads;
+    uint64_t p = 0;
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d)
+      if (f < T && d >= sp && d < MD)
+        p |= (uint64_t)cdigit(f, G.stride[d], G.C[d], G.inv_stride[d], G.inv_c[d]) << (6 * d);
+    kp[e] = p;
+  }
+  auto digit = [](uint64_t p, int d) { return (int)((p >> (6 * d)) & 63); };
+  for (int v = blockIdx.x; v < G.ntiles; v += gridDim.x) {
+    const int x0 = state_tile_of(G.ntiles, v) * T;
+    __syncthreads();   // the previous tile's LDS reads are done
+    if (threadIdx.x < sp) ks[threadIdx.x] = cdigit(x0, G.stride[threadIdx.x], G.C[threadIdx.x],
+                                                   G.inv_stride[threadIdx.x], G.inv_c[threadIdx.x]);
+    cx<R> gv[kVjpEPT];
+    load_lane_entries<kVjpThreads, kVjpEPT>(gv, g + x0, T);
+    stage_tile<kVjpThreads, kVjpEPT>(buf, psi + x0, T);
+    double gx[kVjpEPT], gy[kVjpEPT];
+#pragma unroll
+    for (int e = 0; e < kVjpEPT; ++e) {
+      gx[e] = (double)gv[e].x;
+      gy[e] = (double)gv[e].y;
     }
     __syncthreads();
+    // terms inside tile t
+    {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int e = 0; e < kVjpEPT; ++e) {
+        const int f = threadIdx.x + e * kVjpThreads;
+        if (f < T) dot_acc(sx, sy, 1.0, gx[e], gy[e], buf[f]);
+      }
+      wave_sum_into(wred + ncol - 1, sx, sy);
+    }
+#pragma unroll 1
+    for (int i = sp; i < MD; ++i) {
+      const int si = sst[i];
+      {
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int e = 0; e < kVjpEPT; ++e) {
+          const int f = threadIdx.x + e * kVjpThreads;
+          const int ki = digit(kp[e], i);
+          if (ki >= 1) dot_acc(sx, sy, sq[ki], gx[e], gy[e], buf[f - si]);
+        }
+        wave_sum_into(wred + i, sx, sy);
+      }
+#pragma unroll 1
+      for (int l = i; l < MD; ++l) {
+        const int sil = si + sst[l];
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int e = 0; e < kVjpEPT; ++e) {
+          const int f = threadIdx.x + e * kVjpThreads;
+          const int ki = digit(kp[e], i), kl = digit(kp[e], l) - (l == i ? 1 : 0);
+          if (ki >= 1 && kl >= 1) dot_acc(sx, sy, 0.5 * sq[ki] * sq[kl], gx[e], gy[e], buf[f - sil]);
+        }
+        wave_sum_into(wred + vjp_col_pair(MD, i, l), sx, sy);
+      }
+    }
+    // terms whose leading part is 1_i: tile t - 1_i
+#pragma unroll 1
+    for (int i = 0; i < sp; ++i) {
+      const int ki = ks[i];
+      if (ki < 1) continue;   // uniform
+      const int xs = x0 - sst[i];
+      __syncthreads();
+      stage_tile<kVjpThreads, kVjpEPT>(buf, psi + xs, T);
+      __syncthreads();
+      const double wi = sq[ki];
+      {
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int e = 0; e < kVjpEPT; ++e) {
+          const int f = threadIdx.x + e * kVjpThreads;
+          if (f < T) dot_acc(sx, sy, wi, gx[e], gy[e], buf[f]);
+        }
+        wave_sum_into(wred + i, sx, sy);
+      }
+#pragma unroll 1
+      for (int l = sp; l < MD; ++l) {
+        const int sl = sst[l];
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int e = 0; e < kVjpEPT; ++e) {
+          const int f = threadIdx.x + e * kVjpThreads;
+          const int kl = digit(kp[e], l);
+          if (kl >= 1) dot_acc(sx, sy, 0.5 * wi * sq[kl], gx[e], gy[e], buf[f - sl]);
+        }
+        wave_sum_into(wred + vjp_col_pair(MD, i, l), sx, sy);
+      }
+      // two leading modes: one amplitude per entry from memory
+#pragma unroll 1
+      for (int l = i; l < sp; ++l) {
+        const int kl = ks[l] - (l == i ? 1 : 0);
+        if (kl < 1) continue;   // uniform
+        cx<R> p[kVjpEPT];
+        load_lane_entries<kVjpThreads, kVjpEPT>(p, psi + (xs - sst[l]), T);
+        const double w = 0.5 * wi * sq[kl];
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int e = 0; e < kVjpEPT; ++e) dot_acc(sx, sy, w, gx[e], gy[e], p[e]);
+        wave_sum_into(wred + vjp_col_pair(MD, i, l), sx, sy);
+      }
+    }
   }
-  if (threadIdx.x == 0) slots[(size_t)chunk * T.n + T.col[term]] = red[0];
+  __syncthreads();
+  for (int p = threadIdx.x; p < ncol; p += kVjpThreads) {
+    double sx = 0.0, sy = 0.0;
+    for (int wv = 0; wv < kVjpThreads / 64; ++wv) {
+      sx += red[wv * kVjpCols + p].x;
+      sy += red[wv * kVjpCols + p].y;
+    }
+    slots[(size_t)blockIdx.x * ncol + p] = make_double2(sx, sy);
+  }
 }
 
 // One workgroup per caller entry of dA (M x M), db (M), dc: the slots of its
@@ -272,75 +598,35 @@ __global__ __launch_bounds__(kThreads) void k_state_vjp_final(StateVjpMap m, con
   }
 }
 
-// Forward mode: the tangent of psi along (dA, db, dc), from the same closed
-// forms, one thread per amplitude:
-//   dpsi_k = (dc / c) psi_k + sum_i db_i sqrt(k_i) psi_{k-1_i}
-//          + sum_{i <= l} S_il w_il(k) psi_{k-1_i-1_l},
-// S_il = dA_il + dA_li (i < l), dA_ii (i = l), w_il = 1/2 sqrt(k_i k_l) or
-// 1/2 sqrt(k_i (k_i - 1)): the directional derivative for the symmetric part
-// of dA, as A enters through (A + A^T)/2.
+template <int MD, typename R>
+static void launch_state_jvp(const StateTiles& G, const StateModes& sm, int M, const void* psi, const void* c,
+                             const void* dA, const void* db, const void* dc, void* dpsi, hipStream_t st) {
+  const size_t shm = state_jvp_lds_bytes<R>();
+  if (shm > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_state_jvp<MD, R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_state_jvp<MD, R>), dim3((unsigned)G.ntiles), dim3(kJvpThreads), shm, st, G, sm, M,
+                     static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(c), static_cast<const cx<R>*>(dA),
+                     static_cast<const cx<R>*>(db), static_cast<const cx<R>*>(dc), static_cast<cx<R>*>(dpsi));
+}
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_state_jvp(DevPlan P, StateModes sm, int M, const cx<R>* __restrict__ psi,
-                                                        const cx<R>* __restrict__ c, const cx<R>* __restrict__ tA,
-                                                        const cx<R>* __restrict__ tb, const cx<R>* __restrict__ tc,
-                                                        int total, cx<R>* __restrict__ dpsi) {
-  __shared__ double2 sS[kMaxD * kMaxD];
-  __shared__ double2 sB[kMaxD];
-  __shared__ double sq[kMaxCut + 1];   // sqrt(0..64)
-  const int MD = P.MD;
-  for (int v = threadIdx.x; v <= kMaxCut; v += blockDim.x) sq[v] = sqrt((double)v);
-  for (int e = threadIdx.x; e < MD * MD; e += blockDim.x) {
-    const int i = e / MD, l = e % MD;
-    const cx<R> a = ld(tA + (size_t)sm.mode[i] * M + sm.mode[l]);
-    const cx<R> t = ld(tA + (size_t)sm.mode[l] * M + sm.mode[i]);
-    sS[e] = i == l ? make_double2(a.x, a.y) : make_double2((double)a.x + t.x, (double)a.y + t.y);
+static hipError_t launch_state_jvp_md(const StateTiles& G, const StateModes& sm, int M, const void* psi,
+                                      const void* c, const void* dA, const void* db, const void* dc, void* dpsi,
+                                      hipStream_t st) {
+  switch (G.MD) {
+    case 0: launch_state_jvp<0, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 1: launch_state_jvp<1, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 2: launch_state_jvp<2, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 3: launch_state_jvp<3, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 4: launch_state_jvp<4, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 5: launch_state_jvp<5, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 6: launch_state_jvp<6, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 7: launch_state_jvp<7, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    case 8: launch_state_jvp<8, R>(G, sm, M, psi, c, dA, db, dc, dpsi, st); break;
+    default: return hipErrorInvalidValue;
   }
-  for (int i = threadIdx.x; i < MD; i += blockDim.x) {
-    const cx<R> v = ld(tb + sm.mode[i]);
-    sB[i] = make_double2(v.x, v.y);
-  }
-  __syncthreads();
-  // dc / c
-  const cx<R> cv = ld(c), dv = ld(tc);
-  const double n2 = (double)cv.x * cv.x + (double)cv.y * cv.y;
-  const double rx = ((double)dv.x * cv.x + (double)dv.y * cv.y) / n2, ry = ((double)dv.y * cv.x - (double)dv.x * cv.y) / n2;
-  int stride[kMaxD];
-  {
-    int s = 1;
-    for (int d = MD - 1; d >= 0; --d) {
-      stride[d] = s;
-      s *= P.CD[d];
-    }
-  }
-  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
-    int k[kMaxD];
-    int rem = x;
-    for (int d = MD - 1; d >= 0; --d) {
-      const int q = (int)((rem + 0.5) * P.cinv[d]);
-      k[d] = rem - q * P.CD[d];
-      rem = q;
-    }
-    const cx<R> p0 = ld(psi + x);
-    double ax = rx * p0.x - ry * p0.y, ay = rx * p0.y + ry * p0.x;
-    for (int i = 0; i < MD; ++i) {
-      if (k[i] < 1) continue;
-      const cx<R> p1 = ld(psi + x - stride[i]);
-      const double w = sq[k[i]];
-      const double2 t = sB[i];
-      ax += w * (t.x * p1.x - t.y * p1.y);
-      ay += w * (t.x * p1.y + t.y * p1.x);
-      for (int l = i; l < MD; ++l) {
-        const int kl = k[l] - (l == i ? 1 : 0);
-        if (kl < 1) continue;
-        const cx<R> p2 = ld(psi + x - stride[i] - stride[l]);
-        const double w2 = 0.5 * sq[k[i]] * sq[kl];
-        const double2 S = sS[i * MD + l];
-        ax += w2 * (S.x * p2.x - S.y * p2.y);
-        ay += w2 * (S.x * p2.y + S.y * p2.x);
-      }
-    }
-    st(dpsi + x, cmake<R>((R)ax, (R)ay));
-  }
+  return hipGetLastError();
 }
 
 hipError_t run_state_jvp(const Plan& Pl, const void* c, const void* psi, const void* dA, const void* db, const void* dc,
@@ -349,61 +635,25 @@ hipError_t run_state_jvp(const Plan& Pl, const void* c, const void* psi, const v
   std::memset(&sm, 0, sizeof(sm));
   sm.MD = Pl.MD;
   for (int k = 0; k < Pl.MD; ++k) sm.mode[k] = Pl.dmodes[k];
-  const DevPlan P = make_devplan(Pl, true);
-  const int total = (int)Pl.nodes_total;
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + kThreads - 1) / kThreads, 65536));
+  const StateTiles G = state_tiles(Pl, kJvpTile);
   KTimer kt(Pl, KK_FWD_LEVEL, st);
-  if (Pl.dt == FD_C64)
-    hipLaunchKernelGGL((k_state_jvp<float>), dim3(grid), dim3(kThreads), 0, st, P, sm, Pl.M,
-                       static_cast<const cx<float>*>(psi), static_cast<const cx<float>*>(c),
-                       static_cast<const cx<float>*>(dA), static_cast<const cx<float>*>(db),
-                       static_cast<const cx<float>*>(dc), total, static_cast<cx<float>*>(dpsi));
-  else
-    hipLaunchKernelGGL((k_state_jvp<double>), dim3(grid), dim3(kThreads), 0, st, P, sm, Pl.M,
-                       static_cast<const cx<double>*>(psi), static_cast<const cx<double>*>(c),
-                       static_cast<const cx<double>*>(dA), static_cast<const cx<double>*>(db),
-                       static_cast<const cx<double>*>(dc), total, static_cast<cx<double>*>(dpsi));
-  return hipGetLastError();
+  if (Pl.dt == FD_C64) return launch_state_jvp_md<float>(G, sm, Pl.M, psi, c, dA, db, dc, dpsi, st);
+  return launch_state_jvp_md<double>(G, sm, Pl.M, psi, c, dA, db, dc, dpsi, st);
 }
 
 template <typename R>
 static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi, const void* g, void* dA, void* db,
                                   void* dc, void* ws, hipStream_t st) {
   const int MD = Pl.MD, ncol = MD + MD * (MD + 1) / 2 + 1;
-  const int total = (int)Pl.nodes_total;
   double2* slots = static_cast<double2*>(ws);
-  // chunks of whole wavefront multiples, at most kVjpSlots of them
-  int len = 16 * kThreads;
-  while ((int64_t)(total + len - 1) / len > kVjpSlots) len *= 2;
-  const int nchunks = std::max(1, (total + len - 1) / len);
-  // the terms: bbar_i (col i), Abar_il for i <= l (col MD + upper-triangle index), sum g conj(psi) (last col)
-  StateVjpTerms T;
-  std::memset(&T, 0, sizeof(T));
-  std::vector<int> cstride(MD > 0 ? MD : 1, 1);
-  for (int d = MD - 2; d >= 0; --d) cstride[d] = cstride[d + 1] * Pl.CD[d + 1];
-  auto add = [&](int col, int kind, int i, int l) {
-    const int n = T.n++;
-    T.col[n] = col;
-    T.kind[n] = kind;
-    if (kind != 3) {
-      T.si[n] = cstride[i];
-      T.ci[n] = Pl.CD[i];
-      T.sl[n] = cstride[l];
-      T.cl[n] = Pl.CD[l];
-      T.inv_si[n] = 1.0 / cstride[i];
-      T.inv_ci[n] = 1.0 / Pl.CD[i];
-      T.inv_sl[n] = 1.0 / cstride[l];
-      T.inv_cl[n] = 1.0 / Pl.CD[l];
-    }
-  };
-  for (int i = 0; i < MD; ++i) add(i, 0, i, i);
-  for (int a = 0; a < MD; ++a)
-    for (int bb = a; bb < MD; ++bb) add(MD + a * MD - a * (a - 1) / 2 + (bb - a), a == bb ? 2 : 1, a, bb);
-  add(ncol - 1, 3, 0, 0);
+  const StateTiles G = state_tiles(Pl, kVjpTile);
+  // at most kVjpSlots workgroups (a multiple of 8), one slot each
+  const int grid = std::min(G.ntiles, kVjpSlots);
   {
     KTimer kt(Pl, KK_VJP_LEVEL, st);
-    hipLaunchKernelGGL((k_state_vjp_terms<R>), dim3((unsigned)(nchunks * T.n)), dim3(kThreads), 0, st,
-                       static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(g), total, len, T, slots);
+    const size_t shm = state_vjp_lds_bytes<R>();
+    hipLaunchKernelGGL((k_state_vjp<R>), dim3((unsigned)grid), dim3(kVjpThreads), shm, st, G,
+                       static_cast<const cx<R>*>(psi), static_cast<const cx<R>*>(g), slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -412,7 +662,7 @@ static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi
   m.M = Pl.M;
   m.MD = MD;
   m.ncol = ncol;
-  m.nslots = nchunks;
+  m.nslots = grid;
   for (int d = 0; d < MD; ++d) m.mode[d] = Pl.dmodes[d];
   KTimer kt(Pl, KK_VJP_FINAL, st);
   hipLaunchKernelGGL((k_state_vjp_final<R>), dim3(Pl.M * Pl.M + Pl.M + 1), dim3(kThreads), 0, st, m, slots,

@@ -273,3 +273,81 @@ def test_state_forward_ad():
         p, t = p.cpu().numpy(), t.cpu().numpy()
     assert_close(p, G, label="gpu_state:273")
     assert_close(t, ref, label="gpu_state:274")
+
+
+# Shapes whose derivative kernels split psi into several tiles of trailing
+# modes: one leading mode (6 tiles), two leading modes (25 tiles), two leading
+# modes with the tiles visited in per-XCD ranges (8 tiles)
+TILED = [[6, 5, 4, 6, 5, 4], [5] * 7, [2, 4, 4, 4, 4, 4, 4, 4]]
+
+
+@pytest.mark.parametrize("cut", TILED)
+@pytest.mark.parametrize("b_zero", [False, True])
+def test_state_derivatives_several_tiles(cut, b_zero):
+    rng = np.random.default_rng(sum(cut) * 11 + len(cut) + int(b_zero))
+    M = len(cut)
+    A, b, c = rand_state(rng, M, b_zero, scale=0.15)
+    psi_ref = O.state_vector(A, b, c, cut)
+    # reverse mode against the closed-form adjoint, entry by entry
+    g = rng.standard_normal(cut) + 1j * rng.standard_normal(cut)
+    got = gpu_state_vjp(A, b, c, cut, g)
+    assert_grad_close(got, O.adjoint_closed_form(A, b, c, psi_ref, g), label=f"state vjp {cut}")
+    assert all(np.array_equal(np.asarray(u), np.asarray(v))
+               for u, v in zip(got, gpu_state_vjp(A, b, c, cut, g)))   # deterministic
+    got64 = gpu_state_vjp(A, b, c, cut, g, torch.complex64)
+    assert grad_err(got64, got) <= 1e-5
+    # forward mode against the tangent recurrences
+    tA = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    tb = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    tc = complex(rng.standard_normal(), rng.standard_normal())
+    G, dB, dAr = O.tangent_recurrences(A, b, c, cut)
+    ref = (tc / c * G + np.tensordot(tb, dB, axes=(0, 0))
+           + np.tensordot(0.5 * (tA + tA.T), dAr, axes=([0, 1], [0, 1])))
+    jt = gpu_state_jvp(A, b, c, cut, tA, tb, tc)
+    assert_close(jt, ref, label=f"state jvp {cut}")
+    jt64 = gpu_state_jvp(A, b, c, cut, tA, tb, tc, torch.complex64)
+    assert O.rel_err(jt64.astype(np.complex128), jt) <= 1e-5
+
+
+def test_state8_derivatives_full_size():
+    # the measured workload (8 modes, cutoff 8: 4096 tiles, four leading
+    # modes, tiles visited in per-XCD ranges).  An amplitude and its tangent
+    # depend only on entries at or below it in every mode, so the oracle's box
+    # k + 1 gives them exactly at any pattern k: the tangent at sampled
+    # patterns against the tangent recurrences over those boxes, the reverse
+    # mode with a cotangent supported on the patterns against the closed-form
+    # adjoint over the same boxes (the adjoint is linear in the cotangent),
+    # and <g, J t> = <J^H g, t> with a dense cotangent
+    ci = W.state8()
+    M, cut = 8, ci.cutoffs
+    rng = np.random.default_rng(808)
+    pats = [(7, 6, 0, 0, 0, 0, 0, 1), (0, 0, 0, 0, 0, 0, 7, 7), (1,) * 8, (2, 0, 3, 0, 0, 4, 0, 1),
+            (0, 7, 0, 0, 5, 0, 0, 0), (3, 3, 0, 0, 0, 0, 2, 2), (0, 2, 0, 1, 0, 0, 2, 0), (0, 0, 0, 6, 6, 0, 0, 0)]
+    tA = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    tb = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    tc = complex(rng.standard_normal(), rng.standard_normal())
+    T = 0.5 * (tA + tA.T)
+    jt = gpu_state_jvp(ci.A, ci.b, ci.c, cut, tA, tb, tc)
+    got, ref = [], []
+    gsp = np.zeros(cut, complex)
+    rA, rb, rc = np.zeros((M, M), complex), np.zeros(M, complex), 0j
+    for k in pats:
+        box = [v + 1 for v in k]
+        G, dB, dAr = O.tangent_recurrences(ci.A, ci.b, ci.c, box)
+        ref.append(tc / ci.c * G[k] + np.tensordot(tb, dB[(slice(None),) + k], axes=(0, 0))
+                   + np.tensordot(T, dAr[(slice(None), slice(None)) + k], axes=([0, 1], [0, 1])))
+        got.append(jt[k])
+        gk = complex(rng.standard_normal(), rng.standard_normal())
+        gsp[k] = gk
+        gbox = np.zeros(box, complex)
+        gbox[k] = gk
+        a, bb, cc = O.adjoint_closed_form(ci.A, ci.b, ci.c, O.state_vector(ci.A, ci.b, ci.c, box), gbox)
+        rA, rb, rc = rA + a, rb + bb, rc + cc
+    assert_close(np.array(got), np.array(ref), label="state8 jvp patterns")
+    assert_grad_close(gpu_state_vjp(ci.A, ci.b, ci.c, cut, gsp), (rA, rb, rc), label="state8 vjp patterns")
+    g = W.random_cotangent(tuple(cut), seed=9)
+    dA, db, dc = gpu_state_vjp(ci.A, ci.b, ci.c, cut, g)
+    lhs = np.vdot(g, jt)
+    rhs = np.sum(tA * np.conj(dA)) + np.sum(tb * np.conj(db)) + tc * np.conj(dc)
+    print(f"[parity] state8 adjoint identity |lhs - rhs| / |lhs| = {abs(lhs - rhs) / abs(lhs):.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
