@@ -163,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_state_level(DevPlan P, const cx<R>
 // state).
 constexpr int kJvpTile = 4096, kJvpEPT = 4, kJvpThreads = kJvpTile / kJvpEPT;
 constexpr int kVjpTile = 512, kVjpEPT = 8, kVjpThreads = kVjpTile / kVjpEPT;
+constexpr int kVjpGrid = kVjpSlots;   // reverse-mode workgroups at most (one reduction slot each)
 constexpr int kVjpCols = kMaxD + kMaxD * (kMaxD + 1) / 2 + 1;   // bbar, Abar (i <= l), c
 
 struct StateTiles {
@@ -647,8 +648,9 @@ static hipError_t run_state_vjp_t(const Plan& Pl, const void* c, const void* psi
   const int MD = Pl.MD, ncol = MD + MD * (MD + 1) / 2 + 1;
   double2* slots = static_cast<double2*>(ws);
   const StateTiles G = state_tiles(Pl, kVjpTile);
-  // at most kVjpSlots workgroups (a multiple of 8), one slot each
-  const int grid = std::min(G.ntiles, kVjpSlots);
+  // at most kVjpGrid <= kVjpSlots workgroups (a multiple of 8), one slot each
+  static_assert(kVjpGrid <= kVjpSlots && kVjpGrid % 8 == 0, "reduction slots");
+  const int grid = std::min(G.ntiles, kVjpGrid);
   {
     KTimer kt(Pl, KK_VJP_LEVEL, st);
     const size_t shm = state_vjp_lds_bytes<R>();
