@@ -131,6 +131,23 @@ fd_status fd_plan_workspace(fd_plan p, int with_vjp, size_t* fwd_bytes, size_t* 
  * must be used under the same one.  Drops the plan's captured graphs. */
 fd_status fd_plan_set_checkpoint(fd_plan p, int every);
 
+/* fd_plan_set_write_counters -- debug mode for the exactly-once writes of the
+ * buffer strategy (Sec. 3.1.4; the stored counts of App. B.3).  counters: a
+ * device array of n unsigned ints, caller-owned and caller-zeroed, n >= the
+ * saved buffer's size in elements (saved_bytes / 16 for complex128, / 8 for
+ * complex64).  While set, every fock_diag_fwd call WITH a saved buffer adds 1
+ * to counters[k] for each amplitude its kernels write at element k of
+ * `saved` (Eq. recrel writes: the undetected block fill and every level; the
+ * seed G_0 = c is set by the prep and not counted).  A correct schedule leaves
+ * every count at 0 or 1, and their sum equals fd_plan_query(FD_Q_TARGETS).
+ * Calls without a saved buffer, the reverse sweep, the batched and
+ * static-scratch calls and the forward mode count nothing.  counters = NULL
+ * (n = 0) switches the mode off.  Costs a global atomic per write: for tests,
+ * not for timing.  Errors: FD_ERR_INVALID_ARG (NULL plan, n too small, n != 0
+ * with NULL), FD_ERR_UNSUPPORTED (a checkpointed plan: its saved buffer does
+ * not hold every amplitude).  Drops the plan's captured graphs. */
+fd_status fd_plan_set_write_counters(fd_plan p, unsigned int* counters, size_t n);
+
 /* fd_plan_query -- integer facts about the plan (host only, for tests and
  * reports).  `what`: see FD_Q_* below. */
 enum {

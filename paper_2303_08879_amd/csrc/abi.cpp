@@ -207,6 +207,22 @@ fd_status fd_plan_set_checkpoint(fd_plan p, int every) {
   return ok();
 }
 
+fd_status fd_plan_set_write_counters(fd_plan p, unsigned int* counters, size_t n) {
+  if (!p) return fail(FD_ERR_INVALID_ARG, "plan is NULL");
+  fd::Plan& P = p->P;
+  if (!counters) {
+    if (n != 0) return fail(FD_ERR_INVALID_ARG, "n must be 0 when the counters are NULL");
+  } else {
+    const size_t need = fd::saved_bytes(P) / fd::elem_bytes(P.dt);
+    if (P.ckpt > 0) return fail(FD_ERR_UNSUPPORTED, "write counters need the store-all saved buffer (no checkpoints)");
+    if (n < need) return fail(FD_ERR_INVALID_ARG, "fewer counters than elements of the saved buffer");
+  }
+  if (P.wcnt != counters || P.wcnt_n != n) drop_graphs(P);
+  P.wcnt = counters;
+  P.wcnt_n = n;
+  return ok();
+}
+
 fd_status fd_plan_query(fd_plan p, int what, int64_t* out) {
   if (!p || !out) return fail(FD_ERR_INVALID_ARG, "NULL argument");
   fd::Plan& P = p->P;

@@ -87,6 +87,11 @@ struct DevPlan {
   const int64_t* lvl;        // [(MD) x (smax+2)]: node offset of level S for group g (store-all)
   const int* node;           // Algorithm 2 plans: node records in level-major order (else null)
   int64_t ringN[kMaxD];      // ring slot stride in nodes per group (ring mode)
+  // debug write counters (fd_plan_set_write_counters): one count per element
+  // of the store-all buffer written by the forward kernels; null when off
+  unsigned int* wcnt;
+  const char* wbase;         // start of the store-all buffer
+  int64_t wcnt_n;            // counters
 };
 
 // Split of a node's undetected block into chunks of whole rows of the first
@@ -167,6 +172,8 @@ struct Plan {
   // reverse-sweep checkpoint interval in levels (0: the saved buffer keeps
   // every level of every family)
   int ckpt = 0;
+  unsigned int* wcnt = nullptr;      // debug write counters (caller-owned device array), null: off
+  size_t wcnt_n = 0;
   // blocks whose rows do not fit the LDS staging stream them from HBM, per
   // kernel: forward block units, block fill, reverse block units, reverse fill
   bool st_fwd = false, st_ufill = false, st_vjp = false, st_ufill_vjp = false;

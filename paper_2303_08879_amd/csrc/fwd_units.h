@@ -64,6 +64,16 @@ __device__ __forceinline__ void prep_body(const cx<R>* __restrict__ A, const cx<
   if (bad) atomicOr(status, bad);
 }
 
+// Debug write counter of an amplitude written at dst: counter k of the
+// store-all buffer's element k (fd_plan_set_write_counters, a check of the
+// exactly-once writes of Sec. 3.1.4); a no-op when the counters are off.
+template <typename R>
+__device__ __forceinline__ void count_write(const DevPlan& P, const cx<R>* dst) {
+  if (P.wcnt == nullptr) return;
+  const int64_t k = (int64_t)(reinterpret_cast<const char*>(dst) - P.wbase) / (int64_t)sizeof(cx<R>);
+  if (k >= 0 && k < P.wcnt_n) atomicAdd(P.wcnt + k, 1u);
+}
+
 // ---------------------------------------------------------------------------
 // Step 1 of Algorithm 2: the whole undetected block at zero detections.
 // Entry kappa != 0 is pulled from its parent kappa - 1_q, q = first non-zero
@@ -148,11 +158,17 @@ __device__ __forceinline__ void ufill_body(const DevPlan& P, const cx<R>* __rest
         if (pq > 0) cfma(acc, sA[qf * NQ + q], cscale(blk[pe - P.ustride[q]], sq[pq]));
       }
       blk[e] = cscale(acc, isq[kqf]);
+      if constexpr (ST) count_write(P, G + e);
     }
     unit_sync<ST>();
   }
+  // entry 0 is the seed c, already in G (written by the prep kernel)
   if constexpr (!ST)
-    for (int e = lane; e < B; e += 64) T::store(G + e, blk[e], dT);
+    for (int e = lane; e < B; e += 64)
+      if (e > 0) {
+        T::store(G + e, blk[e], dT);
+        count_write(P, G + e);
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -211,10 +227,18 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
         acc = cscale(acc, isq[m[j] + 1]);
         if (side == 0) {
           yk[j] = acc;
-          if (j == 0 || m[j] <= P.CD[j] - 2) st(at32(L.wr[fam_f1k(j)], (uint32_t)r), acc);
+          if (j == 0 || m[j] <= P.CD[j] - 2) {
+            cx<R>* dst = at32(L.wr[fam_f1k(j)], (uint32_t)r);
+            st(dst, acc);
+            count_write(P, dst);
+          }
         } else {
           const bool ok = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-          if (ok) st(at32(L.wr[fam_f1b(MD, j)], (uint32_t)r), acc);
+          if (ok) {
+            cx<R>* dst = at32(L.wr[fam_f1b(MD, j)], (uint32_t)r);
+            st(dst, acc);
+            count_write(P, dst);
+          }
         }
       }
     }
@@ -268,6 +292,7 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
       for (int l = 2 * K; l < NP; ++l) cfma(acc, ld(Ai + i * NP + l), x[l]);
       st(dst, cscale(acc, scale));
+      count_write(P, dst);
     }
   }
 }
@@ -371,7 +396,11 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
             for (int l = 0; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
             acc = cscale(acc, isq[m[j] + 1]);
-            if (ok && own) T::store(at32(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)], (uint32_t)(r * B + e)), acc, dT);
+            if (ok && own) {
+              cx<R>* dst = at32(L.wr[side ? fam_f1b(MD, j) : fam_f1k(j)], (uint32_t)(r * B + e));
+              T::store(dst, acc, dT);
+              count_write(P, dst);
+            }
             if (bridge) lpk[(size_t)j * pk1 + (e - (k0 - 1) * R0)] = acc;
           }
         }
@@ -438,6 +467,7 @@ __device__ __forceinline__ void fwd_block_unit(const DevPlan& P, const LP& L, co
 #pragma unroll
           for (int l = 2 * K; l < NPD; ++l) cfma(acc, sA[row + NQ + l], x[l]);
           T::store(dst, cscale(acc, scale), dT);
+          count_write(P, dst);
         }
         if constexpr (kFence) compiler_fence();
       }

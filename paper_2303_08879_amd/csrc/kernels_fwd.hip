@@ -473,6 +473,11 @@ static hipError_t run_forward_t(const Plan& Pl, bool odd, const void* A, const v
   cx<R>* ci = bi + Pl.npos;
   cx<R>* f0 = reinterpret_cast<cx<R>*>(fb + LF.f0);
   DevPlan P = make_devplan(Pl, odd);
+  if (store_all && Pl.wcnt) {   // debug write counters over the saved buffer
+    P.wcnt = Pl.wcnt;
+    P.wbase = saved;
+    P.wcnt_n = (int64_t)Pl.wcnt_n;
+  }
   (void)ci;
   hipError_t e;
   if (stop) {

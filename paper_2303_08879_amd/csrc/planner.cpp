@@ -717,7 +717,9 @@ void count_work(const Plan& P, bool b_zero, int64_t* targets, int64_t* terms) {
       if (m[K] > C[K] - 2) continue;
       int reads = 1 + (m[K] > 0);
       for (int j = K + 1; j < MD; ++j) reads += 2 * (m[j] > 0);
-      int t = 1 + (m[K] <= C[K] - 3);
+      // the F0 target d(m + 1_K) lies above a total photon cutoff's last level
+      const bool f0_target = !(P.level_cap >= 0 && msum == P.smax);
+      int t = (f0_target ? 1 : 0) + (m[K] <= C[K] - 3);
       for (int j = K + 1; j < MD; ++j) t += 2 * (m[j] <= C[j] - 2);
       T += (int64_t)t * P.B;
       W += (double)t * ((double)reads * P.B + (odd ? unb + bterm : 0.0));

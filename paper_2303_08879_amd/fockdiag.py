@@ -31,7 +31,7 @@ EXPORTS = [
     "fock_state_fwd", "fd_state_device_status", "fd_state_plan_timing", "fd_state_plan_kernel_times",
     "fd_plan_create_total", "fd_plan_level_offsets", "detection_probs_until", "fd_state_plan_vjp_workspace",
     "fock_state_vjp", "fock_state_jvp", "fd_plan_jvp_workspace", "fock_diag_jvp", "fock_diag_fwd_static",
-    "fd_plan_set_checkpoint",
+    "fd_plan_set_checkpoint", "fd_plan_set_write_counters",
 ]
 (FD_K_PREP, FD_K_UFILL, FD_K_FWD_LEVEL, FD_K_OUT_PERM, FD_K_PERM_IN, FD_K_VJP_LEVEL, FD_K_UFILL_VJP,
  FD_K_VJP_FINAL, FD_K_ZERO, FD_K_BATCH_PREP, FD_K_BATCH_SWEEP, FD_K_BATCH_OUT) = range(12)
@@ -85,6 +85,7 @@ def lib():
     L.fd_plan_timing.argtypes = [vp, u32]
     L.fd_plan_use_graphs.argtypes = [vp, i32]
     L.fd_plan_set_checkpoint.argtypes = [vp, i32]
+    L.fd_plan_set_write_counters.argtypes = [vp, vp, sz]
     L.fd_plan_kernel_times.argtypes = [vp, i32, i64p, ctypes.POINTER(ctypes.c_double)]
     L.fd_batch_set_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
     L.fd_batch_get_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
@@ -361,6 +362,16 @@ def fd_device_status(plan, stream=None):
 def fd_plan_set_checkpoint(plan, every):
     """Reverse-sweep checkpoint interval in levels (0: keep every level)."""
     _check(lib().fd_plan_set_checkpoint(plan.handle, int(every)))
+
+
+def fd_plan_set_write_counters(plan, counters=None):
+    """Debug write counters of fock_diag_fwd with a saved buffer: `counters`
+    is a zeroed device tensor of 32-bit ints with at least one entry per
+    element of the saved buffer, or None to switch the mode off."""
+    if counters is None:
+        _check(lib().fd_plan_set_write_counters(plan.handle, None, 0))
+    else:
+        _check(lib().fd_plan_set_write_counters(plan.handle, _ptr(counters), counters.numel()))
 
 
 def fd_plan_use_graphs(plan, enable=True):

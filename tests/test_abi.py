@@ -319,3 +319,20 @@ def test_checkpoint_setting_and_memory():
     assert plan.workspace(True) == (ws0, sv0)
     with pytest.raises(F.FockDiagError):
         F.fd_plan_set_checkpoint(type("P", (), {"handle": None})(), 2)
+
+
+def test_write_counter_arguments():
+    # host-side checks of the debug write-counter mode (no device access: the
+    # counter pointer is only stored by the call)
+    L = F.lib()
+    plan = F.Plan([4, 3, 3], 0b111, torch.complex128, "zero")
+    _, sv = plan.workspace(True)
+    need = sv // 16
+    fake = ctypes.c_void_p(0x1000)
+    assert L.fd_plan_set_write_counters(None, fake, need) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_set_write_counters(plan.handle, fake, need - 1) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_set_write_counters(plan.handle, None, 5) == F.FD_ERR_INVALID_ARG
+    assert L.fd_plan_set_write_counters(plan.handle, fake, need) == F.FD_OK
+    assert L.fd_plan_set_write_counters(plan.handle, None, 0) == F.FD_OK
+    F.fd_plan_set_checkpoint(plan, 2)   # a checkpointed saved buffer does not hold every amplitude
+    assert L.fd_plan_set_write_counters(plan.handle, fake, need) == F.FD_ERR_UNSUPPORTED
