@@ -197,7 +197,11 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
   unrank<MD>(spn, pnw, P.CD, S, r, m, s);
   neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
 
-  const cx<R> g0 = ld(at32(L.f0cur, (uint32_t)r));
+  // the point's own F0 entry: always valid, the address that neighbour loads
+  // of absent neighbours read instead (their value is then discarded), so
+  // every load is issued unconditionally and a pivot's loads share one wait
+  const cx<R>* own = at32(L.f0cur, (uint32_t)r);
+  const cx<R> g0 = ld(own);
   cx<R> yk[MD];
 #pragma unroll
   for (int K = 0; K < MD; ++K) yk[K] = czero<R>();
@@ -207,13 +211,11 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
     cx<R> x[NP];
 #pragma unroll
     for (int j = 0; j < MD; ++j) {
-      if (m[j] > 0) {
-        x[2 * j] = cscale(ld(at32(L.rd[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]);   // d(m)-1_ket(j) = F1b(j)(m-1_j)
-        x[2 * j + 1] = cscale(ld(at32(L.rd[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]);   // d(m)-1_bra(j) = F1k(j)(m-1_j)
-      } else {
-        x[2 * j] = czero<R>();
-        x[2 * j + 1] = czero<R>();
-      }
+      const bool h = m[j] > 0;
+      const cx<R> vb = ld(h ? at32(L.rd[fam_f1b(MD, j)], (uint32_t)rdn[j]) : own);   // d(m)-1_ket(j) = F1b(j)(m-1_j)
+      const cx<R> vk = ld(h ? at32(L.rd[fam_f1k(j)], (uint32_t)rdn[j]) : own);      // d(m)-1_bra(j) = F1k(j)(m-1_j)
+      x[2 * j] = cscale(h ? vb : czero<R>(), sq[m[j]]);
+      x[2 * j + 1] = cscale(h ? vk : czero<R>(), sq[m[j]]);
     }
 #pragma unroll
     for (int j = 0; j < MD; ++j) {
@@ -255,16 +257,18 @@ __device__ __forceinline__ void fwd_point_unit(const DevPlan& P, const LP& L, co
     // pivot p = d(m) + 1_ket(K): reads p - 1_l for l >= ket(K)
     cx<R> x[NP];
     x[2 * K] = cscale(g0, sq[m[K] + 1]);                                    // p - 1_ket(K) = d(m)
-    x[2 * K + 1] = (m[K] > 0) ? cscale(ld(at32(L.rd[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]) : czero<R>();
+    {
+      const bool h = m[K] > 0;
+      const cx<R> v = ld(h ? at32(L.rd[fam_f2(MD, K)], (uint32_t)rdn[K]) : own);
+      x[2 * K + 1] = cscale(h ? v : czero<R>(), sq[m[K]]);
+    }
 #pragma unroll
     for (int j = K + 1; j < MD; ++j) {
-      if (m[j] > 0) {
-        x[2 * j] = cscale(ld(at32(L.rd[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
-        x[2 * j + 1] = cscale(ld(at32(L.rd[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
-      } else {
-        x[2 * j] = czero<R>();
-        x[2 * j + 1] = czero<R>();
-      }
+      const bool h = m[j] > 0;
+      const cx<R> v0 = ld(h ? at32(L.rd[fam_1001(MD, K, j)], (uint32_t)rdn[j]) : own);
+      const cx<R> v1 = ld(h ? at32(L.rd[fam_1010(MD, K, j)], (uint32_t)rdn[j]) : own);
+      x[2 * j] = cscale(h ? v0 : czero<R>(), sq[m[j]]);
+      x[2 * j + 1] = cscale(h ? v1 : czero<R>(), sq[m[j]]);
     }
     // writes p + 1_i
 #pragma unroll

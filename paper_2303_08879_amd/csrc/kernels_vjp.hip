@@ -149,6 +149,11 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
     for (int d = 0; d < MD; ++d) m[d] = 0;
     int K0 = MD;
     cx<R> g0acc = czero<R>(), G0 = czero<R>();
+    // the point's own F0 entry: always valid for a live lane, the address that
+    // loads of absent neighbours or unset cotangent slots read instead (their
+    // value is then discarded), so a pivot's loads are issued unconditionally
+    // and share one wait
+    const cx<R>* own = at32(V.fcur[0], (uint32_t)(live ? r : 0));
     if (live) {
       unrank<MD>(spn, pnw, P.CD, S, r, m, s);
       neighbour_ranks<MD>(spn, pnw, s, rdn, rup);
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
       for (int d = MD - 1; d >= 0; --d)
         if (m[d] > 0) K0 = d;
       g0acc = ld(at32(V.d0cur, (uint32_t)r));
-      G0 = ld(at32(V.fcur[0], (uint32_t)r));
+      G0 = ld(own);
     }
     cx<R> ykg[MD];
 #pragma unroll
@@ -171,31 +176,39 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
       cx<R> xr[NCOL];
 #pragma unroll
       for (int l = 0; l < NCOL; ++l) xr[l] = czero<R>();
-      if (valid) {
-        xr[2 * K] = cscale(G0, sq[m[K] + 1]);
-        if (m[K] > 0) xr[2 * K + 1] = cscale(ld(at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K])), sq[m[K]]);
-#pragma unroll
-        for (int j = K + 1; j < MD; ++j) {
-          if (m[j] > 0) {
-            xr[2 * j] = cscale(ld(at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
-            xr[2 * j + 1] = cscale(ld(at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j])), sq[m[j]]);
-          }
-        }
-        if (ODD) xr[NP] = ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r));
-      }
       cx<R> h[NP];
 #pragma unroll
       for (int i = 0; i < NP; ++i) h[i] = czero<R>();
       if (valid) {
-        // (no level above the last one under a total photon cutoff)
-        if (V.gf0nxt) h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
-        if (m[K] <= P.CD[K] - 3) h[2 * K] = cscale(ld(at32(V.gcur[fam_f2(MD, K)], (uint32_t)r)), isq[m[K] + 2]);
+        xr[2 * K] = cscale(G0, sq[m[K] + 1]);
+        {
+          const bool hk = m[K] > 0;
+          const cx<R> v = ld(hk ? at32(V.fprev[fam_f2(MD, K)], (uint32_t)rdn[K]) : own);
+          xr[2 * K + 1] = cscale(hk ? v : czero<R>(), sq[m[K]]);
+        }
 #pragma unroll
         for (int j = K + 1; j < MD; ++j) {
-          if (m[j] <= P.CD[j] - 2) {
-            h[2 * j] = cscale(ld(at32(V.gcur[fam_1010(MD, K, j)], (uint32_t)r)), isq[m[j] + 1]);
-            h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_1001(MD, K, j)], (uint32_t)r)), isq[m[j] + 1]);
-          }
+          const bool hj = m[j] > 0;
+          const cx<R> v0 = ld(hj ? at32(V.fprev[fam_1001(MD, K, j)], (uint32_t)rdn[j]) : own);
+          const cx<R> v1 = ld(hj ? at32(V.fprev[fam_1010(MD, K, j)], (uint32_t)rdn[j]) : own);
+          xr[2 * j] = cscale(hj ? v0 : czero<R>(), sq[m[j]]);
+          xr[2 * j + 1] = cscale(hj ? v1 : czero<R>(), sq[m[j]]);
+        }
+        if (ODD) xr[NP] = ld(at32(V.fcur[fam_f1k(K)], (uint32_t)r));
+        // (no level above the last one under a total photon cutoff)
+        if (V.gf0nxt) h[2 * K + 1] = cscale(ld(at32(V.gf0nxt, (uint32_t)rup[K])), isq[m[K] + 1]);
+        {
+          const bool t2 = m[K] <= P.CD[K] - 3;
+          const cx<R> v = ld(t2 ? at32(V.gcur[fam_f2(MD, K)], (uint32_t)r) : own);
+          h[2 * K] = cscale(t2 ? v : czero<R>(), isq[m[K] + 2]);
+        }
+#pragma unroll
+        for (int j = K + 1; j < MD; ++j) {
+          const bool tj = m[j] <= P.CD[j] - 2;
+          const cx<R> v0 = ld(tj ? at32(V.gcur[fam_1010(MD, K, j)], (uint32_t)r) : own);
+          const cx<R> v1 = ld(tj ? at32(V.gcur[fam_1001(MD, K, j)], (uint32_t)r) : own);
+          h[2 * j] = cscale(tj ? v0 : czero<R>(), isq[m[j] + 1]);
+          h[2 * j + 1] = cscale(tj ? v1 : czero<R>(), isq[m[j] + 1]);
         }
         // adjoint of the reads
 #pragma unroll
@@ -247,10 +260,11 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         if (valid) {
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
-            if (m[j] > 0) {
-              xr[2 * j] = cscale(ld(at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j])), sq[m[j]]);
-              xr[2 * j + 1] = cscale(ld(at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j])), sq[m[j]]);
-            }
+            const bool hj = m[j] > 0;
+            const cx<R> v0 = ld(hj ? at32(V.fprev[fam_f1b(MD, j)], (uint32_t)rdn[j]) : own);
+            const cx<R> v1 = ld(hj ? at32(V.fprev[fam_f1k(j)], (uint32_t)rdn[j]) : own);
+            xr[2 * j] = cscale(hj ? v0 : czero<R>(), sq[m[j]]);
+            xr[2 * j + 1] = cscale(hj ? v1 : czero<R>(), sq[m[j]]);
           }
           xr[NP] = G0;
         }
@@ -260,13 +274,13 @@ __global__ __launch_bounds__(kThreads) void k_vjp_point(DevPlan P, VjpPtrs<R> V,
         if (valid) {
 #pragma unroll
           for (int j = 0; j < MD; ++j) {
-            if (j == 0 || m[j] <= P.CD[j] - 2) {
-              const bool kpiv = (j <= K0) && (m[j] <= P.CD[j] - 2);
-              const cx<R> gt = kpiv ? ykg[j] : ld(at32(V.gcur[fam_f1k(j)], (uint32_t)r));
-              h[2 * j] = cscale(gt, isq[m[j] + 1]);
-            }
+            const bool okk = j == 0 || m[j] <= P.CD[j] - 2;
+            const bool kpiv = (j <= K0) && (m[j] <= P.CD[j] - 2);
             const bool okb = (j == 0) ? (m[0] <= P.CD[0] - 3) : (m[j] <= P.CD[j] - 2);
-            if (okb) h[2 * j + 1] = cscale(ld(at32(V.gcur[fam_f1b(MD, j)], (uint32_t)r)), isq[m[j] + 1]);
+            const cx<R> vk = ld(okk && !kpiv ? at32(V.gcur[fam_f1k(j)], (uint32_t)r) : own);
+            const cx<R> vb = ld(okb ? at32(V.gcur[fam_f1b(MD, j)], (uint32_t)r) : own);
+            h[2 * j] = okk ? cscale(kpiv ? ykg[j] : vk, isq[m[j] + 1]) : czero<R>();
+            h[2 * j + 1] = cscale(okb ? vb : czero<R>(), isq[m[j] + 1]);
           }
 #pragma unroll
           for (int l = 0; l < NP; ++l) {
