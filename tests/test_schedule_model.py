@@ -83,3 +83,23 @@ def test_model_figure11_cutoffs():
     mdl.forward(A, b, c)
     assert sum(mdl.stored_counts().values()) == 255
     assert pivot_count_formula([4, 3, 3]) == 62
+
+
+@pytest.mark.parametrize("cut,mask,b_zero", [([4, 3, 3], 0b111, True), ([4, 3, 3], 0b111, False),
+                                             ([5, 3, 3], 0b110, True), ([3, 4, 3], 0b101, False),
+                                             ([3, 3, 3, 3], 0b1100, True), ([3, 2, 3], 0b100, True),
+                                             ([2, 3, 2, 3, 2], 0b11111, False)])
+def test_planner_target_count_matches_model(cut, mask, b_zero):
+    # the planner's count of Eq. recrel targets (what the device write
+    # counters must sum to) against the model's stored nodes: every stored
+    # node is a block of B amplitudes, all computed except the seed G_0 = c
+    import torch
+    from paper_2303_08879_amd import fockdiag as F
+    from paper_2303_08879_amd import workloads as W
+    rng = np.random.default_rng(sum(cut) + mask)
+    circ = W._circuit(rng, len(cut), 0.3, 0.8, lambda g, M: g.uniform(0.8, 0.95, size=M), cut, mask,
+                      alpha_var=0.0 if b_zero else 0.1)
+    model = Model(len(cut), cut, mask, b_zero)
+    model.forward(circ.A, circ.b, circ.c)
+    plan = F.Plan(cut, mask, torch.complex128, "zero" if b_zero else "general")
+    assert plan.query(F.FD_Q_TARGETS) == sum(model.stored_counts().values()) * model.B - 1
